@@ -1,0 +1,216 @@
+#!/usr/bin/env python
+"""Throughput of the candidate-coherence step on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input:
+C = 128 trust-region perturbations of a Haar-random frame of N = 4096 unit
+vectors in C^64, renormalised, screened from BF16 inputs on MFMA (FP32
+accumulation), the 8 best re-evaluated exactly in FP64 (certified tile
+pruning), select / accept / radius update, commit.  The frame is resident in
+HBM when the timed region starts.
+
+Output: one JSON line.  ``value`` is candidate evaluations per second over
+the timed steps; ``roofline`` is the BF16 Gram kernel's algorithmic
+TFLOP/s (8 d N(N-1)/2 flops per candidate) over its average launch time,
+measured with HIP events on its stream inside the timed region;
+``cpu_baseline`` is the numpy FP64 oracle on a bounded sample of the same
+workload on this host.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2516.6, "fp32": 157.3, "fp64": 78.6}   # MI355X dense MFMA
+GRAM_KERNEL = {"bf16": "gram_bf16", "fp32": "gram_f32", "fp64": "gram_f64"}
+KERNEL_SOURCE = {"gram_bf16": "gram_bf16.hip", "gram_f32": "gram_f32.hip", "gram_f64": "gram_f64.hip"}
+METRIC = "candidate coherence evals/s at N=4096,d=64 (% roofline); p50/p99 solve latency"
+
+
+def flops_per_eval(n, d):
+    """Algorithmic flops of one candidate's Gram + coherence: the strict upper
+    triangle has n(n-1)/2 complex inner products of length d, 8 real flops per
+    complex multiply-add."""
+    return 8 * d * n * (n - 1) // 2
+
+
+def kernel_sha(name):
+    path = os.path.join(ROOT, "paper_2207_06374_amd", "csrc", KERNEL_SOURCE[name])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(name)
+    if not rec or rec.get("source_sha") != kernel_sha(name):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
+    s = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode=mode, recheck_topk=topk, radius0=wl.radius0,
+                   max_steps=10 ** 12, seed=wl.seed, stream_id=wl.stream_id)
+    s.init_haar()
+    for _ in range(warmup):
+        s.step(with_report=False)
+    torch.cuda.synchronize()
+    lib.timing_reset()
+    lib.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(with_report=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.timing_enable(False)
+    kernels = {}
+    for name in ("perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck", "gram_recheck",
+                 "select", "commit"):
+        ms, cnt = lib.timing_read(name)
+        if cnt:
+            kernels[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
+    mu = float(s.state.mu.item())
+    elapsed = t1 - t0
+    evals = wl.candidates * steps / elapsed
+    g = kernels[GRAM_KERNEL[mode]]
+    flops_launch = wl.candidates * flops_per_eval(wl.n, wl.d)
+    achieved = flops_launch / (g["avg_us"] * 1e-6) / 1e12
+    del s
+    torch.cuda.empty_cache()
+    return {
+        "evals_per_s": evals,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "final_mu": mu,
+        "kernels": kernels,
+        "gram_tflops": achieved,
+        "gram_frac": achieved / PEAK_TFLOPS[mode],
+        "flops_per_launch": flops_launch,
+    }
+
+
+def cpu_baseline(wl, budget_s):
+    """The FP64 oracle (numpy) on a bounded sample of the workload: one step of
+    the BF16-screen form with c candidates, c chosen so the run takes about
+    ``budget_s`` seconds."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"),
+                      default=1)
+    except Exception:  # noqa: BLE001
+        threads = len(os.sched_getaffinity(0))
+    p = oracle.Params(n=wl.n, d=wl.d, candidates=1, mode="bf16", recheck_topk=1, radius0=wl.radius0,
+                      seed=wl.seed, stream_id=wl.stream_id, max_steps=10 ** 9)
+    st = oracle.haar_init(p)
+    t0 = time.perf_counter()
+    oracle.step(p, st)
+    one = time.perf_counter() - t0
+    c = int(max(2, min(wl.candidates, budget_s / max(one, 1e-3))))
+    p.candidates = c
+    p.recheck_topk = min(8, c)
+    t0 = time.perf_counter()
+    oracle.step(p, st)
+    el = time.perf_counter() - t0
+    return {
+        "value": c / el,
+        "unit": "evals/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"one step with {c} of the {wl.candidates} candidates (BF16-screen form: perturb, "
+                  f"renormalise, FP64 and BF16-input Gram + max, select), N={wl.n}, d={wl.d}, numpy FP64; "
+                  f"{el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--other-modes", default="fp64,fp32",
+                    help="also time these plain forms on the same workload (comma list, '' for none)")
+    ap.add_argument("--other-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the candidate search is measured on one MI355X; "
+              "multi-GPU sharding (candidates or Gram tiles across GPUs) is a design note, not a run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import inputs
+    import paper_2207_06374_amd as lib
+
+    wl = inputs.LARGE
+    main_res = run_mode(lib, torch, wl, "bf16", args.steps, args.warmup)
+    others = {}
+    for m in [x for x in args.other_modes.split(",") if x]:
+        r = run_mode(lib, torch, wl, m, args.other_steps, 2)
+        others[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
+        others[m]["gram_avg_us"] = r["kernels"][GRAM_KERNEL[m]]["avg_us"]
+
+    g = main_res["kernels"]["gram_bf16"]
+    traffic = load_traffic("gram_bf16")
+    line = {
+        "metric": METRIC,
+        "value": main_res["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "N=4096 unit vectors in C^64, 128 candidates/step, radius 0.05, Haar start seed 0; "
+                        "BF16-input MFMA screen, top-8 FP64 recheck (certified tile pruning), FP64 accept",
+            "n": wl.n, "d": wl.d, "candidates": wl.candidates, "recheck_topk": 8, "radius0": wl.radius0,
+            "recheck_dtype": "f64",
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "gram_bf16",
+            "achieved": main_res["gram_tflops"],
+            "peak": PEAK_TFLOPS["bf16"],
+            "unit": "TFLOP/s",
+            "frac": main_res["gram_frac"],
+            "traffic": traffic,
+            "flops_per_launch": main_res["flops_per_launch"],
+            "avg_launch_us": g["avg_us"],
+        },
+        "kernels_avg_us": {k: round(v["avg_us"], 3) for k, v in main_res["kernels"].items()},
+        "final_mu": main_res["final_mu"],
+        "other_modes": others,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        line["cpu_baseline"]["gpu_speedup"] = main_res["evals_per_s"] / line["cpu_baseline"]["value"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * trstmi.h -- C ABI of the MI355X (gfx950) candidate-coherence library.
+ *
+ * The library implements the data-parallel hot path of a stochastic
+ * trust-region search for low-coherence complex frames (Park, Saltijeral,
+ * Zhong, "Grassmannian packings: Trust-region stochastic tuning for matrix
+ * incoherence", arXiv:2207.06374):
+ *
+ *   - random start: N unit vectors in C^d (Alg. 2 step 1);
+ *   - per step: C random perturbations of the frame inside the trust radius,
+ *     column renormalisation (section IV remark: every column is divided by
+ *     its norm), the Hermitian Gram of each candidate, and the fused
+ *     reduction to the coherence mu = max_{j<k} |<phi_j, phi_k>| (section I;
+ *     only the upper triangle is needed, section IV);
+ *   - select the best candidate, accept it if it lowers mu, grow or shrink
+ *     the radius.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Frame layout: a d x N complex frame is 2*d*N doubles, column-major with
+ *   interleaved (re, im): entry (i, j) is at [2*(j*d + i)] (re) and
+ *   [2*(j*d + i) + 1] (im).  Column j is the vector phi_j.
+ * Memory: every pointer marked "device" is HIP device memory owned by the
+ *   caller.  The library never allocates or frees device memory; scratch
+ *   space comes from the caller's workspace buffer (see
+ *   trstmi_workspace_bytes), 256-byte aligned.
+ * Streams: every call is ordered on the given stream (0 = null stream) and
+ *   returns without waiting for the GPU, except trstmi_solve, which polls a
+ *   device flag once per chunk of steps.
+ * Errors: every function returns a trstmi_status.  Argument errors are found
+ *   on the host before anything is launched and leave device memory
+ *   untouched.  A HIP launch failure returns TRSTMI_E_HIP.  The text of the
+ *   last error of the calling thread is returned by trstmi_last_error().
+ * Randomness: draws come from Philox4x32-10 (Salmon et al., SC'11) keyed by
+ *   (seed, stream_id) with counter (block, candidate, step, tag); results are
+ *   a pure function of the inputs and parameters.
+ */
+#ifndef TRSTMI_H
+#define TRSTMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t trstmi_status;
+enum {
+  TRSTMI_OK = 0,
+  TRSTMI_E_INVALID_ARG = 1,   /* a size, pointer, mode or parameter is out of range */
+  TRSTMI_E_WORKSPACE = 2,     /* workspace null, misaligned or smaller than required */
+  TRSTMI_E_HIP = 3,           /* a HIP call failed (message in trstmi_last_error) */
+  TRSTMI_E_UNSUPPORTED = 4    /* valid request this build does not handle */
+};
+
+/* Arithmetic of the candidate evaluation. */
+enum {
+  TRSTMI_MODE_FP64 = 0,        /* candidates and Gram in FP64 */
+  TRSTMI_MODE_FP32 = 1,        /* candidates rounded to FP32, Gram in FP32 (MFMA) */
+  TRSTMI_MODE_BF16_SCREEN = 2  /* all candidates screened from BF16 inputs (MFMA, FP32
+                                  accumulate); the recheck_topk best screened ones are
+                                  re-evaluated exactly in FP64 and only FP64 values decide */
+};
+
+/* Bits of *state.flags. */
+#define TRSTMI_FLAG_ACCEPTED 1  /* the last step accepted a candidate */
+#define TRSTMI_FLAG_DONE 2      /* mu <= target_mu or step == max_steps; steps are no-ops */
+#define TRSTMI_FLAG_NEAR_TIE 4  /* the last decision compared values closer than near_tie */
+#define TRSTMI_FLAG_NO_VALID 8  /* the last step had no valid candidate */
+
+/* Limits of this build. */
+#define TRSTMI_MAX_D 512
+#define TRSTMI_MAX_CANDIDATES 32768
+#define TRSTMI_MAX_TOPK 64
+
+/*
+ * Parameters of a search.  Sizes: n = N >= 2 vectors, 1 <= d <= TRSTMI_MAX_D,
+ * n * ceil(d/2) < 2^32.  candidates = C in [1, TRSTMI_MAX_CANDIDATES].
+ * recheck_topk = k in [1, min(C, TRSTMI_MAX_TOPK)] (BF16 screen only).
+ * seed and stream_id must be < 2^32.  Radius rule: on accept
+ * radius <- min(grow * radius, radius_max), else radius <- max(shrink * radius,
+ * radius_min); 0 < radius_min <= radius0 <= radius_max, grow >= 1,
+ * 0 < shrink <= 1.  A step perturbs every column by radius in RMS norm:
+ * Y_c = Phi + (radius / sqrt(d)) Z_c with Z_c i.i.d. CN(0, 1).
+ * target_mu <= 0 disables the target; max_steps >= 0.  near_tie <= 0 selects
+ * the mode's default (2e-12 for FP64 decisions, 4e-6 for FP32).
+ */
+typedef struct trstmi_params {
+  int64_t n;
+  int64_t d;
+  int32_t candidates;
+  int32_t mode;
+  int32_t recheck_topk;
+  int32_t reserved0;
+  uint64_t seed;
+  uint64_t stream_id;
+  double radius0;
+  double grow;
+  double shrink;
+  double radius_min;
+  double radius_max;
+  int64_t max_steps;
+  double target_mu;
+  double near_tie;
+} trstmi_params;
+
+/* Search state: all device pointers, caller-owned.  frame holds 2*d*n doubles
+ * (layout above) with unit columns; mu, radius, step and flags are scalars. */
+typedef struct trstmi_state {
+  double* frame;
+  double* mu;
+  double* radius;
+  int64_t* step;
+  int32_t* flags;
+} trstmi_state;
+
+/* Optional per-step outputs (device pointers; each may be NULL).
+ * cand_mu[C]   : each candidate's coherence as the mode computes it (FP64,
+ *                FP32, or the BF16-screened value); +inf for an invalid
+ *                candidate (a column of zero or non-finite norm).
+ * rechecked[k] : BF16 screen: the candidates re-evaluated in FP64, in order
+ *                of screened value (ties to the lower index).
+ * recheck_mu[k]: their FP64 coherence.
+ * best[1]      : the selected candidate c* (-1 if none was valid).
+ * Nothing is written when the state is already DONE. */
+typedef struct trstmi_report {
+  double* cand_mu;
+  int32_t* rechecked;
+  double* recheck_mu;
+  int32_t* best;
+} trstmi_report;
+
+/* Fills *p with defaults for a frame of n vectors in C^d: 64 candidates,
+ * FP64, k = 8, seed 0, radius0 0.1, grow 2, shrink 0.5, radius range
+ * [1e-12, 1], 1000 steps, no target. */
+void trstmi_default_params(trstmi_params* p, int64_t n, int64_t d);
+
+/* Bytes of workspace trstmi_init_haar / trstmi_step / trstmi_solve need for
+ * these parameters (0 if the parameters are invalid). */
+size_t trstmi_workspace_bytes(const trstmi_params* p);
+
+/* Bytes of workspace trstmi_coherence needs for an n x d frame in this mode. */
+size_t trstmi_coherence_workspace_bytes(int64_t n, int64_t d, int32_t mode);
+
+/*
+ * Coherence of a frame (section I): the columns of `frame` (device, layout
+ * above, any nonzero scale) are normalised, then
+ * *mu_out (device double) = max_{j<k} |<phi_j, phi_k>|.
+ * mode FP64: exact up to rounding; FP32: Gram in FP32 from FP32-rounded unit
+ * columns; BF16_SCREEN: the screened value from BF16-rounded unit columns.
+ * A column whose norm is zero or not finite gives *mu_out = +inf.
+ * Requires n >= 2, 1 <= d <= TRSTMI_MAX_D.
+ */
+trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double* frame,
+                               double* mu_out, void* workspace, size_t workspace_bytes,
+                               hipStream_t stream);
+
+/*
+ * Random start (Alg. 2 step 1): state->frame <- N normalised CN(0, I_d)
+ * columns drawn with tag 1 (candidate 0, step 0); *mu <- its coherence
+ * (FP32 Gram in FP32 mode, exact FP64 otherwise); *radius <- radius0;
+ * *step <- 0; *flags <- DONE if the target is already met or max_steps == 0.
+ */
+trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state,
+                               void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * The normalised FP64 candidates of one step, for inspection: for
+ * i = 0..count-1, out + i*2*d*n <- normalise(frame + (radius / sqrt(d)) Z)
+ * with Z the draws of candidate (c0 + i) at step t (or explicit_z, see
+ * trstmi_step, if not NULL).  frame and radius are device pointers.  A column
+ * of zero or non-finite norm comes out as NaN.
+ */
+trstmi_status trstmi_candidates(const trstmi_params* p, const double* frame, const double* radius,
+                                int64_t t, int32_t c0, int32_t count, const double* explicit_z,
+                                double* out, hipStream_t stream);
+
+/*
+ * One step of the search on *state (no-op if DONE).  Draws the C
+ * perturbations of step *step (or reads explicit_z: device, C x 2*d*n doubles,
+ * candidate c at offset c*2*d*n, same layout as a frame), renormalises,
+ * evaluates every candidate's coherence in the mode's arithmetic, selects c*
+ * = argmin over (mu_c, c), accepts iff mu_{c*} < *mu, updates frame, mu,
+ * radius, step and flags.  report may be NULL.
+ */
+trstmi_status trstmi_step(const trstmi_params* p, const trstmi_state* state, void* workspace,
+                          size_t workspace_bytes, const double* explicit_z,
+                          const trstmi_report* report, hipStream_t stream);
+
+/*
+ * Steps until DONE, checking the device flag after every `chunk` steps
+ * (chunk >= 1).  Launches of each chunk are captured once into a HIP graph
+ * and replayed.  Blocks the calling thread; returns after the stream has
+ * finished the last chunk.
+ */
+trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, void* workspace,
+                           size_t workspace_bytes, int32_t chunk, hipStream_t stream);
+
+/*
+ * Kernel timing.  trstmi_timing_enable(1) makes every later kernel launch of
+ * the library record a HIP event before and after it on the launch's stream
+ * (launches under graph capture are not timed).  trstmi_timing_read waits for
+ * the recorded events and returns, for one kernel name, the summed elapsed
+ * milliseconds and the number of timed launches since the last reset.  Names:
+ * "perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck",
+ * "gram_recheck", "select", "commit".
+ */
+trstmi_status trstmi_timing_enable(int32_t on);
+trstmi_status trstmi_timing_reset(void);
+trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* trstmi_last_error(void);
+
+/* ABI version of this library (increases when a declaration changes). */
+int32_t trstmi_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRSTMI_H */

@@ -1,0 +1,226 @@
+"""Python binding of the MI355X candidate-coherence library (libtrstmi.so).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  The entry points have
+the names of the C ABI (``include/trstmi.h``) without the ``trstmi_`` prefix:
+``coherence``, ``init_haar``, ``candidates``, ``step``, ``solve``,
+``workspace_bytes``, ``default_params``.  ``Solver`` bundles a state and a
+workspace for one search.
+
+Frame layout on the device: 2*d*N doubles, column-major, interleaved
+(re, im).  ``frame_to_device`` / ``frame_from_device`` convert from / to a
+numpy (d, N) complex128 array.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+
+from . import _abi
+from ._abi import (  # noqa: F401
+    FLAG_ACCEPTED,
+    FLAG_DONE,
+    FLAG_NEAR_TIE,
+    FLAG_NO_VALID,
+    MODE_BF16_SCREEN,
+    MODE_FP32,
+    MODE_FP64,
+    TrstmiError,
+)
+
+MODES = {"fp64": MODE_FP64, "fp32": MODE_FP32, "bf16": MODE_BF16_SCREEN}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2207_06374_amd needs a ROCm GPU (torch.cuda is not available)")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_params(n, d, **kw):
+    """A ``Params`` struct with the library defaults, overridden by ``kw``
+    (``mode`` may be 'fp64' / 'fp32' / 'bf16' or the integer code)."""
+    p = _abi.Params()
+    _abi.lib().trstmi_default_params(ctypes.byref(p), int(n), int(d))
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = MODES[v]
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(params):
+    nbytes = _abi.lib().trstmi_workspace_bytes(ctypes.byref(params))
+    if nbytes == 0:
+        raise _abi.TrstmiError(_abi.E_INVALID_ARG, "workspace_bytes")
+    return nbytes
+
+
+def coherence_workspace_bytes(n, d, mode):
+    return _abi.lib().trstmi_coherence_workspace_bytes(int(n), int(d), int(mode))
+
+
+def frame_to_device(F, device="cuda"):
+    """numpy (d, N) complex -> flat float64 device tensor in the library layout."""
+    torch = _torch()
+    F = np.asarray(F, dtype=np.complex128)
+    flat = np.ascontiguousarray(F.T).view(np.float64).ravel()
+    return torch.from_numpy(flat.copy()).to(device)
+
+
+def frame_from_device(t, n, d):
+    """Flat float64 tensor in the library layout -> numpy (d, N) complex128."""
+    a = t.detach().to("cpu").numpy().reshape(int(n), int(d), 2)
+    return (a[..., 0] + 1j * a[..., 1]).T.copy()
+
+
+def coherence(frame, n, d, mode=MODE_FP64, mu_out=None, workspace=None, stream=None):
+    """Coherence of a device frame (flat float64 tensor).  Returns the device
+    tensor holding mu (shape (1,), float64)."""
+    torch = _torch()
+    mode = MODES.get(mode, mode)
+    if mu_out is None:
+        mu_out = torch.empty(1, dtype=torch.float64, device=frame.device)
+    need = coherence_workspace_bytes(n, d, mode)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=frame.device)
+    _abi.check(_abi.lib().trstmi_coherence(int(n), int(d), int(mode), _ptr(frame), _ptr(mu_out),
+                                           _ptr(workspace), workspace.numel(), _stream(stream)),
+               "trstmi_coherence")
+    return mu_out
+
+
+def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, stream=None):
+    """The normalised FP64 candidates c0..c0+count-1 of step t (flat tensor,
+    candidate i at offset i*2*d*n)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(count * 2 * params.d * params.n, dtype=torch.float64, device=frame.device)
+    _abi.check(_abi.lib().trstmi_candidates(ctypes.byref(params), _ptr(frame), _ptr(radius), int(t), int(c0),
+                                            int(count), _ptr(explicit_z), _ptr(out), _stream(stream)),
+               "trstmi_candidates")
+    return out
+
+
+@dataclasses.dataclass
+class DeviceState:
+    frame: object
+    mu: object
+    radius: object
+    step: object
+    flags: object
+
+    def abi(self):
+        return _abi.State(self.frame.data_ptr(), self.mu.data_ptr(), self.radius.data_ptr(),
+                          self.step.data_ptr(), self.flags.data_ptr())
+
+
+def new_state(n, d, device="cuda"):
+    torch = _torch()
+    return DeviceState(
+        frame=torch.zeros(2 * int(d) * int(n), dtype=torch.float64, device=device),
+        mu=torch.zeros(1, dtype=torch.float64, device=device),
+        radius=torch.zeros(1, dtype=torch.float64, device=device),
+        step=torch.zeros(1, dtype=torch.int64, device=device),
+        flags=torch.zeros(1, dtype=torch.int32, device=device),
+    )
+
+
+def init_haar(params, state, workspace, stream=None):
+    st = state.abi()
+    _abi.check(_abi.lib().trstmi_init_haar(ctypes.byref(params), ctypes.byref(st), _ptr(workspace),
+                                           workspace.numel(), _stream(stream)), "trstmi_init_haar")
+
+
+def step(params, state, workspace, explicit_z=None, report=None, stream=None):
+    st = state.abi()
+    rep = None
+    if report is not None:
+        rep = _abi.Report(*(0 if report.get(k) is None else report[k].data_ptr()
+                            for k in ("cand_mu", "rechecked", "recheck_mu", "best")))
+    _abi.check(_abi.lib().trstmi_step(ctypes.byref(params), ctypes.byref(st), _ptr(workspace), workspace.numel(),
+                                      _ptr(explicit_z), ctypes.byref(rep) if rep is not None else None,
+                                      _stream(stream)), "trstmi_step")
+
+
+def solve(params, state, workspace, chunk=64, stream=None):
+    st = state.abi()
+    _abi.check(_abi.lib().trstmi_solve(ctypes.byref(params), ctypes.byref(st), _ptr(workspace), workspace.numel(),
+                                       int(chunk), _stream(stream)), "trstmi_solve")
+
+
+class Solver:
+    """One search: parameters, device state and workspace."""
+
+    def __init__(self, n, d, device="cuda", **kw):
+        torch = _torch()
+        self.params = default_params(n, d, **kw)
+        self.n, self.d = int(n), int(d)
+        self.state = new_state(n, d, device)
+        self.workspace = torch.empty(workspace_bytes(self.params), dtype=torch.uint8, device=device)
+        C = self.params.candidates
+        k = max(1, self.params.recheck_topk)
+        self.report = {
+            "cand_mu": torch.empty(C, dtype=torch.float64, device=device),
+            "rechecked": torch.empty(k, dtype=torch.int32, device=device),
+            "recheck_mu": torch.empty(k, dtype=torch.float64, device=device),
+            "best": torch.empty(1, dtype=torch.int32, device=device),
+        }
+
+    def init_haar(self):
+        init_haar(self.params, self.state, self.workspace)
+        return self
+
+    def set_frame(self, F, mu=None, radius=None, t=0, flags=0):
+        """Load a host frame (d, N) and scalars into the device state."""
+        self.state.frame.copy_(frame_to_device(F, self.state.frame.device))
+        if mu is not None:
+            self.state.mu.fill_(float(mu))
+        if radius is not None:
+            self.state.radius.fill_(float(radius))
+        self.state.step.fill_(int(t))
+        self.state.flags.fill_(int(flags))
+
+    def step(self, explicit_z=None, with_report=True):
+        step(self.params, self.state, self.workspace, explicit_z, self.report if with_report else None)
+
+    def solve(self, chunk=64):
+        solve(self.params, self.state, self.workspace, chunk)
+
+    def host_state(self):
+        """(frame (d,N) complex128, mu, radius, step, flags) copied to the host."""
+        return (frame_from_device(self.state.frame, self.n, self.d), float(self.state.mu.item()),
+                float(self.state.radius.item()), int(self.state.step.item()), int(self.state.flags.item()))
+
+
+def timing_enable(on=True):
+    _abi.check(_abi.lib().trstmi_timing_enable(1 if on else 0), "trstmi_timing_enable")
+
+
+def timing_reset():
+    _abi.check(_abi.lib().trstmi_timing_reset(), "trstmi_timing_reset")
+
+
+def timing_read(kernel):
+    """(total milliseconds, timed launches) of one kernel since the last reset."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _abi.check(_abi.lib().trstmi_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+               "trstmi_timing_read")
+    return ms.value, cnt.value

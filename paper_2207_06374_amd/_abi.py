@@ -1,0 +1,127 @@
+"""ctypes declarations of the C ABI in ``include/trstmi.h`` (marshalling only).
+
+The shared library is built in-tree (``paper_2207_06374_amd/libtrstmi.so``).
+There is no fallback: if the library is missing, loading raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtrstmi.so")
+
+OK = 0
+E_INVALID_ARG = 1
+E_WORKSPACE = 2
+E_HIP = 3
+E_UNSUPPORTED = 4
+
+MODE_FP64 = 0
+MODE_FP32 = 1
+MODE_BF16_SCREEN = 2
+
+FLAG_ACCEPTED = 1
+FLAG_DONE = 2
+FLAG_NEAR_TIE = 4
+FLAG_NO_VALID = 8
+
+MAX_D = 512
+MAX_CANDIDATES = 32768
+MAX_TOPK = 64
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int64),
+        ("candidates", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("recheck_topk", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint64),
+        ("radius0", ctypes.c_double),
+        ("grow", ctypes.c_double),
+        ("shrink", ctypes.c_double),
+        ("radius_min", ctypes.c_double),
+        ("radius_max", ctypes.c_double),
+        ("max_steps", ctypes.c_int64),
+        ("target_mu", ctypes.c_double),
+        ("near_tie", ctypes.c_double),
+    ]
+
+
+class State(ctypes.Structure):
+    _fields_ = [
+        ("frame", ctypes.c_void_p),
+        ("mu", ctypes.c_void_p),
+        ("radius", ctypes.c_void_p),
+        ("step", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("cand_mu", ctypes.c_void_p),
+        ("rechecked", ctypes.c_void_p),
+        ("recheck_mu", ctypes.c_void_p),
+        ("best", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "trstmi_default_params": (None, [_P(Params), _i64, _i64]),
+    "trstmi_workspace_bytes": (_sz, [_P(Params)]),
+    "trstmi_coherence_workspace_bytes": (_sz, [_i64, _i64, _i32]),
+    "trstmi_coherence": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "trstmi_init_haar": (_i32, [_P(Params), _P(State), _vp, _sz, _vp]),
+    "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
+    "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),
+    "trstmi_solve": (_i32, [_P(Params), _P(State), _vp, _sz, _i32, _vp]),
+    "trstmi_timing_enable": (_i32, [_i32]),
+    "trstmi_timing_reset": (_i32, []),
+    "trstmi_timing_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_i64)]),
+    "trstmi_last_error": (ctypes.c_char_p, []),
+    "trstmi_abi_version": (_i32, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loaded once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2207_06374_amd.build` "
+                "(there is no non-HIP implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class TrstmiError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().trstmi_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+def check(status, where):
+    if status != OK:
+        raise TrstmiError(status, where)
+    return status

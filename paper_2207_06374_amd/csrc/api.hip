@@ -1,0 +1,634 @@
+// C ABI of the candidate-coherence library: argument validation, workspace
+// layout, and the launch sequences of the random start, one step, and a solve.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/trstmi.h"
+#include "launch.h"
+
+using namespace trstmi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+trstmi_status fail(trstmi_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+trstmi_status hip_fail(hipError_t e, const char* where) {
+  return fail(TRSTMI_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define TRY_HIP(expr, where)                  \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel timing.  When enabled, every kernel launch of the library is
+// bracketed by two HIP events recorded on the launch's own stream; reading
+// the totals waits for those events and sums the elapsed times per kernel
+// name.  Launches made while a stream is being captured into a graph are not
+// timed.
+// ---------------------------------------------------------------------------
+struct TimingRecord {
+  const char* name;
+  hipEvent_t start, stop;
+};
+
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TimingRecord> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, int64_t>> totals;  // name -> (ms, launches)
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Records a start event now and a stop event when finish() is called.
+class TimedLaunch {
+ public:
+  TimedLaunch(const char* name, hipStream_t s) : name_(name), s_(s) {
+    Timing& T = timing();
+    std::lock_guard<std::mutex> g(T.mu);
+    if (!T.on || capturing(s)) return;
+    start_ = T.get();
+    stop_ = T.get();
+    if (start_ && stop_ && hipEventRecord(start_, s) == hipSuccess) active_ = true;
+  }
+  hipError_t finish(hipError_t launch_status) {
+    if (!active_) return launch_status;
+    Timing& T = timing();
+    std::lock_guard<std::mutex> g(T.mu);
+    if (hipEventRecord(stop_, s_) == hipSuccess) T.pending.push_back({name_, start_, stop_});
+    return launch_status;
+  }
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t start_ = nullptr, stop_ = nullptr;
+  bool active_ = false;
+};
+
+#define TIMED(name, stream, expr) \
+  [&]() { TimedLaunch tl_(name, stream); return tl_.finish(expr); }()
+
+trstmi_status drain_timing() {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> g(T.mu);
+  for (auto& r : T.pending) {
+    hipError_t e = hipEventSynchronize(r.stop);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) return hip_fail(e, "timing");
+    auto& acc = T.totals[r.name];
+    acc.first += ms;
+    acc.second += 1;
+    T.pool.push_back(r.start);
+    T.pool.push_back(r.stop);
+  }
+  T.pending.clear();
+  return TRSTMI_OK;
+}
+
+constexpr int64_t kMaxN = 1 << 18;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int32_t ld_of(int64_t d) { return (int32_t)((2 * d + 7) / 8 * 8); }
+
+int nt_of(int64_t n, int tile) { return (int)((n + tile - 1) / tile); }
+
+int64_t ntiles_of(int64_t n, int tile) {
+  const int64_t nt = nt_of(n, tile);
+  return nt * (nt + 1) / 2;
+}
+
+size_t elem_of_mode(int32_t mode) { return mode == TRSTMI_MODE_FP64 ? 8 : (mode == TRSTMI_MODE_FP32 ? 4 : 2); }
+
+// Offsets of the step workspace.
+struct Layout {
+  int64_t n, d;
+  int32_t C, k, ld;
+  size_t cand, cand_max, dec, tile_max, rechecked, thr, recheck, recheck_max, total;
+};
+
+Layout layout_of(const trstmi_params* p) {
+  Layout L{};
+  L.n = p->n;
+  L.d = p->d;
+  L.C = p->candidates;
+  L.k = p->mode == TRSTMI_MODE_BF16_SCREEN ? p->recheck_topk : 0;
+  L.ld = ld_of(p->d);
+  size_t off = 0;
+  L.cand = off;
+  off = align256(off + (size_t)L.C * L.n * L.ld * elem_of_mode(p->mode));
+  L.cand_max = off;
+  off = align256(off + (size_t)L.C * 8);
+  L.dec = off;
+  off = align256(off + sizeof(Decision));
+  if (p->mode == TRSTMI_MODE_BF16_SCREEN) {
+    L.tile_max = off;
+    off = align256(off + (size_t)L.C * ntiles_of(L.n, kTileBF16) * 4);
+    L.rechecked = off;
+    off = align256(off + (size_t)L.k * 4);
+    L.thr = off;
+    off = align256(off + (size_t)L.k * 8);
+    L.recheck = off;
+    off = align256(off + (size_t)L.k * L.n * L.ld * 8);
+    L.recheck_max = off;
+    off = align256(off + (size_t)L.k * 8);
+  }
+  L.total = off;
+  return L;
+}
+
+trstmi_status check_size(int64_t n, int64_t d) {
+  if (n < 2 || n > kMaxN) return fail(TRSTMI_E_INVALID_ARG, "n must be in [2, 262144]");
+  if (d < 1 || d > TRSTMI_MAX_D) return fail(TRSTMI_E_INVALID_ARG, "d must be in [1, 512]");
+  if (n * ((d + 1) / 2) >= (int64_t)1 << 32) return fail(TRSTMI_E_INVALID_ARG, "n * ceil(d/2) must be < 2^32");
+  return TRSTMI_OK;
+}
+
+trstmi_status check_mode(int32_t mode) {
+  if (mode != TRSTMI_MODE_FP64 && mode != TRSTMI_MODE_FP32 && mode != TRSTMI_MODE_BF16_SCREEN)
+    return fail(TRSTMI_E_INVALID_ARG, "unknown mode");
+  return TRSTMI_OK;
+}
+
+trstmi_status check_params(const trstmi_params* p) {
+  if (!p) return fail(TRSTMI_E_INVALID_ARG, "params is NULL");
+  trstmi_status st = check_size(p->n, p->d);
+  if (st) return st;
+  if ((st = check_mode(p->mode))) return st;
+  if (p->candidates < 1 || p->candidates > TRSTMI_MAX_CANDIDATES)
+    return fail(TRSTMI_E_INVALID_ARG, "candidates must be in [1, 32768]");
+  if (p->mode == TRSTMI_MODE_BF16_SCREEN &&
+      (p->recheck_topk < 1 || p->recheck_topk > p->candidates || p->recheck_topk > TRSTMI_MAX_TOPK))
+    return fail(TRSTMI_E_INVALID_ARG, "recheck_topk must be in [1, min(candidates, 64)]");
+  if (p->seed >> 32 || p->stream_id >> 32) return fail(TRSTMI_E_INVALID_ARG, "seed and stream_id must be < 2^32");
+  const bool ok_r = std::isfinite(p->radius0) && std::isfinite(p->radius_min) && std::isfinite(p->radius_max) &&
+                    p->radius_min > 0 && p->radius_min <= p->radius0 && p->radius0 <= p->radius_max;
+  if (!ok_r) return fail(TRSTMI_E_INVALID_ARG, "need finite 0 < radius_min <= radius0 <= radius_max");
+  if (!(std::isfinite(p->grow) && p->grow >= 1.0) || !(std::isfinite(p->shrink) && p->shrink > 0 && p->shrink <= 1.0))
+    return fail(TRSTMI_E_INVALID_ARG, "need grow >= 1 and 0 < shrink <= 1");
+  if (p->max_steps < 0) return fail(TRSTMI_E_INVALID_ARG, "max_steps must be >= 0");
+  if (std::isnan(p->target_mu) || std::isnan(p->near_tie)) return fail(TRSTMI_E_INVALID_ARG, "NaN parameter");
+  return TRSTMI_OK;
+}
+
+trstmi_status check_state(const trstmi_state* s) {
+  if (!s || !s->frame || !s->mu || !s->radius || !s->step || !s->flags)
+    return fail(TRSTMI_E_INVALID_ARG, "state or one of its pointers is NULL");
+  if (((uintptr_t)s->frame & 15) || ((uintptr_t)s->mu & 7) || ((uintptr_t)s->radius & 7) ||
+      ((uintptr_t)s->step & 7) || ((uintptr_t)s->flags & 3))
+    return fail(TRSTMI_E_INVALID_ARG, "state pointer misaligned (frame needs 16 bytes)");
+  return TRSTMI_OK;
+}
+
+trstmi_status check_ws(void* ws, size_t have, size_t need) {
+  if (need == 0) return TRSTMI_OK;
+  if (!ws) return fail(TRSTMI_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws & 255) return fail(TRSTMI_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (have < need) return fail(TRSTMI_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  return TRSTMI_OK;
+}
+
+double tau_of(const trstmi_params* p) {
+  if (p->near_tie > 0) return p->near_tie;
+  return p->mode == TRSTMI_MODE_FP32 ? 4e-6 : 2e-12;
+}
+
+// Certified bound on |screened - exact| coherence for unit columns in C^d:
+// bfloat16 inputs move each real dot product of two unit 2d-vectors by at
+// most 2u + u^2 (u = 2^-8); FP32 accumulation of 2d exact products adds
+// gamma_{2d} (1 + u)^2 (gamma_n = n v / (1 - n v), v = 2^-24); Re and Im give
+// sqrt(2); the last terms cover the FP32 epilogue and FP64 rounding.
+double screen_eps(int64_t d) {
+  const double u = std::ldexp(1.0, -8), v = std::ldexp(1.0, -24);
+  const double nv = 2.0 * d * v;
+  const double gamma = nv / (1.0 - nv);
+  return std::sqrt(2.0) * (2 * u + u * u + gamma * (1 + u) * (1 + u)) + 8 * v + 1e-12;
+}
+
+PerturbArgs perturb_base(const trstmi_params* p) {
+  PerturbArgs a{};
+  a.n = p->n;
+  a.d = (int32_t)p->d;
+  a.seed = (uint32_t)p->seed;
+  a.stream_id = (uint32_t)p->stream_id;
+  a.tag = 0;
+  a.have_z = 1;
+  return a;
+}
+
+GramArgs gram_base(int64_t n, int64_t d, const void* cand, int64_t stride, int32_t ld, int tile, uint64_t* mx,
+                   const int32_t* flags) {
+  GramArgs g{};
+  g.cand = cand;
+  g.slot_stride = stride;
+  g.ldk = ld;
+  g.n = (int32_t)n;
+  g.d = (int32_t)d;
+  g.nt = nt_of(n, tile);
+  g.cand_max = mx;
+  g.flags = flags;
+  return g;
+}
+
+trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char* ws, const double* z,
+                           const trstmi_report* rep, hipStream_t s) {
+  const Layout L = layout_of(p);
+  const int C = p->candidates;
+  uint64_t* cand_max = (uint64_t*)(ws + L.cand_max);
+  Decision* dec = (Decision*)(ws + L.dec);
+  const int64_t slot_stride = L.n * L.ld;
+
+  PerturbArgs pa = perturb_base(p);
+  pa.base = st->frame;
+  pa.radius = st->radius;
+  pa.tstep = st->step;
+  pa.gate = st->flags;
+  pa.gate_mask = TRSTMI_FLAG_DONE;
+  pa.gate_want = 0;
+  pa.z_explicit = z;
+  pa.out = ws + L.cand;
+  pa.out_kind = p->mode == TRSTMI_MODE_FP64 ? kOutF64 : (p->mode == TRSTMI_MODE_FP32 ? kOutF32 : kOutBF16);
+  pa.out_ld = L.ld;
+  pa.out_slot_stride = slot_stride;
+  pa.zero_max = cand_max;
+  TRY_HIP(TIMED("perturb", s, launch_perturb(pa, C, s)), "perturb");
+
+  SelectArgs sa{};
+  sa.tau = tau_of(p);
+  sa.mu = st->mu;
+  sa.radius = st->radius;
+  sa.step = st->step;
+  sa.flags = st->flags;
+  sa.grow = p->grow;
+  sa.shrink = p->shrink;
+  sa.radius_min = p->radius_min;
+  sa.radius_max = p->radius_max;
+  sa.max_steps = p->max_steps;
+  sa.target_mu = p->target_mu;
+  sa.dec = dec;
+  sa.rep_best = rep ? rep->best : nullptr;
+
+  if (p->mode == TRSTMI_MODE_FP64 || p->mode == TRSTMI_MODE_FP32) {
+    const bool f32 = p->mode == TRSTMI_MODE_FP32;
+    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ld, f32 ? kTileF32 : kTileF64, cand_max, st->flags);
+    TRY_HIP(TIMED(f32 ? "gram_f32" : "gram_f64", s, f32 ? launch_gram_f32(g, C, s) : launch_gram_f64(g, C, s)), "gram");
+    sa.cand_max = cand_max;
+    sa.count = C;
+    sa.is_f32 = f32 ? 1 : 0;
+    sa.rep_cand_mu = rep ? rep->cand_mu : nullptr;
+    TRY_HIP(TIMED("select", s, launch_select(sa, s)), "select");
+  } else {
+    uint32_t* tile_max = (uint32_t*)(ws + L.tile_max);
+    int32_t* rechecked = (int32_t*)(ws + L.rechecked);
+    double* thr = (double*)(ws + L.thr);
+    uint64_t* recheck_max = (uint64_t*)(ws + L.recheck_max);
+    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ld, kTileBF16, cand_max, st->flags);
+    g.tile_max = tile_max;
+    TRY_HIP(TIMED("gram_bf16", s, launch_gram_bf16(g, C, s)), "gram_bf16");
+
+    TopkArgs ta{};
+    ta.cand_max = cand_max;
+    ta.C = C;
+    ta.k = L.k;
+    ta.eps = screen_eps(L.d);
+    ta.screen_tie = 2e-5;
+    ta.flags = st->flags;
+    ta.rechecked = rechecked;
+    ta.thr = thr;
+    ta.dec = dec;
+    ta.rep_cand_mu = rep ? rep->cand_mu : nullptr;
+    ta.rep_rechecked = rep ? rep->rechecked : nullptr;
+    TRY_HIP(TIMED("topk", s, launch_topk(ta, s)), "topk");
+
+    PerturbArgs pr = pa;
+    pr.cand_idx = rechecked;
+    pr.out = ws + L.recheck;
+    pr.out_kind = kOutF64;
+    pr.zero_max = recheck_max;
+    TRY_HIP(TIMED("perturb_recheck", s, launch_perturb(pr, L.k, s)), "perturb_recheck");
+
+    GramArgs g64 = gram_base(L.n, L.d, ws + L.recheck, slot_stride, L.ld, kTileF64, recheck_max, st->flags);
+    g64.screen_tile_max = tile_max;
+    g64.slot_cand = rechecked;
+    g64.thr = thr;
+    g64.screen_ratio = kTileBF16 / kTileF64;
+    g64.screen_nt = nt_of(L.n, kTileBF16);
+    TRY_HIP(TIMED("gram_recheck", s, launch_gram_f64(g64, L.k, s)), "gram_recheck");
+
+    sa.cand_max = recheck_max;
+    sa.count = L.k;
+    sa.is_f32 = 0;
+    sa.slot_cand = rechecked;
+    sa.use_screen_near = 1;
+    sa.rep_cand_mu = rep ? rep->recheck_mu : nullptr;
+    TRY_HIP(TIMED("select", s, launch_select(sa, s)), "select");
+  }
+
+  // commit: regenerate the accepted candidate in FP64 into the frame, in place
+  PerturbArgs pc = perturb_base(p);
+  pc.base = st->frame;
+  pc.radius = &dec->radius_old;
+  pc.tstep = &dec->t_old;
+  pc.cand_idx = &dec->best;
+  pc.gate = &dec->commit;
+  pc.gate_mask = 1;
+  pc.gate_want = 1;
+  pc.z_explicit = z;
+  pc.out = st->frame;
+  pc.out_kind = kOutF64;
+  pc.out_ld = (int32_t)(2 * L.d);
+  pc.out_slot_stride = 2 * L.d * L.n;
+  TRY_HIP(TIMED("commit", s, launch_perturb(pc, 1, s)), "commit");
+  return TRSTMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void trstmi_default_params(trstmi_params* p, int64_t n, int64_t d) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n = n;
+  p->d = d;
+  p->candidates = 64;
+  p->mode = TRSTMI_MODE_FP64;
+  p->recheck_topk = 8;
+  p->seed = 0;
+  p->stream_id = 0;
+  p->radius0 = 0.1;
+  p->grow = 2.0;
+  p->shrink = 0.5;
+  p->radius_min = 1e-12;
+  p->radius_max = 1.0;
+  p->max_steps = 1000;
+  p->target_mu = 0.0;
+  p->near_tie = 0.0;
+}
+
+size_t trstmi_workspace_bytes(const trstmi_params* p) {
+  if (check_params(p)) return 0;
+  return layout_of(p).total;
+}
+
+size_t trstmi_coherence_workspace_bytes(int64_t n, int64_t d, int32_t mode) {
+  if (check_size(n, d) || check_mode(mode)) return 0;
+  return align256((size_t)n * ld_of(d) * elem_of_mode(mode)) + 256;
+}
+
+trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double* frame, double* mu_out,
+                               void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if ((st = check_mode(mode))) return st;
+  if (!frame || !mu_out) return fail(TRSTMI_E_INVALID_ARG, "frame and mu_out must be device pointers");
+  if (((uintptr_t)frame & 15) || ((uintptr_t)mu_out & 7)) return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_coherence_workspace_bytes(n, d, mode);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  char* ws = (char*)workspace;
+  const int32_t ld = ld_of(d);
+  uint64_t* mx = (uint64_t*)(ws + align256((size_t)n * ld * elem_of_mode(mode)));
+
+  PerturbArgs pa{};
+  pa.base = frame;
+  pa.have_z = 0;
+  pa.n = n;
+  pa.d = (int32_t)d;
+  pa.out = ws;
+  pa.out_kind = mode == TRSTMI_MODE_FP64 ? kOutF64 : (mode == TRSTMI_MODE_FP32 ? kOutF32 : kOutBF16);
+  pa.out_ld = ld;
+  pa.out_slot_stride = n * ld;
+  pa.zero_max = mx;
+  TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
+  const int tile = mode == TRSTMI_MODE_FP64 ? kTileF64 : (mode == TRSTMI_MODE_FP32 ? kTileF32 : kTileBF16);
+  GramArgs g = gram_base(n, d, ws, n * ld, ld, tile, mx, nullptr);
+  if (mode == TRSTMI_MODE_FP64) TRY_HIP(launch_gram_f64(g, 1, stream), "gram_f64");
+  else if (mode == TRSTMI_MODE_FP32) TRY_HIP(launch_gram_f32(g, 1, stream), "gram_f32");
+  else TRY_HIP(launch_gram_bf16(g, 1, stream), "gram_bf16");
+  InitFinishArgs f{};
+  f.max_bits = mx;
+  f.is_f32 = mode == TRSTMI_MODE_FP64 ? 0 : 1;
+  f.mu_out = mu_out;
+  TRY_HIP(launch_init_finish(f, stream), "finish");
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_state(state))) return st;
+  const Layout L = layout_of(p);
+  if ((st = check_ws(workspace, workspace_bytes, L.total))) return st;
+  char* ws = (char*)workspace;
+  uint64_t* mx = (uint64_t*)(ws + L.cand_max);
+
+  PerturbArgs pa = perturb_base(p);
+  pa.base = nullptr;
+  pa.tag = 1;
+  pa.t_const = 0;
+  pa.c0 = 0;
+  pa.out = state->frame;
+  pa.out_kind = kOutF64;
+  pa.out_ld = (int32_t)(2 * p->d);
+  pa.out_slot_stride = 2 * p->d * p->n;
+  pa.zero_max = mx;
+  TRY_HIP(launch_perturb(pa, 1, stream), "haar");
+  const bool f32 = p->mode == TRSTMI_MODE_FP32;
+  if (f32) {
+    float* buf = (float*)(ws + L.cand);
+    TRY_HIP(launch_convert_f32(state->frame, p->n, (int32_t)p->d, buf, L.ld, mx, stream), "convert");
+    GramArgs g = gram_base(p->n, p->d, buf, p->n * L.ld, L.ld, kTileF32, mx, nullptr);
+    TRY_HIP(launch_gram_f32(g, 1, stream), "gram_f32");
+  } else {
+    GramArgs g = gram_base(p->n, p->d, state->frame, 2 * p->d * p->n, (int32_t)(2 * p->d), kTileF64, mx, nullptr);
+    TRY_HIP(launch_gram_f64(g, 1, stream), "gram_f64");
+  }
+  InitFinishArgs f{};
+  f.max_bits = mx;
+  f.is_f32 = f32 ? 1 : 0;
+  f.mu = state->mu;
+  f.radius = state->radius;
+  f.step = state->step;
+  f.flags = state->flags;
+  f.radius0 = p->radius0;
+  f.max_steps = p->max_steps;
+  f.target_mu = p->target_mu;
+  TRY_HIP(launch_init_finish(f, stream), "init_finish");
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_candidates(const trstmi_params* p, const double* frame, const double* radius, int64_t t,
+                                int32_t c0, int32_t count, const double* explicit_z, double* out,
+                                hipStream_t stream) {
+  trstmi_status st = check_params(p);
+  if (st) return st;
+  if (!frame || !radius || !out) return fail(TRSTMI_E_INVALID_ARG, "frame, radius and out must be device pointers");
+  if (((uintptr_t)frame & 15) || ((uintptr_t)out & 15)) return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  if (count < 1 || c0 < 0 || t < 0 || t >= ((int64_t)1 << 32) || (int64_t)c0 + count > ((int64_t)1 << 31))
+    return fail(TRSTMI_E_INVALID_ARG, "bad candidate range or step");
+  if (count > 65535) return fail(TRSTMI_E_INVALID_ARG, "count must be <= 65535");
+  if (explicit_z && (int64_t)c0 + count > p->candidates)
+    return fail(TRSTMI_E_INVALID_ARG, "explicit_z holds params.candidates draws: need c0 + count <= candidates");
+  PerturbArgs pa = perturb_base(p);
+  pa.base = frame;
+  pa.radius = radius;
+  pa.t_const = t;
+  pa.c0 = c0;
+  pa.z_explicit = explicit_z;
+  pa.out = out;
+  pa.out_kind = kOutF64;
+  pa.out_ld = (int32_t)(2 * p->d);
+  pa.out_slot_stride = 2 * p->d * p->n;
+  TRY_HIP(launch_perturb(pa, count, stream), "candidates");
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_step(const trstmi_params* p, const trstmi_state* state, void* workspace, size_t workspace_bytes,
+                          const double* explicit_z, const trstmi_report* report, hipStream_t stream) {
+  trstmi_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_state(state))) return st;
+  const Layout L = layout_of(p);
+  if ((st = check_ws(workspace, workspace_bytes, L.total))) return st;
+  if (explicit_z && ((uintptr_t)explicit_z & 15)) return fail(TRSTMI_E_INVALID_ARG, "explicit_z misaligned");
+  return enqueue_step(p, state, (char*)workspace, explicit_z, report, stream);
+}
+
+trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, void* workspace,
+                           size_t workspace_bytes, int32_t chunk, hipStream_t stream) {
+  trstmi_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_state(state))) return st;
+  const Layout L = layout_of(p);
+  if ((st = check_ws(workspace, workspace_bytes, L.total))) return st;
+  if (chunk < 1) return fail(TRSTMI_E_INVALID_ARG, "chunk must be >= 1");
+  char* ws = (char*)workspace;
+
+  int64_t t0 = 0;
+  int32_t flags = 0;
+  TRY_HIP(hipMemcpyAsync(&t0, state->step, sizeof(t0), hipMemcpyDeviceToHost, stream), "read step");
+  TRY_HIP(hipMemcpyAsync(&flags, state->flags, sizeof(flags), hipMemcpyDeviceToHost, stream), "read flags");
+  TRY_HIP(hipStreamSynchronize(stream), "sync");
+  if (flags & TRSTMI_FLAG_DONE) return TRSTMI_OK;
+  const int64_t left = p->max_steps > t0 ? p->max_steps - t0 : 0;
+  const int64_t max_chunks = left / chunk + 2;
+
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (stream != nullptr) {
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      trstmi_status cst = TRSTMI_OK;
+      for (int i = 0; i < chunk && cst == TRSTMI_OK; ++i) cst = enqueue_step(p, state, ws, nullptr, nullptr, stream);
+      hipError_t e2 = hipStreamEndCapture(stream, &graph);
+      if (cst != TRSTMI_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+      }
+      TRY_HIP(e2, "end capture");
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "graph instantiate");
+      }
+    }
+  }
+  trstmi_status result = TRSTMI_OK;
+  for (int64_t it = 0; it < max_chunks; ++it) {
+    if (exec) {
+      hipError_t e = hipGraphLaunch(exec, stream);
+      if (e != hipSuccess) {
+        result = hip_fail(e, "graph launch");
+        break;
+      }
+    } else {
+      for (int i = 0; i < chunk && result == TRSTMI_OK; ++i)
+        result = enqueue_step(p, state, ws, nullptr, nullptr, stream);
+      if (result != TRSTMI_OK) break;
+    }
+    hipError_t e = hipMemcpyAsync(&flags, state->flags, sizeof(flags), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      result = hip_fail(e, "poll");
+      break;
+    }
+    if (flags & TRSTMI_FLAG_DONE) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  return result;
+}
+
+trstmi_status trstmi_timing_enable(int32_t on) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> g(T.mu);
+  T.on = on != 0;
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_timing_reset(void) {
+  trstmi_status st = drain_timing();
+  Timing& T = timing();
+  std::lock_guard<std::mutex> g(T.mu);
+  T.totals.clear();
+  return st;
+}
+
+trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel || !total_ms || !launches) return fail(TRSTMI_E_INVALID_ARG, "timing_read: NULL argument");
+  trstmi_status st = drain_timing();
+  if (st) return st;
+  Timing& T = timing();
+  std::lock_guard<std::mutex> g(T.mu);
+  auto it = T.totals.find(kernel);
+  *total_ms = it == T.totals.end() ? 0.0 : it->second.first;
+  *launches = it == T.totals.end() ? 0 : it->second.second;
+  return TRSTMI_OK;
+}
+
+const char* trstmi_last_error(void) { return g_last_error.c_str(); }
+
+int32_t trstmi_abi_version(void) { return 1; }
+
+}  // extern "C"

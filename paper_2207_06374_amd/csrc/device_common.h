@@ -1,0 +1,115 @@
+// Device-side building blocks shared by the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trstmi {
+
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFlagAccepted = 1;
+constexpr int kFlagDone = 2;
+constexpr int kFlagNearTie = 4;
+constexpr int kFlagNoValid = 8;
+
+// Bit pattern of +inf; a stored maximum at or above it (as an unsigned
+// integer) is +inf or NaN, i.e. an invalid candidate.
+constexpr uint64_t kInfBits64 = 0x7FF0000000000000ull;
+constexpr uint32_t kInfBits32 = 0x7F800000u;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds on a 4-word
+// counter, 2-word key bumped by the Weyl constants between rounds.
+// One 32x32->64 multiply per product (v_mad_u64_u32) gives both halves.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Word -> uniform in (0, 1): (w + 1/2) 2^-32, exact in FP64.
+__device__ __forceinline__ double word_to_unit(uint32_t w) {
+  return ((double)w + 0.5) * 0x1p-32;
+}
+
+// Box-Muller (1958): (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0), in FP64.
+__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, double& g0, double& g1) {
+  const double u0 = word_to_unit(w0);
+  const double u1 = word_to_unit(w1);
+  const double r = sqrt(-2.0 * log(u0));
+  double s, c;
+  sincospi(2.0 * u1, &s, &c);
+  g0 = r * c;
+  g1 = r * s;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 -> bfloat16, round to nearest, ties to even, computed directly from
+// the double (no intermediate float rounding).  A bfloat16 keeps 8
+// significant bits: with |x| = m 2^e, 1/2 <= m < 1, the result is an integer
+// multiple of 2^(e-8) (spacing fixed at 2^-133 below the normal range).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
+  if (x != x) return 0x7FC0;
+  const uint64_t bits = (uint64_t)__double_as_longlong(x);
+  int e = (int)((bits >> 52) & 0x7FF) - 1022;  // frexp exponent for normal x (0 or subnormal -> tiny)
+  if (e < -125) e = -125;
+  const double up = __longlong_as_double((int64_t)(1023 + 8 - e) << 52);    // 2^(8-e)
+  const double down = __longlong_as_double((int64_t)(1023 - 8 + e) << 52);  // 2^(e-8)
+  const double r = rint(x * up) * down;  // exact: representable in bfloat16
+  const float f = (float)r;               // exact
+  return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Upper-triangle tile enumeration: tile t in [0, nt(nt+1)/2) <-> (bi, bj),
+// bi <= bj, row by row.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tile_decode(int t, int nt, int& bi, int& bj) {
+  int row = 0;
+  int rem = t;
+  while (rem >= nt - row) {
+    rem -= nt - row;
+    ++row;
+  }
+  bi = row;
+  bj = row + rem;
+}
+
+__device__ __forceinline__ int tile_linear(int bi, int bj, int nt) {
+  // number of tiles in rows 0..bi-1 plus offset in row bi
+  return bi * nt - (bi * (bi - 1)) / 2 + (bj - bi);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+}  // namespace trstmi

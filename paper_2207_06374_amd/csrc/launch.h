@@ -1,0 +1,128 @@
+// Host-side launchers of the library's kernels and their argument records.
+// Shared by the kernel translation units and the C-ABI layer (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace trstmi {
+
+enum OutKind { kOutF64 = 0, kOutF32 = 1, kOutBF16 = 2 };
+
+// Decision record written by the select kernel and read by the commit.
+struct Decision {
+  int32_t commit;        // 1: regenerate candidate `best` into the frame
+  int32_t best;          // selected candidate, -1 if none valid
+  int64_t t_old;         // step index the candidates were drawn at
+  double radius_old;     // radius the candidates were drawn with
+  int32_t screen_near;   // BF16 screen: k-th and (k+1)-th screened values nearly tie
+  int32_t pad;
+};
+
+// Perturb + renormalise (also: random start, normalise-only, commit).
+struct PerturbArgs {
+  const double* base;       // frame (2*d*n doubles, column stride 2d) or null (y = z)
+  const double* radius;     // device scalar radius (used when base and draws are both present)
+  const int64_t* tstep;     // device scalar step index, or null -> t_const
+  int64_t t_const;
+  const int32_t* cand_idx;  // device list slot -> candidate, or null -> c0 + slot
+  int32_t c0;
+  int32_t have_z;           // 0: y = base (normalise only)
+  const int32_t* gate;      // run only if (*gate & gate_mask) == gate_want (null: always)
+  int32_t gate_mask;
+  int32_t gate_want;
+  const double* z_explicit; // [c][n][d] complex, or null -> Philox draws
+  int64_t n;
+  int32_t d;
+  uint32_t seed;
+  uint32_t stream_id;
+  uint32_t tag;
+  void* out;                // candidate buffer
+  int32_t out_kind;         // OutKind
+  int32_t out_ld;           // elements per column in `out` (>= 2d; padding written as zero)
+  int64_t out_slot_stride;  // elements per slot in `out`
+  uint64_t* zero_max;       // if not null: zero_max[slot] <- 0 (block 0)
+};
+
+// Gram + fused max of |G|^2 over the strict upper triangle.
+struct GramArgs {
+  const void* cand;          // slot-major candidates
+  int64_t slot_stride;       // elements per slot
+  int32_t ldk;               // elements per column (>= 2d, multiple of 8, zero padded)
+  int32_t n;
+  int32_t d;
+  int32_t nt;                // tiles per side
+  uint64_t* cand_max;        // [slot] running max (bits of the float type)
+  const int32_t* flags;      // DONE gate (null: always run)
+  uint32_t* tile_max;        // screen: [slot][ntiles] max bits per tile (null: not kept)
+  // certified pruning of the FP64 recheck (all null/0 when off)
+  const uint32_t* screen_tile_max;  // [candidate][screen ntiles] float bits
+  const int32_t* slot_cand;         // slot -> candidate index
+  const double* thr;                // per slot: skip tiles whose screened max < thr
+  int32_t screen_ratio;             // screen tile edge / this kernel's tile edge
+  int32_t screen_nt;                // screen tiles per side
+};
+
+struct SelectArgs {
+  const uint64_t* cand_max;  // [count] max bits (double, or float if is_f32)
+  int32_t count;
+  int32_t is_f32;
+  const int32_t* slot_cand;  // slot -> candidate (null: identity)
+  double tau;                // near-tie threshold
+  int32_t use_screen_near;   // also report dec->screen_near as a near tie
+  double* mu;
+  double* radius;
+  int64_t* step;
+  int32_t* flags;
+  double grow, shrink, radius_min, radius_max;
+  int64_t max_steps;
+  double target_mu;
+  Decision* dec;
+  double* rep_cand_mu;       // [count] (null: not written)
+  int32_t* rep_best;         // [1]
+};
+
+struct TopkArgs {
+  const uint64_t* cand_max;  // [C] float bits of the screened max |G|^2
+  int32_t C;
+  int32_t k;
+  double eps;                // certified screen error bound (|G| units)
+  double screen_tie;         // gap below which membership of the top-k is a near tie
+  const int32_t* flags;
+  int32_t* rechecked;        // [k] out
+  double* thr;               // [k] out: per rechecked candidate, mu_screen - 2 eps
+  Decision* dec;
+  double* rep_cand_mu;       // [C] screened mu (null: not written)
+  int32_t* rep_rechecked;    // [k]
+};
+
+struct InitFinishArgs {
+  const uint64_t* max_bits;  // one value
+  int32_t is_f32;
+  double* mu;
+  double* radius;
+  int64_t* step;
+  int32_t* flags;
+  double radius0;
+  int64_t max_steps;
+  double target_mu;
+  double* mu_out;            // coherence entry: write mu here instead (state pointers null)
+};
+
+hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
+hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
+hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
+hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
+hipError_t launch_select(const SelectArgs& a, hipStream_t s);
+hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
+hipError_t launch_init_finish(const InitFinishArgs& a, hipStream_t s);
+hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,
+                              uint64_t* zero_max, hipStream_t s);
+
+// Tile edges of the Gram kernels (columns per tile side).
+constexpr int kTileF64 = 64;
+constexpr int kTileF32 = 64;
+constexpr int kTileBF16 = 128;
+
+}  // namespace trstmi

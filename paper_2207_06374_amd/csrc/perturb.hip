@@ -1,0 +1,213 @@
+// Candidate generation: trust-region perturbation and column renormalisation.
+//
+// For candidate c at step t:  Y = Phi + (radius / sqrt(d)) Z,  Z i.i.d. CN(0,1)
+// from Philox4x32-10, then every column is divided by its Euclidean norm (the
+// unconstrained formulation of section IV divides each column by its norm).
+// The same kernel draws the random start (Alg. 2 step 1: y = z, tag 1),
+// normalises a caller frame (y = Phi), and commits an accepted candidate in
+// place (regenerating it from the same counters).
+//
+// Work split: a column of d complex entries is ceil(d/2) Philox blocks (one
+// block = 4 words = 2 complex entries).  LPC lanes (a power of two <= 64)
+// share a column, each holding up to kMaxQ blocks in registers; the norm is
+// reduced across the LPC lanes with xor-shuffles, so a column never leaves
+// the wavefront.  Loads and stores are 16-byte and consecutive lanes touch
+// consecutive entries of a column.
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace trstmi {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxQ = 4;  // blocks per lane: d <= 2 * 64 * kMaxQ = 512
+
+__device__ __forceinline__ void store_pair(const PerturbArgs& a, size_t slot, int64_t col, int i,
+                                           double re0, double im0, double re1, double im1, bool two) {
+  const size_t off = slot * (size_t)a.out_slot_stride + (size_t)col * a.out_ld + 2 * (size_t)i;
+  if (a.out_kind == kOutF64) {
+    double* o = (double*)a.out + off;
+    *(double2*)o = make_double2(re0, im0);
+    if (two) *(double2*)(o + 2) = make_double2(re1, im1);
+  } else if (a.out_kind == kOutF32) {
+    float* o = (float*)a.out + off;
+    if (two) {
+      *(float4*)o = make_float4((float)re0, (float)im0, (float)re1, (float)im1);
+    } else {
+      *(float2*)o = make_float2((float)re0, (float)im0);
+    }
+  } else {
+    uint16_t* o = (uint16_t*)a.out + off;
+    const uint32_t w0 = (uint32_t)f64_to_bf16_rne(re0) | ((uint32_t)f64_to_bf16_rne(im0) << 16);
+    if (two) {
+      const uint32_t w1 = (uint32_t)f64_to_bf16_rne(re1) | ((uint32_t)f64_to_bf16_rne(im1) << 16);
+      *(uint2*)o = make_uint2(w0, w1);
+    } else {
+      *(uint32_t*)o = w0;
+    }
+  }
+}
+
+__device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot, int64_t col) {
+  // elements [2d, out_ld) of the column
+  const size_t off = slot * (size_t)a.out_slot_stride + (size_t)col * a.out_ld;
+  for (int k = 2 * a.d; k < a.out_ld; ++k) {
+    if (a.out_kind == kOutF64) ((double*)a.out)[off + k] = 0.0;
+    else if (a.out_kind == kOutF32) ((float*)a.out)[off + k] = 0.0f;
+    else ((uint16_t*)a.out)[off + k] = 0;
+  }
+}
+
+template <int LPC>
+__global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
+  if (a.gate && ((*a.gate & a.gate_mask) != a.gate_want)) return;
+  const int slot = blockIdx.y;
+  if (a.zero_max && blockIdx.x == 0 && threadIdx.x == 0) a.zero_max[slot] = 0;
+
+  const int c = a.cand_idx ? a.cand_idx[slot] : a.c0 + slot;
+  const int64_t t = a.tstep ? *a.tstep : a.t_const;
+  const int d = a.d;
+  const int nb = (d + 1) >> 1;
+  double s = 0.0;
+  if (a.base && a.have_z) s = *a.radius / sqrt((double)d);
+
+  constexpr int kColsPerWave = 64 / LPC;
+  constexpr int kColsPerIter = (kThreads / 64) * kColsPerWave;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lq = lane & (LPC - 1);
+
+  for (int64_t col0 = (int64_t)blockIdx.x * kColsPerIter; col0 < a.n;
+       col0 += (int64_t)gridDim.x * kColsPerIter) {
+    const int64_t col = col0 + wave * kColsPerWave + lane / LPC;
+    const bool active = col < a.n;  // whole LPC groups share `active`
+    double y[kMaxQ][4];
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int qi = 0; qi < kMaxQ; ++qi) {
+      const int q = lq + qi * LPC;
+      y[qi][0] = y[qi][1] = y[qi][2] = y[qi][3] = 0.0;
+      if (!active || q >= nb) continue;
+      const int i0 = 2 * q;
+      const bool two = (i0 + 1) < d;
+      double z[4] = {0.0, 0.0, 0.0, 0.0};
+      if (a.have_z || !a.base) {
+        if (a.z_explicit) {
+          const double* zp = a.z_explicit + 2 * (((size_t)c * a.n + col) * d + i0);
+          z[0] = zp[0];
+          z[1] = zp[1];
+          if (two) {
+            z[2] = zp[2];
+            z[3] = zp[3];
+          }
+        } else {
+          const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, a.tag};
+          const u32x4 w = philox4x32_10(ctr, a.seed, a.stream_id);
+          double g0, g1, g2, g3;
+          box_muller(w.x, w.y, g0, g1);
+          box_muller(w.z, w.w, g2, g3);
+          const double h = 0.7071067811865476;  // sqrt(1/2), correctly rounded
+          z[0] = g0 * h;
+          z[1] = g1 * h;
+          z[2] = g2 * h;
+          z[3] = g3 * h;
+        }
+      }
+      if (a.base) {
+        const double* bp = a.base + 2 * ((size_t)col * d + i0);
+        const double2 p0 = *(const double2*)bp;
+        double2 p1 = make_double2(0.0, 0.0);
+        if (two) p1 = *(const double2*)(bp + 2);
+        if (a.have_z) {
+          y[qi][0] = p0.x + s * z[0];
+          y[qi][1] = p0.y + s * z[1];
+          y[qi][2] = p1.x + s * z[2];
+          y[qi][3] = p1.y + s * z[3];
+        } else {
+          y[qi][0] = p0.x;
+          y[qi][1] = p0.y;
+          y[qi][2] = p1.x;
+          y[qi][3] = p1.y;
+        }
+      } else {
+        y[qi][0] = z[0];
+        y[qi][1] = z[1];
+        y[qi][2] = z[2];
+        y[qi][3] = z[3];
+      }
+      if (!two) {
+        y[qi][2] = 0.0;
+        y[qi][3] = 0.0;
+      }
+      nrm2 += (y[qi][0] * y[qi][0] + y[qi][1] * y[qi][1]) + (y[qi][2] * y[qi][2] + y[qi][3] * y[qi][3]);
+    }
+#pragma unroll
+    for (int off = LPC / 2; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
+    if (!active) continue;
+    const double nrm = sqrt(nrm2);
+    const bool bad = !(nrm > 0.0 && nrm < __builtin_inf());
+    const double qnan = __builtin_nan("");
+#pragma unroll
+    for (int qi = 0; qi < kMaxQ; ++qi) {
+      const int q = lq + qi * LPC;
+      if (q >= nb) continue;
+      const int i0 = 2 * q;
+      const bool two = (i0 + 1) < d;
+      double o[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = bad ? qnan : y[qi][e] / nrm;
+      store_pair(a, slot, col, i0, o[0], o[1], o[2], o[3], two);
+      if (q == nb - 1 && a.out_ld > 2 * d) store_zero_pad(a, slot, col);
+    }
+  }
+}
+
+// FP64 frame -> FP32 copy with zero padding (no renormalisation).
+__global__ __launch_bounds__(kThreads) void k_convert_f32(const double* frame, int64_t n, int d, float* out,
+                                                          int out_ld, uint64_t* zero_max) {
+  if (zero_max && blockIdx.x == 0 && threadIdx.x == 0) zero_max[0] = 0;
+  const int64_t total = n * out_ld;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThreads) {
+    const int64_t col = e / out_ld;
+    const int k = (int)(e - col * out_ld);
+    out[e] = k < 2 * d ? (float)frame[2 * col * d + k] : 0.0f;
+  }
+}
+
+template <int LPC>
+hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
+  constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
+  int64_t groups = (a.n + kColsPerIter - 1) / kColsPerIter;
+  // enough blocks to fill the chip across all slots, each looping over column groups
+  int64_t want = (8192 + slots - 1) / slots;
+  if (want < 1) want = 1;
+  const int gx = (int)(groups < want ? groups : want);
+  hipLaunchKernelGGL(k_perturb<LPC>, dim3(gx, slots), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
+  const int nb = (a.d + 1) / 2;
+  if (nb <= 1) return launch_lpc<1>(a, slots, s);
+  if (nb <= 2) return launch_lpc<2>(a, slots, s);
+  if (nb <= 4) return launch_lpc<4>(a, slots, s);
+  if (nb <= 8) return launch_lpc<8>(a, slots, s);
+  if (nb <= 16) return launch_lpc<16>(a, slots, s);
+  if (nb <= 32) return launch_lpc<32>(a, slots, s);
+  return launch_lpc<64>(a, slots, s);
+}
+
+hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,
+                              uint64_t* zero_max, hipStream_t s) {
+  const int64_t total = n * out_ld;
+  int64_t blocks = (total + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_convert_f32, dim3((int)blocks), dim3(kThreads), 0, s, frame, n, d, out, out_ld, zero_max);
+  return hipGetLastError();
+}
+
+}  // namespace trstmi

@@ -1,0 +1,198 @@
+// Select / accept / radius update, top-k screening selection, and the
+// finishing kernels of the random start and of the coherence entry point.
+//
+// All run as a single 256-thread block on the stream after the Gram kernels,
+// so a step never waits on the host.  Candidate maxima arrive as IEEE bit
+// patterns of max |G|^2 (double, or float widened to 64 bits); a pattern at
+// or above +inf is an invalid candidate.  mu_c = sqrt(max |G|^2) in FP64.
+// The best candidate is the minimum of (mu_c, c), ties to the lower index;
+// it is accepted iff mu_c* < mu (strict); the radius is multiplied by grow
+// on accept and by shrink otherwise, clamped to [radius_min, radius_max].
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace trstmi {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kBitmapWords = 65536 / 32;  // one bit per candidate
+
+__device__ __forceinline__ double bits_to_mu(uint64_t b, int is_f32) {
+  if (is_f32) {
+    const uint32_t f = (uint32_t)b;
+    if (f >= kInfBits32) return __builtin_inf();
+    return sqrt((double)__uint_as_float(f));
+  }
+  if (b >= kInfBits64) return __builtin_inf();
+  return sqrt(__longlong_as_double((int64_t)b));
+}
+
+// (value, index) lexicographic min, and the smallest value of any other entry.
+struct Best2 {
+  double v1;
+  int c1;
+  double v2;
+};
+
+__device__ __forceinline__ void best2_push(Best2& b, double v, int c) {
+  if (v < b.v1 || (v == b.v1 && c < b.c1)) {
+    b.v2 = b.v1;
+    b.v1 = v;
+    b.c1 = c;
+  } else if (v < b.v2) {
+    b.v2 = v;
+  }
+}
+
+__device__ __forceinline__ void best2_merge(Best2& a, const Best2& o) {
+  if (o.c1 >= 0) best2_push(a, o.v1, o.c1);
+  if (o.v2 < a.v2) a.v2 = o.v2;
+}
+
+__global__ __launch_bounds__(kThreads) void k_select(SelectArgs a) {
+  __shared__ Best2 sh[kThreads];
+  const int tid = threadIdx.x;
+  if (*a.flags & kFlagDone) {
+    if (tid == 0) a.dec->commit = 0;
+    return;
+  }
+  Best2 b = {__builtin_inf(), -1, __builtin_inf()};
+  for (int s = tid; s < a.count; s += kThreads) {
+    const double mu = bits_to_mu(a.cand_max[s], a.is_f32);
+    const int c = a.slot_cand ? a.slot_cand[s] : s;
+    if (a.rep_cand_mu) a.rep_cand_mu[s] = mu;
+    if (mu < __builtin_inf()) best2_push(b, mu, c);
+  }
+  sh[tid] = b;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      Best2 x = sh[tid];
+      best2_merge(x, sh[tid + off]);
+      sh[tid] = x;
+    }
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  const Best2 r = sh[0];
+  const double mu_t = *a.mu;
+  const double rad = *a.radius;
+  const int64_t t = *a.step;
+  const bool valid = r.c1 >= 0;
+  const bool accept = valid && r.v1 < mu_t;
+  bool near = valid && fabs(r.v1 - mu_t) <= a.tau;
+  if (valid && r.v2 - r.v1 <= a.tau) near = true;
+  if (a.use_screen_near && a.dec->screen_near) near = true;
+
+  a.dec->best = r.c1;
+  a.dec->t_old = t;
+  a.dec->radius_old = rad;
+  a.dec->commit = accept ? 1 : 0;
+  double new_mu = mu_t;
+  double new_rad;
+  if (accept) {
+    new_mu = r.v1;
+    new_rad = fmin(rad * a.grow, a.radius_max);
+  } else {
+    new_rad = fmax(rad * a.shrink, a.radius_min);
+  }
+  const int64_t nt = t + 1;
+  const bool done = (a.target_mu > 0.0 && new_mu <= a.target_mu) || nt >= a.max_steps;
+  *a.mu = new_mu;
+  *a.radius = new_rad;
+  *a.step = nt;
+  *a.flags = (accept ? kFlagAccepted : 0) | (near ? kFlagNearTie : 0) | (valid ? 0 : kFlagNoValid) |
+             (done ? kFlagDone : 0);
+  if (a.rep_best) *a.rep_best = r.c1;
+}
+
+// k smallest screened values by (mu_screen, c); thresholds for certified pruning.
+__global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
+  __shared__ double sv[kThreads];
+  __shared__ int sc[kThreads];
+  __shared__ uint32_t taken[kBitmapWords];
+  const int tid = threadIdx.x;
+  if (*a.flags & kFlagDone) return;
+  for (int q = tid; q < kBitmapWords; q += kThreads) taken[q] = 0;
+  for (int c = tid; c < a.C && a.rep_cand_mu; c += kThreads) a.rep_cand_mu[c] = bits_to_mu(a.cand_max[c], 1);
+  __syncthreads();
+  double prev = 0.0;
+  for (int round = 0; round <= a.k && round < a.C; ++round) {
+    double bv = __builtin_inf();
+    int bc = 0x7fffffff;
+    for (int c = tid; c < a.C; c += kThreads) {
+      if (taken[c >> 5] & (1u << (c & 31))) continue;
+      const double mu = bits_to_mu(a.cand_max[c], 1);
+      if (mu < bv || (mu == bv && c < bc)) {
+        bv = mu;
+        bc = c;
+      }
+    }
+    sv[tid] = bv;
+    sc[tid] = bc;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double ov = sv[tid + off];
+        const int oc = sc[tid + off];
+        if (ov < sv[tid] || (ov == sv[tid] && oc < sc[tid])) {
+          sv[tid] = ov;
+          sc[tid] = oc;
+        }
+      }
+      __syncthreads();
+    }
+    const double v = sv[0];
+    const int c = sc[0];
+    __syncthreads();
+    if (round < a.k) {
+      if (tid == 0) {
+        taken[c >> 5] |= 1u << (c & 31);
+        a.rechecked[round] = c;
+        // an invalid (non-finite) screened value disables pruning for that candidate
+        a.thr[round] = v < __builtin_inf() ? v - 2.0 * a.eps : -__builtin_inf();
+        if (a.rep_rechecked) a.rep_rechecked[round] = c;
+      }
+      prev = v;
+    } else if (tid == 0) {
+      a.dec->screen_near = (v - prev <= a.screen_tie) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && a.k >= a.C) a.dec->screen_near = 0;
+}
+
+__global__ void k_init_finish(InitFinishArgs a) {
+  if (threadIdx.x != 0) return;
+  const double mu = bits_to_mu(*a.max_bits, a.is_f32);
+  if (a.mu_out) {
+    *a.mu_out = mu;
+    return;
+  }
+  *a.mu = mu;
+  *a.radius = a.radius0;
+  *a.step = 0;
+  const bool done = (a.target_mu > 0.0 && mu <= a.target_mu) || a.max_steps <= 0;
+  *a.flags = done ? kFlagDone : 0;
+}
+
+}  // namespace
+
+hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_finish(const InitFinishArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace trstmi

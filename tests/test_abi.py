@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function ``include/trstmi.h`` declares, and rejects bad arguments
+before anything reaches the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+abi = pytest.importorskip("paper_2207_06374_amd._abi")
+
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if fn.endswith(".h"):
+            text = open(os.path.join(HEADER_DIR, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(trstmi_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.fail("libtrstmi.so is not built (run `python -m paper_2207_06374_amd.build`)")
+    return abi.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(abi.SIGNATURES) >= names
+
+
+def test_struct_sizes_match_header():
+    # int64 n, d; 4 x int32; 2 x uint64; 5 doubles; int64; 2 doubles
+    assert ctypes.sizeof(abi.Params) == 8 * 2 + 4 * 4 + 8 * 2 + 8 * 5 + 8 + 8 * 2
+    assert ctypes.sizeof(abi.State) == 5 * 8
+    assert ctypes.sizeof(abi.Report) == 4 * 8
+
+
+def _params(L, n=16, d=4, **kw):
+    p = abi.Params()
+    L.trstmi_default_params(ctypes.byref(p), n, d)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_defaults_and_workspace(L):
+    p = _params(L)
+    assert p.candidates == 64 and p.mode == abi.MODE_FP64 and p.recheck_topk == 8
+    assert p.radius0 == 0.1 and p.grow == 2.0 and p.shrink == 0.5 and p.radius_min == 1e-12
+    assert p.radius_max == 1.0 and p.max_steps == 1000
+    ws = L.trstmi_workspace_bytes(ctypes.byref(p))
+    # candidate buffer: 64 candidates x 16 columns x 8 (padded 2d) doubles
+    assert ws >= 64 * 16 * 8 * 8 and ws % 256 == 0
+    big = _params(L, 4096, 64, candidates=128, mode=abi.MODE_BF16_SCREEN)
+    assert L.trstmi_workspace_bytes(ctypes.byref(big)) >= 128 * 4096 * 128 * 2 + 8 * 4096 * 128 * 8
+    assert L.trstmi_coherence_workspace_bytes(4096, 64, abi.MODE_FP64) >= 4096 * 128 * 8
+
+
+@pytest.mark.parametrize("field,value", [("n", 1), ("d", 0), ("d", 513), ("candidates", 0),
+                                         ("candidates", 40000), ("radius0", 0.0), ("radius0", 2.0),
+                                         ("radius_min", -1.0), ("grow", 0.5), ("shrink", 0.0),
+                                         ("shrink", 1.5), ("max_steps", -1), ("seed", 2 ** 32),
+                                         ("stream_id", 2 ** 33), ("mode", 7), ("radius0", float("nan"))])
+def test_invalid_params_rejected_on_host(L, field, value):
+    p = _params(L, **{field: value})
+    assert L.trstmi_workspace_bytes(ctypes.byref(p)) == 0
+    fake = ctypes.c_void_p(256)
+    st = abi.State(256, 256, 256, 256, 256)
+    status = L.trstmi_step(ctypes.byref(p), ctypes.byref(st), fake, 1 << 40, None, None, None)
+    assert status == abi.E_INVALID_ARG
+    assert L.trstmi_last_error()
+
+
+def test_bf16_topk_range(L):
+    p = _params(L, mode=abi.MODE_BF16_SCREEN, candidates=4, recheck_topk=5)
+    assert L.trstmi_workspace_bytes(ctypes.byref(p)) == 0
+    p.recheck_topk = 4
+    assert L.trstmi_workspace_bytes(ctypes.byref(p)) > 0
+
+
+def test_workspace_errors(L):
+    p = _params(L)
+    need = L.trstmi_workspace_bytes(ctypes.byref(p))
+    st = abi.State(256, 256, 256, 256, 256)
+    assert L.trstmi_step(ctypes.byref(p), ctypes.byref(st), None, need, None, None, None) == abi.E_WORKSPACE
+    assert L.trstmi_step(ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(128), need, None, None,
+                         None) == abi.E_WORKSPACE
+    assert L.trstmi_step(ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(512), need - 1, None, None,
+                         None) == abi.E_WORKSPACE
+    assert b"workspace" in L.trstmi_last_error()
+
+
+def test_state_and_pointer_errors(L):
+    p = _params(L)
+    st = abi.State(256, 0, 256, 256, 256)
+    assert L.trstmi_init_haar(ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(256), 1 << 30,
+                              None) == abi.E_INVALID_ARG
+    st = abi.State(264, 256, 256, 256, 256)   # frame not 16-byte aligned
+    assert L.trstmi_init_haar(ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(256), 1 << 30,
+                              None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence(1, 4, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                              1 << 20, None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence(16, 4, 9, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                              1 << 20, None) == abi.E_INVALID_ARG
+    assert L.trstmi_solve(ctypes.byref(p), ctypes.byref(abi.State(256, 256, 256, 256, 256)),
+                          ctypes.c_void_p(256), 1 << 30, 0, None) == abi.E_INVALID_ARG
+    assert L.trstmi_candidates(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 0, 0, 0, None,
+                               ctypes.c_void_p(256), None) == abi.E_INVALID_ARG
+
+
+def test_binding_refuses_without_gpu_or_library(monkeypatch):
+    """The product path has no fallback: with the library path pointing
+    nowhere, loading fails loudly."""
+    monkeypatch.setattr(abi, "LIB_PATH", "/nonexistent/libtrstmi.so")
+    monkeypatch.setattr(abi, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        abi.lib()

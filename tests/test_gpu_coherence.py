@@ -1,0 +1,135 @@
+"""GPU parity: trstmi_coherence and the random start / candidates against the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import frames
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2207_06374_amd")
+
+
+def _gpu_mu(F, mode):
+    d, n = F.shape
+    dev = lib.frame_to_device(F)
+    return float(lib.coherence(dev, n, d, mode).item())
+
+
+SHAPES = [(2, 1), (3, 2), (16, 4), (65, 3), (100, 7), (129, 5), (200, 16), (257, 33), (300, 64), (64, 128),
+          (130, 100), (1000, 32)]
+
+
+@pytest.mark.parametrize("n,d", SHAPES)
+def test_coherence_fp64_random(n, d):
+    F = inputs.random_frame(n, d, seed=n * 1000 + d)
+    ref = oracle.coherence(F)
+    got = _gpu_mu(F, lib.MODE_FP64)
+    print(f"n={n} d={d} ref={ref!r} got={got!r}", flush=True)
+    assert abs(got - ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(frames.KNOWN))
+def test_coherence_fp64_known_frames(name):
+    build, mu = frames.KNOWN[name]
+    F = build()
+    got = _gpu_mu(F, lib.MODE_FP64)
+    assert abs(got - mu) <= 1e-12
+
+
+def test_coherence_fp64_numeric_sic():
+    F = frames.sic_numeric(4)
+    assert abs(_gpu_mu(F, lib.MODE_FP64) - math.sqrt(0.2)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,d", SHAPES)
+def test_coherence_fp32_random(n, d):
+    F = inputs.random_frame(n, d, seed=7 + n + d)
+    ref = oracle.coherence(F)
+    got = _gpu_mu(F, lib.MODE_FP32)
+    assert abs(got - ref) <= 2e-6
+
+
+@pytest.mark.parametrize("n,d", SHAPES)
+def test_coherence_bf16_screen_within_bound(n, d):
+    F = inputs.random_frame(n, d, seed=11 + n + d)
+    exact = oracle.coherence(F)
+    Fn, _ = oracle.normalize_columns(F)
+    emul = oracle.evaluate_candidates(Fn[None], np.array([True]), "bf16")[0]
+    got = _gpu_mu(F, lib.MODE_BF16_SCREEN)
+    assert abs(got - exact) <= oracle.screen_error_bound(d)
+    # same bf16 inputs: only the FP32 accumulation differs
+    assert abs(got - emul) <= 2e-5
+
+
+@pytest.mark.parametrize("mode", [lib.MODE_FP64, lib.MODE_FP32, lib.MODE_BF16_SCREEN])
+def test_zero_and_nonfinite_column_give_inf(mode):
+    F = inputs.random_frame(40, 5, seed=3)
+    F[:, 17] = 0
+    assert _gpu_mu(F, mode) == math.inf
+    F = inputs.random_frame(40, 5, seed=3)
+    F[2, 33] = np.inf
+    assert _gpu_mu(F, mode) == math.inf
+
+
+def test_coherence_full_size_haar():
+    """Full-size 4096 x 64 frame (the throughput workload's shape)."""
+    p = oracle.Params(n=4096, d=64, seed=0)
+    F = oracle.haar_init(p).frame
+    ref = oracle.coherence(F)
+    assert abs(_gpu_mu(F, lib.MODE_FP64) - ref) <= 1e-12
+    assert abs(_gpu_mu(F, lib.MODE_FP32) - ref) <= 2e-6
+    assert abs(_gpu_mu(F, lib.MODE_BF16_SCREEN) - ref) <= oracle.screen_error_bound(64)
+
+
+@pytest.mark.parametrize("n,d,seed,stream", [(16, 4, 0, 0), (33, 5, 7, 3), (1024, 32, 0, 0), (300, 64, 9, 1),
+                                             (50, 1, 2, 0)])
+def test_haar_start_parity(n, d, seed, stream):
+    s = lib.Solver(n, d, seed=seed, stream_id=stream, mode="fp64")
+    s.init_haar()
+    F, mu, radius, t, flags = s.host_state()
+    ref = oracle.haar_init(oracle.Params(n=n, d=d, seed=seed, stream_id=stream))
+    assert np.max(np.abs(F - ref.frame)) <= 1e-14
+    assert abs(mu - ref.mu) <= 1e-12
+    assert radius == 0.1 and t == 0 and flags == 0
+
+
+@pytest.mark.parametrize("n,d,C,t", [(16, 4, 64, 0), (37, 7, 9, 5), (1024, 32, 4, 123), (70, 130, 3, 2)])
+def test_candidates_parity(n, d, C, t):
+    p = oracle.Params(n=n, d=d, candidates=C, seed=1, stream_id=2)
+    st = oracle.haar_init(p)
+    params = lib.default_params(n, d, candidates=C, seed=1, stream_id=2)
+    frame = lib.frame_to_device(st.frame)
+    radius = torch.tensor([0.05], dtype=torch.float64, device="cuda")
+    out = lib.candidates(params, frame, radius, t, 0, C)
+    got = out.cpu().numpy().reshape(C, n, d, 2)
+    got = (got[..., 0] + 1j * got[..., 1]).transpose(0, 2, 1)
+    Z = oracle.perturbations(p, t)
+    ref, valid = oracle.make_candidates(st.frame, 0.05, d, Z)
+    assert valid.all()
+    assert np.max(np.abs(got - ref)) <= 1e-14
+
+
+def test_candidates_explicit_z_and_invalid_column():
+    n, d = 20, 3
+    F = inputs.random_frame(n, d, 1)
+    Fn, _ = oracle.normalize_columns(F)
+    Z = inputs.random_perturbation(n, d, 2, seed=5)
+    s = 0.3 / math.sqrt(d)
+    Z[1][:, 4] = np.nan                                   # candidate 1, column 4: non-finite
+    params = lib.default_params(n, d, candidates=2)
+    zdev = torch.from_numpy(np.ascontiguousarray(np.transpose(Z, (0, 2, 1))).view(np.float64).ravel().copy()).cuda()
+    out = lib.candidates(params, lib.frame_to_device(Fn), torch.tensor([0.3], dtype=torch.float64, device="cuda"),
+                         0, 0, 2, explicit_z=zdev)
+    got = out.cpu().numpy().reshape(2, n, d, 2)
+    got = (got[..., 0] + 1j * got[..., 1]).transpose(0, 2, 1)
+    ref, valid = oracle.make_candidates(Fn, 0.3, d, Z)
+    assert valid[0] and not valid[1]
+    assert np.max(np.abs(got[0] - ref[0])) <= 1e-15
+    assert np.all(np.isnan(got[1][:, 4]))
+    assert np.max(np.abs(np.delete(got[1], 4, axis=1) - np.delete(ref[1], 4, axis=1))) <= 1e-15
