@@ -129,7 +129,11 @@ constexpr int64_t kMaxN = 1 << 18;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Elements per column of an internal candidate buffer: 2d rounded up to a
+// multiple of 8 (FP64 / FP32) or of 32 (BF16: one MFMA K step), zero padded.
 int32_t ld_of(int64_t d) { return (int32_t)((2 * d + 7) / 8 * 8); }
+int32_t ld16_of(int64_t d) { return (int32_t)((2 * d + 31) / 32 * 32); }
+int32_t ld_mode(int64_t d, int32_t mode) { return mode == TRSTMI_MODE_BF16_SCREEN ? ld16_of(d) : ld_of(d); }
 
 int nt_of(int64_t n, int tile) { return (int)((n + tile - 1) / tile); }
 
@@ -143,7 +147,7 @@ size_t elem_of_mode(int32_t mode) { return mode == TRSTMI_MODE_FP64 ? 8 : (mode 
 // Offsets of the step workspace.
 struct Layout {
   int64_t n, d;
-  int32_t C, k, ld;
+  int32_t C, k, ld, ldc;  // ld: FP64/FP32 buffers; ldc: the mode's candidate buffer
   size_t cand, cand_max, dec, tile_max, rechecked, thr, recheck, recheck_max, total;
 };
 
@@ -154,9 +158,10 @@ Layout layout_of(const trstmi_params* p) {
   L.C = p->candidates;
   L.k = p->mode == TRSTMI_MODE_BF16_SCREEN ? p->recheck_topk : 0;
   L.ld = ld_of(p->d);
+  L.ldc = ld_mode(p->d, p->mode);
   size_t off = 0;
   L.cand = off;
-  off = align256(off + (size_t)L.C * L.n * L.ld * elem_of_mode(p->mode));
+  off = align256(off + (size_t)L.C * L.n * L.ldc * elem_of_mode(p->mode));
   L.cand_max = off;
   off = align256(off + (size_t)L.C * 8);
   L.dec = off;
@@ -276,7 +281,8 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   const int C = p->candidates;
   uint64_t* cand_max = (uint64_t*)(ws + L.cand_max);
   Decision* dec = (Decision*)(ws + L.dec);
-  const int64_t slot_stride = L.n * L.ld;
+  const int64_t slot_stride = L.n * L.ldc;
+  const int64_t slot_stride64 = L.n * L.ld;
 
   PerturbArgs pa = perturb_base(p);
   pa.base = st->frame;
@@ -288,7 +294,7 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   pa.z_explicit = z;
   pa.out = ws + L.cand;
   pa.out_kind = p->mode == TRSTMI_MODE_FP64 ? kOutF64 : (p->mode == TRSTMI_MODE_FP32 ? kOutF32 : kOutBF16);
-  pa.out_ld = L.ld;
+  pa.out_ld = L.ldc;
   pa.out_slot_stride = slot_stride;
   pa.zero_max = cand_max;
   TRY_HIP(TIMED("perturb", s, launch_perturb(pa, C, s)), "perturb");
@@ -310,7 +316,7 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
 
   if (p->mode == TRSTMI_MODE_FP64 || p->mode == TRSTMI_MODE_FP32) {
     const bool f32 = p->mode == TRSTMI_MODE_FP32;
-    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ld, f32 ? kTileF32 : kTileF64, cand_max, st->flags);
+    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ldc, f32 ? kTileF32 : kTileF64, cand_max, st->flags);
     TRY_HIP(TIMED(f32 ? "gram_f32" : "gram_f64", s, f32 ? launch_gram_f32(g, C, s) : launch_gram_f64(g, C, s)), "gram");
     sa.cand_max = cand_max;
     sa.count = C;
@@ -322,7 +328,7 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
     int32_t* rechecked = (int32_t*)(ws + L.rechecked);
     double* thr = (double*)(ws + L.thr);
     uint64_t* recheck_max = (uint64_t*)(ws + L.recheck_max);
-    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ld, kTileBF16, cand_max, st->flags);
+    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ldc, kTileBF16, cand_max, st->flags);
     g.tile_max = tile_max;
     TRY_HIP(TIMED("gram_bf16", s, launch_gram_bf16(g, C, s)), "gram_bf16");
 
@@ -344,10 +350,12 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
     pr.cand_idx = rechecked;
     pr.out = ws + L.recheck;
     pr.out_kind = kOutF64;
+    pr.out_ld = L.ld;
+    pr.out_slot_stride = slot_stride64;
     pr.zero_max = recheck_max;
     TRY_HIP(TIMED("perturb_recheck", s, launch_perturb(pr, L.k, s)), "perturb_recheck");
 
-    GramArgs g64 = gram_base(L.n, L.d, ws + L.recheck, slot_stride, L.ld, kTileF64, recheck_max, st->flags);
+    GramArgs g64 = gram_base(L.n, L.d, ws + L.recheck, slot_stride64, L.ld, kTileF64, recheck_max, st->flags);
     g64.screen_tile_max = tile_max;
     g64.slot_cand = rechecked;
     g64.thr = thr;
@@ -413,7 +421,7 @@ size_t trstmi_workspace_bytes(const trstmi_params* p) {
 
 size_t trstmi_coherence_workspace_bytes(int64_t n, int64_t d, int32_t mode) {
   if (check_size(n, d) || check_mode(mode)) return 0;
-  return align256((size_t)n * ld_of(d) * elem_of_mode(mode)) + 256;
+  return align256((size_t)n * ld_mode(d, mode) * elem_of_mode(mode)) + 256;
 }
 
 trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double* frame, double* mu_out,
@@ -426,7 +434,7 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
   const size_t need = trstmi_coherence_workspace_bytes(n, d, mode);
   if ((st = check_ws(workspace, workspace_bytes, need))) return st;
   char* ws = (char*)workspace;
-  const int32_t ld = ld_of(d);
+  const int32_t ld = ld_mode(d, mode);
   uint64_t* mx = (uint64_t*)(ws + align256((size_t)n * ld * elem_of_mode(mode)));
 
   PerturbArgs pa{};

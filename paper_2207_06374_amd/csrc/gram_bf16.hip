@@ -2,18 +2,34 @@
 // v_mfma_f32_16x16x32_bf16 (gfx950), FP32 accumulation.
 //
 // Inputs are the FP64 unit candidates rounded to bfloat16 (nearest-even) by
-// the perturb kernel, column stride ldk (multiple of 8, zero padded).  As in
-// the FP64 kernel, Re <phi_j,phi_k> = u_j . u_k and Im = u_j . v_k with v the
-// (im, -re) swap of u; here v is built in registers from each 32-bit (re, im)
-// pair of the B fragment with one funnel shift and one sign flip.
+// the perturb kernel, column stride ldk = 2d rounded up to a multiple of 32,
+// zero padded.  A complex column is the real 2d-vector u = (a_0, b_0, ...);
+// with v = (b_0, -a_0, b_1, -a_1, ...):
+//   Re <phi_j, phi_k> = u_j . u_k,   Im <phi_j, phi_k> = -(v_j . u_k),
+// so both parts share the B operand u_k, and v_j is built once per tile from
+// the A rows held in registers (one funnel shift and one sign flip per 32-bit
+// (re, im) pair).
 //
-// Tile: 128 x 128 complex outputs per 256-thread block, each wave a 64 x 64
-// quadrant = 4 x 4 MFMA blocks of 16 x 16 (Re and Im accumulators in 128
-// VGPRs).  K is staged through LDS in chunks of 128 bf16 per column, 8 bf16 of
-// padding per column so 16 lanes reading 16 columns at one k offset hit
-// distinct banks with 16-byte reads.  The block writes its tile maximum
-// (for certified pruning of the FP64 recheck) and updates the candidate's
-// running maximum with one atomic.
+// Main kernel (2d <= 256): a 256-thread block owns a 128 x 128 tile of the
+// strict upper triangle.  Each wave keeps its 32 rows (A = u and v for the
+// whole K) in VGPRs, loaded straight from global memory; the 128 B columns
+// are staged once in LDS (16 bytes of padding per column: 16 lanes reading 16
+// columns at one k offset hit distinct banks).  The wave then sweeps the 8
+// column blocks of 16: 2 x 2 x K/32 MFMAs per block, then |G|^2 = Re^2 + Im^2
+// and a running max on the float bit patterns (integer max keeps NaN, which
+// marks an invalid candidate, above every finite value).  Only diagonal tiles
+// mask (j > i); rows/columns past N are zero and contribute 0.  On a diagonal
+// tile a wave skips the column blocks lying wholly below the diagonal.
+//
+// Blocks are mapped XCD-aware: the dispatcher deals consecutive block ids to
+// the 8 XCDs in turn, so block b runs on XCD b mod 8; all tiles of candidate
+// c are given to blocks with b mod 8 = c mod 8, which keeps a candidate's
+// columns in one XCD's L2.
+//
+// Each block writes its tile maximum (used to prune the FP64 recheck) and
+// updates the candidate's running maximum with one atomic.
+//
+// Fallback kernel (2d > 256): 128 x 128 tile, K looped in LDS chunks of 128.
 
 #include "device_common.h"
 #include "launch.h"
@@ -23,8 +39,6 @@ namespace trstmi {
 namespace {
 
 constexpr int T = kTileBF16;
-constexpr int KCB = 128;
-constexpr int LDB = KCB + 8;
 
 __device__ __forceinline__ u32x4 swap_negate(u32x4 u) {
   u32x4 v;
@@ -33,11 +47,138 @@ __device__ __forceinline__ u32x4 swap_negate(u32x4 u) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_gram_bf16(GramArgs a) {
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) {
+  const uint32_t bc = b > c ? b : c;  // folded into v_max3_u32
+  return a > bc ? a : bc;
+}
+
+__device__ __forceinline__ bool xcd_slot(const GramArgs& a, int tiles, int& slot, int& tile) {
+  const int b = blockIdx.x;
+  const int local = b >> 3;
+  slot = (local / tiles) * 8 + (b & 7);
+  tile = local % tiles;
+  return slot < a.slots;
+}
+
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
   if (a.flags && (*a.flags & kFlagDone)) return;
-  const int slot = blockIdx.y;
+  const int tiles = a.nt * (a.nt + 1) / 2;
+  int slot, tile;
+  if (!xcd_slot(a, tiles, slot, tile)) return;
   int bi, bj;
-  tile_decode(blockIdx.x, a.nt, bi, bj);
+  tile_decode(tile, a.nt, bi, bj);
+
+  constexpr int KP = 32 * KS;   // bf16 per column
+  constexpr int LDL = KP + 8;   // LDS column stride (bf16)
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * LDL];
+  __shared__ uint32_t red[4];
+
+  const uint16_t* base = (const uint16_t*)a.cand + (size_t)slot * a.slot_stride;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int l16 = lane & 15;
+  const int koff = 8 * (lane >> 4);
+
+  // B columns of the tile -> LDS
+#pragma unroll
+  for (int it = 0; it < (T * KS * 4) / 256; ++it) {
+    const int idx = it * 256 + tid;
+    const int col = idx / (KS * 4);
+    const int ch = idx % (KS * 4);
+    const int cj = bj * T + col;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (cj < a.n) v = *(const u32x4*)(base + (size_t)cj * a.ldk + ch * 8);
+    *(u32x4*)&Bs[col * LDL + ch * 8] = v;
+  }
+
+  // this wave's 32 rows, u and v, whole K, in registers
+  u32x4 aU[2][KS], aV[2][KS];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    const int row = bi * T + w * 32 + rb * 16 + l16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (row < a.n) v = *(const u32x4*)(base + (size_t)row * a.ldk + ks * 32 + koff);
+      aU[rb][ks] = v;
+      aV[rb][ks] = swap_negate(v);
+    }
+  }
+  __syncthreads();
+
+  const bool diag = bi == bj;
+  uint32_t best = 0;
+#pragma unroll 2
+  for (int cb = 0; cb < T / 16; ++cb) {
+    if (diag && 16 * cb + 15 <= 32 * w) continue;  // wholly below the diagonal
+    u32x4 bq[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bq[ks] = *(const u32x4*)&Bs[(cb * 16 + l16) * LDL + ks * 32 + koff];
+    v4f32 accR[2], accI[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      accR[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
+      accI[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const bf16x8 b = as_bf16x8(bq[ks]);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        accR[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(aU[rb][ks]), b, accR[rb], 0, 0, 0);
+        accI[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(aV[rb][ks]), b, accI[rb], 0, 0, 0);
+      }
+    }
+    uint32_t m[8];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float re = accR[rb][v], im = accI[rb][v];
+        m[rb * 4 + v] = __float_as_uint(fmaf(re, re, im * im));
+      }
+    if (diag) {
+      // output (row 4 (lane/16) + v of MFMA block rb, column lane % 16): keep column > row
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = w * 32 + rb * 16 + 4 * (lane >> 4) + v;
+          const int j = cb * 16 + l16;
+          if (i >= j) m[rb * 4 + v] = 0u;
+        }
+    }
+    best = max3u(best, m[0], m[1]);
+    best = max3u(best, m[2], m[3]);
+    best = max3u(best, m[4], m[5]);
+    best = max3u(best, m[6], m[7]);
+  }
+
+  best = wave_max_u32(best);
+  if (lane == 0) red[w] = best;
+  __syncthreads();
+  if (tid == 0) {
+    const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
+    if (a.tile_max) a.tile_max[(size_t)slot * tiles + tile] = mx;
+    atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
+  }
+}
+
+// General K: chunks of 128 bf16 through LDS, each wave a 64 x 64 quadrant.
+constexpr int KCB = 128;
+constexpr int LDB = KCB + 8;
+
+__global__ __launch_bounds__(256) void k_gram_bf16_chunked(GramArgs a) {
+  if (a.flags && (*a.flags & kFlagDone)) return;
+  const int tiles = a.nt * (a.nt + 1) / 2;
+  int slot, tile;
+  if (!xcd_slot(a, tiles, slot, tile)) return;
+  int bi, bj;
+  tile_decode(tile, a.nt, bi, bj);
 
   __shared__ __attribute__((aligned(16))) uint16_t As[T * LDB];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[T * LDB];
@@ -59,10 +200,9 @@ __global__ __launch_bounds__(256) void k_gram_bf16(GramArgs a) {
       accI[r][c] = v4f32{0.f, 0.f, 0.f, 0.f};
     }
 
-  const int K = a.ldk;  // padded with zeros beyond 2d
+  const int K = a.ldk;
   for (int k0 = 0; k0 < K; k0 += KCB) {
     __syncthreads();
-    // T columns x KCB bf16 per side = 2048 chunks of 16 bytes per side
 #pragma unroll
     for (int it = 0; it < (T * KCB / 8) / 256; ++it) {
       const int idx = it * 256 + tid;
@@ -84,22 +224,21 @@ __global__ __launch_bounds__(256) void k_gram_bf16(GramArgs a) {
       const int ksteps = (rem + 31) / 32;
       const int koff = 8 * (lane >> 4);
       for (int kk = 0; kk < ksteps; ++kk) {
-        bf16x8 av[4];
-        u32x4 bu[4];
+        u32x4 au[4];
+        bf16x8 bb[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          av[r] = __builtin_bit_cast(bf16x8, *(const u32x4*)&As[(wr * 64 + r * 16 + (lane & 15)) * LDB + kk * 32 + koff]);
+        for (int r = 0; r < 4; ++r) au[r] = *(const u32x4*)&As[(wr * 64 + r * 16 + (lane & 15)) * LDB + kk * 32 + koff];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          bu[c] = *(const u32x4*)&Bs[(wc * 64 + c * 16 + (lane & 15)) * LDB + kk * 32 + koff];
+          bb[c] = as_bf16x8(*(const u32x4*)&Bs[(wc * 64 + c * 16 + (lane & 15)) * LDB + kk * 32 + koff]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const bf16x8 bU = __builtin_bit_cast(bf16x8, bu[c]);
-          const bf16x8 bV = __builtin_bit_cast(bf16x8, swap_negate(bu[c]));
+        for (int r = 0; r < 4; ++r) {
+          const bf16x8 aU = as_bf16x8(au[r]);
+          const bf16x8 aV = as_bf16x8(swap_negate(au[r]));
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            accR[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bU, accR[r][c], 0, 0, 0);
-            accI[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bV, accI[r][c], 0, 0, 0);
+          for (int c = 0; c < 4; ++c) {
+            accR[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aU, bb[c], accR[r][c], 0, 0, 0);
+            accI[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aV, bb[c], accI[r][c], 0, 0, 0);
           }
         }
       }
@@ -108,7 +247,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(GramArgs a) {
 
   uint32_t best = 0;
   if (!skip) {
-    const bool interior = (bi < bj) && ((bj + 1) * T <= a.n);
+    const bool diag = bi == bj;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -116,34 +255,52 @@ __global__ __launch_bounds__(256) void k_gram_bf16(GramArgs a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float re = accR[r][c][v], im = accI[r][c][v];
-          const float m = re * re + im * im;
-          const uint32_t mb = __float_as_uint(m);
-          bool ok = true;
-          if (!interior) {
-            const int i = bi * T + wr * 64 + r * 16 + 4 * (lane >> 4) + v;
-            const int j = bj * T + wc * 64 + c * 16 + (lane & 15);
-            ok = i < j && j < a.n;
+          uint32_t mb = __float_as_uint(fmaf(re, re, im * im));
+          if (diag) {
+            const int i = wr * 64 + r * 16 + 4 * (lane >> 4) + v;
+            const int j = wc * 64 + c * 16 + (lane & 15);
+            if (i >= j) mb = 0u;
           }
-          if (ok && mb > best) best = mb;
+          best = mb > best ? mb : best;
         }
   }
   best = wave_max_u32(best);
   if (lane == 0) red[w] = best;
   __syncthreads();
   if (tid == 0) {
-    uint32_t m = red[0];
-    for (int q = 1; q < 4; ++q) m = red[q] > m ? red[q] : m;
-    if (a.tile_max) a.tile_max[(size_t)slot * gridDim.x + blockIdx.x] = m;
-    atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)m);
+    const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
+    if (a.tile_max) a.tile_max[(size_t)slot * tiles + tile] = mx;
+    atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
   }
+}
+
+template <int KS>
+hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_bf16<KS>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s) {
-  const int tiles = a.nt * (a.nt + 1) / 2;
-  hipLaunchKernelGGL(k_gram_bf16, dim3(tiles, slots), dim3(256), 0, s, a);
-  return hipGetLastError();
+hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
+  GramArgs a = a_in;
+  a.slots = slots;
+  const long tiles = (long)a.nt * (a.nt + 1) / 2;
+  const long grid = tiles * ((slots + 7) / 8) * 8;
+  const int ks = a.ldk / 32;
+  switch (a.ldk % 32 == 0 ? ks : 0) {
+    case 1: return launch_ks<1>(a, (int)grid, s);
+    case 2: return launch_ks<2>(a, (int)grid, s);
+    case 3: return launch_ks<3>(a, (int)grid, s);
+    case 4: return launch_ks<4>(a, (int)grid, s);
+    case 5: return launch_ks<5>(a, (int)grid, s);
+    case 6: return launch_ks<6>(a, (int)grid, s);
+    case 7: return launch_ks<7>(a, (int)grid, s);
+    case 8: return launch_ks<8>(a, (int)grid, s);
+    default:
+      hipLaunchKernelGGL(k_gram_bf16_chunked, dim3((int)grid), dim3(256), 0, s, a);
+      return hipGetLastError();
+  }
 }
 
 }  // namespace trstmi

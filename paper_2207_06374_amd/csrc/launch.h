@@ -53,6 +53,7 @@ struct GramArgs {
   int32_t n;
   int32_t d;
   int32_t nt;                // tiles per side
+  int32_t slots;             // candidates in this launch (set by the launcher)
   uint64_t* cand_max;        // [slot] running max (bits of the float type)
   const int32_t* flags;      // DONE gate (null: always run)
   uint32_t* tile_max;        // screen: [slot][ntiles] max bits per tile (null: not kept)
