@@ -80,7 +80,7 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
     t1 = time.perf_counter()
     lib.timing_enable(False)
     kernels = {}
-    for name in ("perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck", "gram_recheck",
+    for name in ("perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck", "recheck",
                  "select", "commit"):
         ms, cnt = lib.timing_read(name)
         if cnt:

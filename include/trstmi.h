@@ -62,7 +62,8 @@ enum {
   TRSTMI_MODE_FP32 = 1,        /* candidates rounded to FP32, Gram in FP32 (MFMA) */
   TRSTMI_MODE_BF16_SCREEN = 2  /* all candidates screened from BF16 inputs (MFMA, FP32
                                   accumulate); the recheck_topk best screened ones are
-                                  re-evaluated exactly in FP64 and only FP64 values decide */
+                                  re-evaluated exactly in FP64 and only FP64 values decide.
+                                  Steps in this mode need d <= 128 (else E_UNSUPPORTED). */
 };
 
 /* Bits of *state.flags. */
@@ -206,7 +207,7 @@ trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, vo
  * the recorded events and returns, for one kernel name, the summed elapsed
  * milliseconds and the number of timed launches since the last reset.  Names:
  * "perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck",
- * "gram_recheck", "select", "commit".
+ * "recheck", "select", "commit".
  */
 trstmi_status trstmi_timing_enable(int32_t on);
 trstmi_status trstmi_timing_reset(void);

@@ -148,7 +148,7 @@ size_t elem_of_mode(int32_t mode) { return mode == TRSTMI_MODE_FP64 ? 8 : (mode 
 struct Layout {
   int64_t n, d;
   int32_t C, k, ld, ldc;  // ld: FP64/FP32 buffers; ldc: the mode's candidate buffer
-  size_t cand, cand_max, dec, tile_max, rechecked, thr, recheck, recheck_max, total;
+  size_t cand, cand_max, dec, tile_max, rechecked, thr, recheck, recheck_max, list, list_count, total;
 };
 
 Layout layout_of(const trstmi_params* p) {
@@ -177,6 +177,10 @@ Layout layout_of(const trstmi_params* p) {
     off = align256(off + (size_t)L.k * L.n * L.ld * 8);
     L.recheck_max = off;
     off = align256(off + (size_t)L.k * 8);
+    L.list = off;
+    off = align256(off + (size_t)L.k * ntiles_of(L.n, kTileBF16) * 8);
+    L.list_count = off;
+    off = align256(off + 8);
   }
   L.total = off;
   return L;
@@ -205,6 +209,8 @@ trstmi_status check_params(const trstmi_params* p) {
   if (p->mode == TRSTMI_MODE_BF16_SCREEN &&
       (p->recheck_topk < 1 || p->recheck_topk > p->candidates || p->recheck_topk > TRSTMI_MAX_TOPK))
     return fail(TRSTMI_E_INVALID_ARG, "recheck_topk must be in [1, min(candidates, 64)]");
+  if (p->mode == TRSTMI_MODE_BF16_SCREEN && p->d > 128)
+    return fail(TRSTMI_E_UNSUPPORTED, "the BF16 screen form supports d <= 128");
   if (p->seed >> 32 || p->stream_id >> 32) return fail(TRSTMI_E_INVALID_ARG, "seed and stream_id must be < 2^32");
   const bool ok_r = std::isfinite(p->radius0) && std::isfinite(p->radius_min) && std::isfinite(p->radius_max) &&
                     p->radius_min > 0 && p->radius_min <= p->radius0 && p->radius0 <= p->radius_max;
@@ -344,6 +350,11 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
     ta.dec = dec;
     ta.rep_cand_mu = rep ? rep->cand_mu : nullptr;
     ta.rep_rechecked = rep ? rep->rechecked : nullptr;
+    ta.tile_max = tile_max;
+    ta.screen_nt = nt_of(L.n, kTileBF16);
+    ta.list = (int2*)(ws + L.list);
+    ta.list_count = (int32_t*)(ws + L.list_count);
+    ta.list_cap = (int32_t)(L.k * ntiles_of(L.n, kTileBF16));
     TRY_HIP(TIMED("topk", s, launch_topk(ta, s)), "topk");
 
     PerturbArgs pr = pa;
@@ -355,13 +366,25 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
     pr.zero_max = recheck_max;
     TRY_HIP(TIMED("perturb_recheck", s, launch_perturb(pr, L.k, s)), "perturb_recheck");
 
-    GramArgs g64 = gram_base(L.n, L.d, ws + L.recheck, slot_stride64, L.ld, kTileF64, recheck_max, st->flags);
-    g64.screen_tile_max = tile_max;
-    g64.slot_cand = rechecked;
-    g64.thr = thr;
-    g64.screen_ratio = kTileBF16 / kTileF64;
-    g64.screen_nt = nt_of(L.n, kTileBF16);
-    TRY_HIP(TIMED("gram_recheck", s, launch_gram_f64(g64, L.k, s)), "gram_recheck");
+    RecheckArgs ra{};
+    ra.screen = (const uint16_t*)(ws + L.cand);
+    ra.screen_stride = slot_stride;
+    ra.ldk16 = L.ldc;
+    ra.cand64 = (const double*)(ws + L.recheck);
+    ra.stride64 = slot_stride64;
+    ra.ld64 = L.ld;
+    ra.n = (int32_t)L.n;
+    ra.d = (int32_t)L.d;
+    ra.nt = nt_of(L.n, kTileBF16);
+    ra.k = L.k;
+    ra.list = (const int2*)(ws + L.list);
+    ra.count = (const int32_t*)(ws + L.list_count);
+    ra.list_cap = ta.list_cap;
+    ra.rechecked = rechecked;
+    ra.thr = thr;
+    ra.recheck_max = recheck_max;
+    ra.flags = st->flags;
+    TRY_HIP(TIMED("recheck", s, launch_recheck_pairs(ra, s)), "recheck");
 
     sa.cand_max = recheck_max;
     sa.count = L.k;

@@ -29,6 +29,10 @@
 // Each block writes its tile maximum (used to prune the FP64 recheck) and
 // updates the candidate's running maximum with one atomic.
 //
+// The FP64 recheck of the best screened candidates (k_recheck_pairs) reuses
+// the same tile code on the tiles that can hold the exact maximum and
+// evaluates only the pairs that can attain it in FP64.
+//
 // Fallback kernel (2d > 256): 128 x 128 tile, K looped in LDS chunks of 128.
 
 #include "device_common.h"
@@ -62,6 +66,78 @@ __device__ __forceinline__ bool xcd_slot(const GramArgs& a, int tiles, int& slot
   return slot < a.slots;
 }
 
+// The 32 rows of wave w (u for Re, v for -Im, whole K) in registers.
+template <int KS>
+struct ARows {
+  u32x4 u[2][KS];
+  u32x4 v[2][KS];
+};
+
+// Stage the 128 B columns of tile column block bj into LDS and load this
+// wave's A rows of tile row block bi.  The caller synchronises.
+template <int KS>
+__device__ __forceinline__ void load_tile(const uint16_t* base, int ldk, int n, int bi, int bj, uint16_t* Bs,
+                                          ARows<KS>& A) {
+  constexpr int LDL = 32 * KS + 8;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+#pragma unroll
+  for (int it = 0; it < (T * KS * 4) / 256; ++it) {
+    const int idx = it * 256 + tid;
+    const int col = idx / (KS * 4);
+    const int ch = idx % (KS * 4);
+    const int cj = bj * T + col;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (cj < n) v = *(const u32x4*)(base + (size_t)cj * ldk + ch * 8);
+    *(u32x4*)&Bs[col * LDL + ch * 8] = v;
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    const int row = bi * T + w * 32 + rb * 16 + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (row < n) v = *(const u32x4*)(base + (size_t)row * ldk + ks * 32 + 8 * (lane >> 4));
+      A.u[rb][ks] = v;
+      A.v[rb][ks] = swap_negate(v);
+    }
+  }
+}
+
+// |G|^2 (float bits) of the 2 x 4 outputs this lane holds for column block cb:
+// m[rb * 4 + v] is tile row 32 w + 16 rb + 4 (lane / 16) + v, tile column 16 cb + lane % 16.
+template <int KS>
+__device__ __forceinline__ void colblock(const ARows<KS>& A, const uint16_t* Bs, int cb, uint32_t m[8]) {
+  constexpr int LDL = 32 * KS + 8;
+  const int lane = threadIdx.x & 63;
+  u32x4 bq[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) bq[ks] = *(const u32x4*)&Bs[(cb * 16 + (lane & 15)) * LDL + ks * 32 + 8 * (lane >> 4)];
+  v4f32 accR[2], accI[2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    accR[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
+    accI[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const bf16x8 b = as_bf16x8(bq[ks]);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      accR[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.u[rb][ks]), b, accR[rb], 0, 0, 0);
+      accI[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][ks]), b, accI[rb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float re = accR[rb][v], im = accI[rb][v];
+      m[rb * 4 + v] = __float_as_uint(fmaf(re, re, im * im));
+    }
+}
+
 template <int KS>
 __global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
   if (a.flags && (*a.flags & kFlagDone)) return;
@@ -71,43 +147,15 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
   int bi, bj;
   tile_decode(tile, a.nt, bi, bj);
 
-  constexpr int KP = 32 * KS;   // bf16 per column
-  constexpr int LDL = KP + 8;   // LDS column stride (bf16)
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * LDL];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * (32 * KS + 8)];
   __shared__ uint32_t red[4];
-
   const uint16_t* base = (const uint16_t*)a.cand + (size_t)slot * a.slot_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
-  const int l16 = lane & 15;
-  const int koff = 8 * (lane >> 4);
 
-  // B columns of the tile -> LDS
-#pragma unroll
-  for (int it = 0; it < (T * KS * 4) / 256; ++it) {
-    const int idx = it * 256 + tid;
-    const int col = idx / (KS * 4);
-    const int ch = idx % (KS * 4);
-    const int cj = bj * T + col;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (cj < a.n) v = *(const u32x4*)(base + (size_t)cj * a.ldk + ch * 8);
-    *(u32x4*)&Bs[col * LDL + ch * 8] = v;
-  }
-
-  // this wave's 32 rows, u and v, whole K, in registers
-  u32x4 aU[2][KS], aV[2][KS];
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
-    const int row = bi * T + w * 32 + rb * 16 + l16;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (row < a.n) v = *(const u32x4*)(base + (size_t)row * a.ldk + ks * 32 + koff);
-      aU[rb][ks] = v;
-      aV[rb][ks] = swap_negate(v);
-    }
-  }
+  ARows<KS> A;
+  load_tile<KS>(base, a.ldk, a.n, bi, bj, Bs, A);
   __syncthreads();
 
   const bool diag = bi == bj;
@@ -115,42 +163,15 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
 #pragma unroll 2
   for (int cb = 0; cb < T / 16; ++cb) {
     if (diag && 16 * cb + 15 <= 32 * w) continue;  // wholly below the diagonal
-    u32x4 bq[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) bq[ks] = *(const u32x4*)&Bs[(cb * 16 + l16) * LDL + ks * 32 + koff];
-    v4f32 accR[2], accI[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      accR[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
-      accI[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const bf16x8 b = as_bf16x8(bq[ks]);
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        accR[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(aU[rb][ks]), b, accR[rb], 0, 0, 0);
-        accI[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(aV[rb][ks]), b, accI[rb], 0, 0, 0);
-      }
-    }
     uint32_t m[8];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float re = accR[rb][v], im = accI[rb][v];
-        m[rb * 4 + v] = __float_as_uint(fmaf(re, re, im * im));
-      }
+    colblock<KS>(A, Bs, cb, m);
     if (diag) {
-      // output (row 4 (lane/16) + v of MFMA block rb, column lane % 16): keep column > row
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = w * 32 + rb * 16 + 4 * (lane >> 4) + v;
-          const int j = cb * 16 + l16;
-          if (i >= j) m[rb * 4 + v] = 0u;
-        }
+      for (int q = 0; q < 8; ++q) {
+        const int i = w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
+        const int j = cb * 16 + (lane & 15);
+        if (i >= j) m[q] = 0u;
+      }
     }
     best = max3u(best, m[0], m[1]);
     best = max3u(best, m[2], m[3]);
@@ -165,6 +186,74 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
     const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
     if (a.tile_max) a.tile_max[(size_t)slot * tiles + tile] = mx;
     atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
+  }
+}
+
+// Exact FP64 |<phi_j, phi_k>|^2 from the FP64 candidate (column stride ld).
+__device__ __forceinline__ uint64_t pair_f64(const double* c64, int ld, int d, int j, int k) {
+  const double2* x = (const double2*)(c64 + (size_t)j * ld);
+  const double2* y = (const double2*)(c64 + (size_t)k * ld);
+  double re = 0.0, im = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const double2 p = x[i], q = y[i];
+    re += p.x * q.x + p.y * q.y;
+    im += p.x * q.y - p.y * q.x;
+  }
+  return (uint64_t)__double_as_longlong(re * re + im * im);
+}
+
+// Pair-level FP64 recheck.  For a rechecked candidate with screened maximum s
+// and certified screen error eps, the exact maximiser has screened value
+// >= s - 2 eps = thr (its exact value is >= the exact value at the screened
+// maximiser >= s - eps).  Each listed screen tile is screened again (any
+// screen within eps of the exact values serves) and every pair whose screened
+// value reaches thr is evaluated exactly in FP64 from the FP64 candidate.
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_recheck_pairs(RecheckArgs a) {
+  if (*a.flags & kFlagDone) return;
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * (32 * KS + 8)];
+  __shared__ uint64_t red[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  if (blockIdx.x == 0 && tid < a.k && !(a.thr[tid] > -__builtin_inf()))
+    atomicMax((unsigned long long*)&a.recheck_max[tid], ~0ull);  // invalid candidate
+  const int count = *a.count;
+  for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    const int2 item = a.list[e];
+    const int slot = item.x;
+    int bi, bj;
+    tile_decode(item.y, a.nt, bi, bj);
+    const double thr = a.thr[slot];
+    const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
+    const uint16_t* base = a.screen + (size_t)a.rechecked[slot] * a.screen_stride;
+    const double* c64 = a.cand64 + (size_t)slot * a.stride64;
+    ARows<KS> A;
+    load_tile<KS>(base, a.ldk16, a.n, bi, bj, Bs, A);
+    __syncthreads();
+    uint64_t best = 0;
+    for (int cb = 0; cb < T / 16; ++cb) {
+      uint32_t m[8];
+      colblock<KS>(A, Bs, cb, m);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = bi * T + w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
+        const int j = bj * T + cb * 16 + (lane & 15);
+        if (i < j && j < a.n && !(__uint_as_float(m[q]) < thr_sq)) {
+          const uint64_t mb = pair_f64(c64, a.ld64, a.d, i, j);
+          best = mb > best ? mb : best;
+        }
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) red[w] = best;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t mx = red[0];
+      for (int q = 1; q < 4; ++q) mx = red[q] > mx ? red[q] : mx;
+      if (mx) atomicMax((unsigned long long*)&a.recheck_max[slot], (unsigned long long)mx);
+    }
+    __syncthreads();
   }
 }
 
@@ -275,6 +364,12 @@ __global__ __launch_bounds__(256) void k_gram_bf16_chunked(GramArgs a) {
 }
 
 template <int KS>
+hipError_t launch_rp(const RecheckArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_recheck_pairs<KS>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int KS>
 hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_bf16<KS>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
@@ -300,6 +395,21 @@ hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
     default:
       hipLaunchKernelGGL(k_gram_bf16_chunked, dim3((int)grid), dim3(256), 0, s, a);
       return hipGetLastError();
+  }
+}
+
+hipError_t launch_recheck_pairs(const RecheckArgs& a, hipStream_t s) {
+  const int grid = a.list_cap < 1024 ? a.list_cap : 1024;
+  switch (a.ldk16 / 32) {
+    case 1: return launch_rp<1>(a, grid, s);
+    case 2: return launch_rp<2>(a, grid, s);
+    case 3: return launch_rp<3>(a, grid, s);
+    case 4: return launch_rp<4>(a, grid, s);
+    case 5: return launch_rp<5>(a, grid, s);
+    case 6: return launch_rp<6>(a, grid, s);
+    case 7: return launch_rp<7>(a, grid, s);
+    case 8: return launch_rp<8>(a, grid, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -32,27 +32,8 @@ constexpr int T = kTileF64;
 constexpr int KC = 32;
 constexpr int LDA = KC + 1;
 
-__global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
-  if (a.flags && (*a.flags & kFlagDone)) return;
-  const int slot = blockIdx.y;
-  int bi, bj;
-  tile_decode(blockIdx.x, a.nt, bi, bj);
-
-  if (a.thr) {
-    // certified pruning: this tile can only hold the FP64 maximum if the
-    // screened maximum of the screen tile containing it is >= thr
-    const int c = a.slot_cand[slot];
-    const int sbi = bi / a.screen_ratio, sbj = bj / a.screen_ratio;
-    const int sn = a.screen_nt * (a.screen_nt + 1) / 2;
-    const uint32_t mb = a.screen_tile_max[(size_t)c * sn + tile_linear(sbi, sbj, a.screen_nt)];
-    const double m = sqrt((double)__uint_as_float(mb));
-    if (m < a.thr[slot]) return;  // NaN compares false: kept
-  }
-
-  __shared__ double As[T * LDA];
-  __shared__ double Bs[T * LDA];
-  __shared__ uint64_t red[4];
-
+__device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int bi, int bj, double* As, double* Bs,
+                                              uint64_t* red) {
   const double* base = (const double*)a.cand + (size_t)slot * a.slot_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -142,6 +123,16 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
     for (int q = 1; q < 4; ++q) m = red[q] > m ? red[q] : m;
     atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)m);
   }
+}
+
+__global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
+  if (a.flags && (*a.flags & kFlagDone)) return;
+  __shared__ double As[T * LDA];
+  __shared__ double Bs[T * LDA];
+  __shared__ uint64_t red[4];
+  int bi, bj;
+  tile_decode(blockIdx.x, a.nt, bi, bj);
+  gram_f64_tile(a, blockIdx.y, bi, bj, As, Bs, red);
 }
 
 }  // namespace

@@ -57,12 +57,6 @@ struct GramArgs {
   uint64_t* cand_max;        // [slot] running max (bits of the float type)
   const int32_t* flags;      // DONE gate (null: always run)
   uint32_t* tile_max;        // screen: [slot][ntiles] max bits per tile (null: not kept)
-  // certified pruning of the FP64 recheck (all null/0 when off)
-  const uint32_t* screen_tile_max;  // [candidate][screen ntiles] float bits
-  const int32_t* slot_cand;         // slot -> candidate index
-  const double* thr;                // per slot: skip tiles whose screened max < thr
-  int32_t screen_ratio;             // screen tile edge / this kernel's tile edge
-  int32_t screen_nt;                // screen tiles per side
 };
 
 struct SelectArgs {
@@ -96,6 +90,31 @@ struct TopkArgs {
   Decision* dec;
   double* rep_cand_mu;       // [C] screened mu (null: not written)
   int32_t* rep_rechecked;    // [k]
+  // certified pruning of the FP64 recheck: screen tile maxima in, list of
+  // screen tiles that may hold a rechecked candidate's exact maximum out
+  const uint32_t* tile_max;  // [C][screen tiles] float bits of max |G|^2
+  int32_t screen_nt;         // screen tiles per side
+  int2* list;                // out: (slot, screen tile) items
+  int32_t* list_count;       // out
+  int32_t list_cap;
+};
+
+// Pair-level FP64 recheck over the listed screen tiles.
+struct RecheckArgs {
+  const uint16_t* screen;    // BF16 candidates, indexed by candidate
+  int64_t screen_stride;     // elements per candidate
+  int32_t ldk16;             // BF16 column stride (multiple of 32, <= 256)
+  const double* cand64;      // FP64 candidates of the rechecked slots
+  int64_t stride64;          // doubles per slot
+  int32_t ld64;              // FP64 column stride (doubles)
+  int32_t n, d, nt, k;       // nt: screen tiles per side; k: rechecked slots
+  const int2* list;          // (slot, screen tile)
+  const int32_t* count;
+  int32_t list_cap;
+  const int32_t* rechecked;  // slot -> candidate
+  const double* thr;         // slot -> screened max - 2 eps (-inf: invalid candidate)
+  uint64_t* recheck_max;     // [k] FP64 max |G|^2 bits (zeroed before)
+  const int32_t* flags;
 };
 
 struct InitFinishArgs {
@@ -117,6 +136,7 @@ hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
+hipError_t launch_recheck_pairs(const RecheckArgs& a, hipStream_t s);
 hipError_t launch_init_finish(const InitFinishArgs& a, hipStream_t s);
 hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,
                               uint64_t* zero_max, hipStream_t s);

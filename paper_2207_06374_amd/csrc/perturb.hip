@@ -22,7 +22,7 @@ namespace trstmi {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxQ = 4;  // blocks per lane: d <= 2 * 64 * kMaxQ = 512
+constexpr int kMaxQ = 4;  // blocks per lane: d <= 2 * 64 * kMaxQ = 512 (Q below is the compiled bound)
 
 __device__ __forceinline__ void store_pair(const PerturbArgs& a, size_t slot, int64_t col, int i,
                                            double re0, double im0, double re1, double im1, bool two) {
@@ -60,7 +60,7 @@ __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot
   }
 }
 
-template <int LPC>
+template <int LPC, int Q>
 __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   if (a.gate && ((*a.gate & a.gate_mask) != a.gate_want)) return;
   const int slot = blockIdx.y;
@@ -83,10 +83,10 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
        col0 += (int64_t)gridDim.x * kColsPerIter) {
     const int64_t col = col0 + wave * kColsPerWave + lane / LPC;
     const bool active = col < a.n;  // whole LPC groups share `active`
-    double y[kMaxQ][4];
+    double y[Q][4];
     double nrm2 = 0.0;
 #pragma unroll
-    for (int qi = 0; qi < kMaxQ; ++qi) {
+    for (int qi = 0; qi < Q; ++qi) {
       const int q = lq + qi * LPC;
       y[qi][0] = y[qi][1] = y[qi][2] = y[qi][3] = 0.0;
       if (!active || q >= nb) continue;
@@ -148,16 +148,16 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
     if (!active) continue;
     const double nrm = sqrt(nrm2);
     const bool bad = !(nrm > 0.0 && nrm < __builtin_inf());
-    const double qnan = __builtin_nan("");
+    const double inv = bad ? __builtin_nan("") : 1.0 / nrm;  // one IEEE division per column and lane
 #pragma unroll
-    for (int qi = 0; qi < kMaxQ; ++qi) {
+    for (int qi = 0; qi < Q; ++qi) {
       const int q = lq + qi * LPC;
       if (q >= nb) continue;
       const int i0 = 2 * q;
       const bool two = (i0 + 1) < d;
       double o[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) o[e] = bad ? qnan : y[qi][e] / nrm;
+      for (int e = 0; e < 4; ++e) o[e] = y[qi][e] * inv;
       store_pair(a, slot, col, i0, o[0], o[1], o[2], o[3], two);
       if (q == nb - 1 && a.out_ld > 2 * d) store_zero_pad(a, slot, col);
     }
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_convert_f32(const double* frame, i
   }
 }
 
-template <int LPC>
+template <int LPC, int Q>
 hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
   int64_t groups = (a.n + kColsPerIter - 1) / kColsPerIter;
@@ -184,7 +184,7 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   int64_t want = (8192 + slots - 1) / slots;
   if (want < 1) want = 1;
   const int gx = (int)(groups < want ? groups : want);
-  hipLaunchKernelGGL(k_perturb<LPC>, dim3(gx, slots), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_perturb<LPC, Q>), dim3(gx, slots), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -192,13 +192,15 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
   const int nb = (a.d + 1) / 2;
-  if (nb <= 1) return launch_lpc<1>(a, slots, s);
-  if (nb <= 2) return launch_lpc<2>(a, slots, s);
-  if (nb <= 4) return launch_lpc<4>(a, slots, s);
-  if (nb <= 8) return launch_lpc<8>(a, slots, s);
-  if (nb <= 16) return launch_lpc<16>(a, slots, s);
-  if (nb <= 32) return launch_lpc<32>(a, slots, s);
-  return launch_lpc<64>(a, slots, s);
+  if (nb <= 1) return launch_lpc<1, 1>(a, slots, s);
+  if (nb <= 2) return launch_lpc<2, 1>(a, slots, s);
+  if (nb <= 4) return launch_lpc<4, 1>(a, slots, s);
+  if (nb <= 8) return launch_lpc<8, 1>(a, slots, s);
+  if (nb <= 16) return launch_lpc<16, 1>(a, slots, s);
+  if (nb <= 32) return launch_lpc<32, 1>(a, slots, s);
+  if (nb <= 64) return launch_lpc<64, 1>(a, slots, s);
+  if (nb <= 128) return launch_lpc<64, 2>(a, slots, s);
+  return launch_lpc<64, kMaxQ>(a, slots, s);
 }
 
 hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,

@@ -113,6 +113,9 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
   __shared__ double sv[kThreads];
   __shared__ int sc[kThreads];
   __shared__ uint32_t taken[kBitmapWords];
+  __shared__ int sel_c[64];
+  __shared__ double sel_thr[64];
+  __shared__ int list_n;
   const int tid = threadIdx.x;
   if (*a.flags & kFlagDone) return;
   for (int q = tid; q < kBitmapWords; q += kThreads) taken[q] = 0;
@@ -153,6 +156,8 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
         a.rechecked[round] = c;
         // an invalid (non-finite) screened value disables pruning for that candidate
         a.thr[round] = v < __builtin_inf() ? v - 2.0 * a.eps : -__builtin_inf();
+        sel_c[round] = c;
+        sel_thr[round] = a.thr[round];
         if (a.rep_rechecked) a.rep_rechecked[round] = c;
       }
       prev = v;
@@ -162,6 +167,39 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
     __syncthreads();
   }
   if (tid == 0 && a.k >= a.C) a.dec->screen_near = 0;
+
+  // Certified pruning.  For every pair |screened - exact| <= eps, so a screen
+  // tile whose screened maximum is below (candidate's screened max - 2 eps)
+  // cannot hold the candidate's exact maximum.  List the remaining screen
+  // tiles of every rechecked candidate (an invalid candidate needs none: its
+  // FP64 value is invalid as well).  Appends are aggregated per wavefront.
+  if (tid == 0) list_n = 0;
+  __syncthreads();
+  const int sn = a.screen_nt * (a.screen_nt + 1) / 2;
+  const int lane = tid & 63;
+  for (int e0 = 0; e0 < a.k * sn; e0 += kThreads) {
+    const int e = e0 + tid;
+    bool keep = false;
+    int slot = 0, st = 0;
+    if (e < a.k * sn) {
+      slot = e / sn;
+      st = e - slot * sn;
+      if (sel_thr[slot] > -__builtin_inf()) {
+        const double m = sqrt((double)__uint_as_float(a.tile_max[(size_t)sel_c[slot] * sn + st]));
+        keep = !(m < sel_thr[slot]);
+      }
+    }
+    const uint64_t ballot = __ballot(keep);
+    int base = 0;
+    if (lane == 0 && ballot) base = atomicAdd(&list_n, __popcll(ballot));
+    base = __shfl(base, 0, 64);
+    if (keep) {
+      const int pos = base + __popcll(ballot & ((1ull << lane) - 1));
+      if (pos < a.list_cap) a.list[pos] = make_int2(slot, st);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) *a.list_count = list_n < a.list_cap ? list_n : a.list_cap;
 }
 
 __global__ void k_init_finish(InitFinishArgs a) {
