@@ -168,7 +168,7 @@ Layout layout_of(const trstmi_params* p) {
   off = align256(off + sizeof(Decision));
   if (p->mode == TRSTMI_MODE_BF16_SCREEN) {
     L.tile_max = off;
-    off = align256(off + (size_t)L.C * ntiles_of(L.n, kTileBF16) * 4);
+    off = align256(off + (size_t)L.C * ntiles_of(L.n, kTileBF16) * 16);  // 4 waves per tile
     L.rechecked = off;
     off = align256(off + (size_t)L.k * 4);
     L.thr = off;

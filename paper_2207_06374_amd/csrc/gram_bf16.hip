@@ -6,34 +6,39 @@
 // zero padded.  A complex column is the real 2d-vector u = (a_0, b_0, ...);
 // with v = (b_0, -a_0, b_1, -a_1, ...):
 //   Re <phi_j, phi_k> = u_j . u_k,   Im <phi_j, phi_k> = -(v_j . u_k),
-// so both parts share the B operand u_k, and v_j is built once per tile from
-// the A rows held in registers (one funnel shift and one sign flip per 32-bit
-// (re, im) pair).
+// so both parts share the B operand u_k, and v_j is formed in registers from
+// the A rows (one funnel shift and one sign flip per 32-bit (re, im) pair).
 //
-// Main kernel (2d <= 256): a 256-thread block owns a 128 x 128 tile of the
-// strict upper triangle.  Each wave keeps its 32 rows (A = u and v for the
-// whole K) in VGPRs, loaded straight from global memory; the 128 B columns
-// are staged once in LDS (16 bytes of padding per column: 16 lanes reading 16
-// columns at one k offset hit distinct banks).  The wave then sweeps the 8
-// column blocks of 16: 2 x 2 x K/32 MFMAs per block, then |G|^2 = Re^2 + Im^2
-// and a running max on the float bit patterns (integer max keeps NaN, which
-// marks an invalid candidate, above every finite value).  Only diagonal tiles
-// mask (j > i); rows/columns past N are zero and contribute 0.  On a diagonal
-// tile a wave skips the column blocks lying wholly below the diagonal.
+// Main kernel (2d <= 256): a 256-thread block owns a row segment: tile row
+// block bi (128 frame columns) against up to kSeg consecutive tile column
+// blocks bj >= bi of the strict upper triangle.  Each wave keeps its 32 rows
+// (u and v for the whole K) in VGPRs for the whole segment, so the A side is
+// read and converted once per segment.  The 128 B columns of one tile sit in
+// LDS (16 bytes of padding per column: 16 lanes reading 16 columns at one k
+// offset hit distinct banks); the next tile's columns are prefetched into
+// registers while the current tile is computed.  Per tile, the wave sweeps 8
+// column blocks of 16 columns: 2 x 2 x K/32 MFMAs per block, then
+// |G|^2 = Re^2 + Im^2 and a running max on the float bit patterns (integer
+// max keeps NaN, which marks an invalid candidate, above every finite
+// value).  Off-diagonal tiles run a straight-line loop that issues the MFMAs
+// of the next column block before the epilogue of the current one, so matrix
+// and vector work of one wave overlap.  Diagonal tiles skip the column blocks
+// wholly below the diagonal and keep j > i; rows/columns past N are zero and
+// contribute 0.
 //
 // Blocks are mapped XCD-aware: the dispatcher deals consecutive block ids to
-// the 8 XCDs in turn, so block b runs on XCD b mod 8; all tiles of candidate
-// c are given to blocks with b mod 8 = c mod 8, which keeps a candidate's
+// the 8 XCDs in turn, so block b runs on XCD b mod 8; all segments of
+// candidate c go to blocks with b mod 8 = c mod 8, which keeps a candidate's
 // columns in one XCD's L2.
 //
-// Each block writes its tile maximum (used to prune the FP64 recheck) and
-// updates the candidate's running maximum with one atomic.
-//
-// The FP64 recheck of the best screened candidates (k_recheck_pairs) reuses
-// the same tile code on the tiles that can hold the exact maximum and
+// Each wave writes its maximum for every tile (used to prune the FP64
+// recheck) and the block updates the candidate's running maximum with one
+// atomic.  The FP64 recheck of the best screened candidates (k_recheck_pairs)
+// reuses the per-tile code on the tiles that can hold the exact maximum and
 // evaluates only the pairs that can attain it in FP64.
 //
-// Fallback kernel (2d > 256): 128 x 128 tile, K looped in LDS chunks of 128.
+// Fallback kernel (2d > 256, coherence entry point only): 128 x 128 tiles, K
+// looped in LDS chunks of 128.
 
 #include "device_common.h"
 #include "launch.h"
@@ -43,6 +48,7 @@ namespace trstmi {
 namespace {
 
 constexpr int T = kTileBF16;
+constexpr int kSeg = 8;  // column tiles per row segment
 
 __device__ __forceinline__ u32x4 swap_negate(u32x4 u) {
   u32x4 v;
@@ -73,48 +79,60 @@ struct ARows {
   u32x4 v[2][KS];
 };
 
-// Stage the 128 B columns of tile column block bj into LDS and load this
-// wave's A rows of tile row block bi.  The caller synchronises.
 template <int KS>
-__device__ __forceinline__ void load_tile(const uint16_t* base, int ldk, int n, int bi, int bj, uint16_t* Bs,
-                                          ARows<KS>& A) {
-  constexpr int LDL = 32 * KS + 8;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-#pragma unroll
-  for (int it = 0; it < (T * KS * 4) / 256; ++it) {
-    const int idx = it * 256 + tid;
-    const int col = idx / (KS * 4);
-    const int ch = idx % (KS * 4);
-    const int cj = bj * T + col;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (cj < n) v = *(const u32x4*)(base + (size_t)cj * ldk + ch * 8);
-    *(u32x4*)&Bs[col * LDL + ch * 8] = v;
-  }
+__device__ __forceinline__ void load_rows(const uint16_t* base, int ldk, int n, int bi, ARows<KS>& A) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
     const int row = bi * T + w * 32 + rb * 16 + (lane & 15);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (row < n) v = *(const u32x4*)(base + (size_t)row * ldk + ks * 32 + 8 * (lane >> 4));
-      A.u[rb][ks] = v;
-      A.v[rb][ks] = swap_negate(v);
+      u32x4 u = {0u, 0u, 0u, 0u};
+      if (row < n) u = *(const u32x4*)(base + (size_t)row * ldk + ks * 32 + 8 * (lane >> 4));
+      A.u[rb][ks] = u;
+      A.v[rb][ks] = swap_negate(u);
     }
   }
 }
 
-// |G|^2 (float bits) of the 2 x 4 outputs this lane holds for column block cb:
-// m[rb * 4 + v] is tile row 32 w + 16 rb + 4 (lane / 16) + v, tile column 16 cb + lane % 16.
+// The B columns of tile column block bj: 128 columns x 4 KS chunks of 16 bytes,
+// 2 KS chunks per thread, fetched into registers and stored into LDS.
 template <int KS>
-__device__ __forceinline__ void colblock(const ARows<KS>& A, const uint16_t* Bs, int cb, uint32_t m[8]) {
+__device__ __forceinline__ void fetch_cols(const uint16_t* base, int ldk, int n, int bj, u32x4 pf[2 * KS]) {
+#pragma unroll
+  for (int it = 0; it < 2 * KS; ++it) {
+    const int idx = it * 256 + threadIdx.x;
+    const int col = idx / (KS * 4);
+    const int ch = idx % (KS * 4);
+    const int cj = bj * T + col;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (cj < n) v = *(const u32x4*)(base + (size_t)cj * ldk + ch * 8);
+    pf[it] = v;
+  }
+}
+
+template <int KS>
+__device__ __forceinline__ void store_cols(const u32x4 pf[2 * KS], uint16_t* Bs) {
+  constexpr int LDL = 32 * KS + 8;
+#pragma unroll
+  for (int it = 0; it < 2 * KS; ++it) {
+    const int idx = it * 256 + threadIdx.x;
+    const int col = idx / (KS * 4);
+    const int ch = idx % (KS * 4);
+    *(u32x4*)&Bs[col * LDL + ch * 8] = pf[it];
+  }
+}
+
+// MFMAs of column block cb: Re and -Im of the 2 x (16 x 16) outputs.
+template <int KS>
+__device__ __forceinline__ void mma_block(const ARows<KS>& A, const uint16_t* Bs, int cb, v4f32 accR[2],
+                                          v4f32 accI[2]) {
   constexpr int LDL = 32 * KS + 8;
   const int lane = threadIdx.x & 63;
   u32x4 bq[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) bq[ks] = *(const u32x4*)&Bs[(cb * 16 + (lane & 15)) * LDL + ks * 32 + 8 * (lane >> 4)];
-  v4f32 accR[2], accI[2];
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
     accR[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
@@ -129,6 +147,11 @@ __device__ __forceinline__ void colblock(const ARows<KS>& A, const uint16_t* Bs,
       accI[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][ks]), b, accI[rb], 0, 0, 0);
     }
   }
+}
+
+// |G|^2 float bits of the outputs: m[rb * 4 + v] is tile row
+// 32 w + 16 rb + 4 (lane / 16) + v, tile column 16 cb + lane % 16.
+__device__ __forceinline__ void sq_mag(const v4f32 accR[2], const v4f32 accI[2], uint32_t m[8]) {
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -138,53 +161,115 @@ __device__ __forceinline__ void colblock(const ARows<KS>& A, const uint16_t* Bs,
     }
 }
 
+__device__ __forceinline__ uint32_t max_of(uint32_t best, const uint32_t m[8]) {
+  const uint32_t a = max3u(m[0], m[1], m[2]);
+  const uint32_t b = max3u(m[3], m[4], m[5]);
+  const uint32_t c = max3u(m[6], m[7], best);
+  return max3u(a, b, c);
+}
+
+// Max |G|^2 bits over this wave's rows of one tile held in LDS.
+template <int KS>
+__device__ __forceinline__ uint32_t tile_max_wave(const ARows<KS>& A, const uint16_t* Bs, bool diag) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  uint32_t best = 0;
+  uint32_t m[8];
+  if (!diag) {
+    v4f32 xR[2], xI[2], yR[2], yI[2];
+    mma_block<KS>(A, Bs, 0, xR, xI);
+#pragma unroll
+    for (int cb = 1; cb < T / 16; ++cb) {
+      if (cb & 1) {
+        mma_block<KS>(A, Bs, cb, yR, yI);
+        sq_mag(xR, xI, m);
+      } else {
+        mma_block<KS>(A, Bs, cb, xR, xI);
+        sq_mag(yR, yI, m);
+      }
+      best = max_of(best, m);
+    }
+    sq_mag(yR, yI, m);
+    return max_of(best, m);
+  }
+  for (int cb = 2 * w; cb < T / 16; ++cb) {
+    v4f32 xR[2], xI[2];
+    mma_block<KS>(A, Bs, cb, xR, xI);
+    sq_mag(xR, xI, m);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
+      const int j = cb * 16 + (lane & 15);
+      if (i >= j) m[q] = 0u;
+    }
+    best = max_of(best, m);
+  }
+  return best;
+}
+
+// Segment s of the row-segment enumeration: row block bi in order, each row
+// block split into ceil((nt - bi) / kSeg) runs of at most kSeg column tiles.
+__device__ __forceinline__ void seg_decode(int s, int nt, int& bi, int& bj0, int& bj1) {
+  int r = 0;
+  int rem = s;
+  for (;;) {
+    const int ns = (nt - r + kSeg - 1) / kSeg;
+    if (rem < ns) break;
+    rem -= ns;
+    ++r;
+  }
+  bi = r;
+  bj0 = r + rem * kSeg;
+  bj1 = bj0 + kSeg < nt ? bj0 + kSeg : nt;
+}
+
 template <int KS>
 __global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
   if (a.flags && (*a.flags & kFlagDone)) return;
+  const int b = blockIdx.x;
+  const int local = b >> 3;
+  const int slot = (local / a.nseg) * 8 + (b & 7);
+  const int seg = local % a.nseg;
+  if (slot >= a.slots) return;
+  int bi, bj0, bj1;
+  seg_decode(seg, a.nt, bi, bj0, bj1);
   const int tiles = a.nt * (a.nt + 1) / 2;
-  int slot, tile;
-  if (!xcd_slot(a, tiles, slot, tile)) return;
-  int bi, bj;
-  tile_decode(tile, a.nt, bi, bj);
 
   __shared__ __attribute__((aligned(16))) uint16_t Bs[T * (32 * KS + 8)];
   __shared__ uint32_t red[4];
   const uint16_t* base = (const uint16_t*)a.cand + (size_t)slot * a.slot_stride;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
 
+  u32x4 pf[2 * KS];
+  fetch_cols<KS>(base, a.ldk, a.n, bj0, pf);
   ARows<KS> A;
-  load_tile<KS>(base, a.ldk, a.n, bi, bj, Bs, A);
+  load_rows<KS>(base, a.ldk, a.n, bi, A);
+  store_cols<KS>(pf, Bs);
   __syncthreads();
+  if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.ldk, a.n, bj0 + 1, pf);
 
-  const bool diag = bi == bj;
-  uint32_t best = 0;
-#pragma unroll 2
-  for (int cb = 0; cb < T / 16; ++cb) {
-    if (diag && 16 * cb + 15 <= 32 * w) continue;  // wholly below the diagonal
-    uint32_t m[8];
-    colblock<KS>(A, Bs, cb, m);
-    if (diag) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
-        const int j = cb * 16 + (lane & 15);
-        if (i >= j) m[q] = 0u;
-      }
+  uint32_t cmax = 0;
+  for (int bj = bj0; bj < bj1; ++bj) {
+    const uint32_t tmax = tile_max_wave<KS>(A, Bs, bj == bi);
+    cmax = tmax > cmax ? tmax : cmax;
+    if (a.tile_max) {
+      const uint32_t wm = wave_max_u32(tmax);
+      if (lane == 0) a.tile_max[((size_t)slot * tiles + tile_linear(bi, bj, a.nt)) * 4 + w] = wm;
     }
-    best = max3u(best, m[0], m[1]);
-    best = max3u(best, m[2], m[3]);
-    best = max3u(best, m[4], m[5]);
-    best = max3u(best, m[6], m[7]);
+    if (bj + 1 < bj1) {
+      __syncthreads();  // every wave is done with this tile's columns
+      store_cols<KS>(pf, Bs);
+      __syncthreads();
+      if (bj + 2 < bj1) fetch_cols<KS>(base, a.ldk, a.n, bj + 2, pf);
+    }
   }
 
-  best = wave_max_u32(best);
-  if (lane == 0) red[w] = best;
+  cmax = wave_max_u32(cmax);
+  if (lane == 0) red[w] = cmax;
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
-    if (a.tile_max) a.tile_max[(size_t)slot * tiles + tile] = mx;
     atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
   }
 }
@@ -228,13 +313,20 @@ __global__ __launch_bounds__(256, 2) void k_recheck_pairs(RecheckArgs a) {
     const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
     const uint16_t* base = a.screen + (size_t)a.rechecked[slot] * a.screen_stride;
     const double* c64 = a.cand64 + (size_t)slot * a.stride64;
+    {
+      u32x4 pf[2 * KS];
+      fetch_cols<KS>(base, a.ldk16, a.n, bj, pf);
+      store_cols<KS>(pf, Bs);
+    }
     ARows<KS> A;
-    load_tile<KS>(base, a.ldk16, a.n, bi, bj, Bs, A);
+    load_rows<KS>(base, a.ldk16, a.n, bi, A);
     __syncthreads();
     uint64_t best = 0;
     for (int cb = 0; cb < T / 16; ++cb) {
+      v4f32 xR[2], xI[2];
       uint32_t m[8];
-      colblock<KS>(A, Bs, cb, m);
+      mma_block<KS>(A, Bs, cb, xR, xI);
+      sq_mag(xR, xI, m);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int i = bi * T + w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
@@ -358,7 +450,8 @@ __global__ __launch_bounds__(256) void k_gram_bf16_chunked(GramArgs a) {
   __syncthreads();
   if (tid == 0) {
     const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
-    if (a.tile_max) a.tile_max[(size_t)slot * tiles + tile] = mx;
+    if (a.tile_max)
+      for (int q = 0; q < 4; ++q) a.tile_max[((size_t)slot * tiles + tile) * 4 + q] = mx;
     atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
   }
 }
@@ -377,11 +470,18 @@ hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s) {
 
 }  // namespace
 
+int bf16_segments(int nt) {
+  int total = 0;
+  for (int r = 0; r < nt; ++r) total += (nt - r + kSeg - 1) / kSeg;
+  return total;
+}
+
 hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
   GramArgs a = a_in;
   a.slots = slots;
-  const long tiles = (long)a.nt * (a.nt + 1) / 2;
-  const long grid = tiles * ((slots + 7) / 8) * 8;
+  a.nseg = bf16_segments(a.nt);
+  const long slots8 = (slots + 7) / 8 * 8;
+  const long grid = (long)a.nseg * slots8;
   const int ks = a.ldk / 32;
   switch (a.ldk % 32 == 0 ? ks : 0) {
     case 1: return launch_ks<1>(a, (int)grid, s);
@@ -392,9 +492,11 @@ hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
     case 6: return launch_ks<6>(a, (int)grid, s);
     case 7: return launch_ks<7>(a, (int)grid, s);
     case 8: return launch_ks<8>(a, (int)grid, s);
-    default:
-      hipLaunchKernelGGL(k_gram_bf16_chunked, dim3((int)grid), dim3(256), 0, s, a);
+    default: {
+      const long tiles = (long)a.nt * (a.nt + 1) / 2;
+      hipLaunchKernelGGL(k_gram_bf16_chunked, dim3((int)(tiles * slots8)), dim3(256), 0, s, a);
       return hipGetLastError();
+    }
   }
 }
 

@@ -54,9 +54,10 @@ struct GramArgs {
   int32_t d;
   int32_t nt;                // tiles per side
   int32_t slots;             // candidates in this launch (set by the launcher)
+  int32_t nseg;              // BF16: row segments per candidate (set by the launcher)
   uint64_t* cand_max;        // [slot] running max (bits of the float type)
   const int32_t* flags;      // DONE gate (null: always run)
-  uint32_t* tile_max;        // screen: [slot][ntiles] max bits per tile (null: not kept)
+  uint32_t* tile_max;        // screen: [slot][ntiles][4] max bits per tile and wave (null: not kept)
 };
 
 struct SelectArgs {
@@ -92,7 +93,7 @@ struct TopkArgs {
   int32_t* rep_rechecked;    // [k]
   // certified pruning of the FP64 recheck: screen tile maxima in, list of
   // screen tiles that may hold a rechecked candidate's exact maximum out
-  const uint32_t* tile_max;  // [C][screen tiles] float bits of max |G|^2
+  const uint32_t* tile_max;  // [C][screen tiles][4] float bits of max |G|^2 (per wave)
   int32_t screen_nt;         // screen tiles per side
   int2* list;                // out: (slot, screen tile) items
   int32_t* list_count;       // out

@@ -54,9 +54,13 @@ __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot
   // elements [2d, out_ld) of the column
   const size_t off = slot * (size_t)a.out_slot_stride + (size_t)col * a.out_ld;
   for (int k = 2 * a.d; k < a.out_ld; ++k) {
-    if (a.out_kind == kOutF64) ((double*)a.out)[off + k] = 0.0;
-    else if (a.out_kind == kOutF32) ((float*)a.out)[off + k] = 0.0f;
-    else ((uint16_t*)a.out)[off + k] = 0;
+    if (a.out_kind == kOutF64) {
+      ((double*)a.out)[off + k] = 0.0;
+    } else if (a.out_kind == kOutF32) {
+      ((float*)a.out)[off + k] = 0.0f;
+    } else {
+      ((uint16_t*)a.out)[off + k] = 0;
+    }
   }
 }
 

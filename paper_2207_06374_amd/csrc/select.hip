@@ -185,7 +185,11 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
       slot = e / sn;
       st = e - slot * sn;
       if (sel_thr[slot] > -__builtin_inf()) {
-        const double m = sqrt((double)__uint_as_float(a.tile_max[(size_t)sel_c[slot] * sn + st]));
+        const uint32_t* tm = a.tile_max + ((size_t)sel_c[slot] * sn + st) * 4;
+        uint32_t mb = tm[0] > tm[1] ? tm[0] : tm[1];
+        mb = tm[2] > mb ? tm[2] : mb;
+        mb = tm[3] > mb ? tm[3] : mb;
+        const double m = sqrt((double)__uint_as_float(mb));
         keep = !(m < sel_thr[slot]);
       }
     }
