@@ -97,18 +97,25 @@ __device__ __forceinline__ void load_rows(const uint16_t* base, int ldk, int n, 
 }
 
 // The B columns of tile column block bj: 128 columns x 4 KS chunks of 16 bytes,
-// 2 KS chunks per thread, fetched into registers and stored into LDS.
+// 2 KS chunks per thread, fetched into registers and stored into LDS.  Chunk
+// idx = it * 256 + thread is column idx / (4 KS), part idx % (4 KS); since the
+// column stride is 32 KS elements, the tile's columns are contiguous in
+// memory and chunk idx sits at element 8 idx of the tile.
 template <int KS>
-__device__ __forceinline__ void fetch_cols(const uint16_t* base, int ldk, int n, int bj, u32x4 pf[2 * KS]) {
+__device__ __forceinline__ void fetch_cols(const uint16_t* base, int n, int bj, u32x4 pf[2 * KS]) {
+  constexpr int LDK = 32 * KS;
+  const uint16_t* p = base + (size_t)bj * T * LDK + 8 * threadIdx.x;
+  if ((bj + 1) * T <= n) {
 #pragma unroll
-  for (int it = 0; it < 2 * KS; ++it) {
-    const int idx = it * 256 + threadIdx.x;
-    const int col = idx / (KS * 4);
-    const int ch = idx % (KS * 4);
-    const int cj = bj * T + col;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (cj < n) v = *(const u32x4*)(base + (size_t)cj * ldk + ch * 8);
-    pf[it] = v;
+    for (int it = 0; it < 2 * KS; ++it) pf[it] = *(const u32x4*)(p + it * 256 * 8);
+  } else {
+#pragma unroll
+    for (int it = 0; it < 2 * KS; ++it) {
+      const int col = (it * 256 + (int)threadIdx.x) / (KS * 4);
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (bj * T + col < n) v = *(const u32x4*)(p + it * 256 * 8);
+      pf[it] = v;
+    }
   }
 }
 
@@ -124,15 +131,18 @@ __device__ __forceinline__ void store_cols(const u32x4 pf[2 * KS], uint16_t* Bs)
   }
 }
 
-// MFMAs of column block cb: Re and -Im of the 2 x (16 x 16) outputs.
+// B fragments of column block cb from LDS.
 template <int KS>
-__device__ __forceinline__ void mma_block(const ARows<KS>& A, const uint16_t* Bs, int cb, v4f32 accR[2],
-                                          v4f32 accI[2]) {
+__device__ __forceinline__ void read_frags(const uint16_t* Bs, int cb, u32x4 bq[KS]) {
   constexpr int LDL = 32 * KS + 8;
   const int lane = threadIdx.x & 63;
-  u32x4 bq[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) bq[ks] = *(const u32x4*)&Bs[(cb * 16 + (lane & 15)) * LDL + ks * 32 + 8 * (lane >> 4)];
+}
+
+// MFMAs of one column block: Re and -Im of the 2 x (16 x 16) outputs.
+template <int KS>
+__device__ __forceinline__ void mma_frags(const ARows<KS>& A, const u32x4 bq[KS], v4f32 accR[2], v4f32 accI[2]) {
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
     accR[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
@@ -147,6 +157,14 @@ __device__ __forceinline__ void mma_block(const ARows<KS>& A, const uint16_t* Bs
       accI[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][ks]), b, accI[rb], 0, 0, 0);
     }
   }
+}
+
+template <int KS>
+__device__ __forceinline__ void mma_block(const ARows<KS>& A, const uint16_t* Bs, int cb, v4f32 accR[2],
+                                          v4f32 accI[2]) {
+  u32x4 bq[KS];
+  read_frags<KS>(Bs, cb, bq);
+  mma_frags<KS>(A, bq, accR, accI);
 }
 
 // |G|^2 float bits of the outputs: m[rb * 4 + v] is tile row
@@ -176,15 +194,22 @@ __device__ __forceinline__ uint32_t tile_max_wave(const ARows<KS>& A, const uint
   uint32_t best = 0;
   uint32_t m[8];
   if (!diag) {
+    // fragments of block cb + 1 are read while block cb multiplies; the
+    // epilogue of block cb - 1 runs behind the MFMAs of block cb
     v4f32 xR[2], xI[2], yR[2], yI[2];
-    mma_block<KS>(A, Bs, 0, xR, xI);
+    u32x4 bp[KS], bq[KS];
+    read_frags<KS>(Bs, 0, bp);
+    read_frags<KS>(Bs, 1, bq);
+    mma_frags<KS>(A, bp, xR, xI);
 #pragma unroll
     for (int cb = 1; cb < T / 16; ++cb) {
       if (cb & 1) {
-        mma_block<KS>(A, Bs, cb, yR, yI);
+        if (cb + 1 < T / 16) read_frags<KS>(Bs, cb + 1, bp);
+        mma_frags<KS>(A, bq, yR, yI);
         sq_mag(xR, xI, m);
       } else {
-        mma_block<KS>(A, Bs, cb, xR, xI);
+        if (cb + 1 < T / 16) read_frags<KS>(Bs, cb + 1, bq);
+        mma_frags<KS>(A, bp, xR, xI);
         sq_mag(yR, yI, m);
       }
       best = max_of(best, m);
@@ -223,8 +248,10 @@ __device__ __forceinline__ void seg_decode(int s, int nt, int& bi, int& bj0, int
   bj1 = bj0 + kSeg < nt ? bj0 + kSeg : nt;
 }
 
+// Two blocks per CU while the whole-K rows fit (2d <= 160); one block with the
+// full register file (VGPRs and AGPRs) beyond that.
 template <int KS>
-__global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
+__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) {
   if (a.flags && (*a.flags & kFlagDone)) return;
   const int b = blockIdx.x;
   const int local = b >> 3;
@@ -242,30 +269,30 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
   const int w = threadIdx.x >> 6;
 
   u32x4 pf[2 * KS];
-  fetch_cols<KS>(base, a.ldk, a.n, bj0, pf);
+  fetch_cols<KS>(base, a.n, bj0, pf);
   ARows<KS> A;
   load_rows<KS>(base, a.ldk, a.n, bi, A);
   store_cols<KS>(pf, Bs);
   __syncthreads();
-  if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.ldk, a.n, bj0 + 1, pf);
+  if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.n, bj0 + 1, pf);
 
   uint32_t cmax = 0;
   for (int bj = bj0; bj < bj1; ++bj) {
     const uint32_t tmax = tile_max_wave<KS>(A, Bs, bj == bi);
     cmax = tmax > cmax ? tmax : cmax;
     if (a.tile_max) {
-      const uint32_t wm = wave_max_u32(tmax);
+      const uint32_t wm = wave_max_u32_dpp(tmax);
       if (lane == 0) a.tile_max[((size_t)slot * tiles + tile_linear(bi, bj, a.nt)) * 4 + w] = wm;
     }
     if (bj + 1 < bj1) {
       __syncthreads();  // every wave is done with this tile's columns
       store_cols<KS>(pf, Bs);
       __syncthreads();
-      if (bj + 2 < bj1) fetch_cols<KS>(base, a.ldk, a.n, bj + 2, pf);
+      if (bj + 2 < bj1) fetch_cols<KS>(base, a.n, bj + 2, pf);
     }
   }
 
-  cmax = wave_max_u32(cmax);
+  cmax = wave_max_u32_dpp(cmax);
   if (lane == 0) red[w] = cmax;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -294,7 +321,7 @@ __device__ __forceinline__ uint64_t pair_f64(const double* c64, int ld, int d, i
 // screen within eps of the exact values serves) and every pair whose screened
 // value reaches thr is evaluated exactly in FP64 from the FP64 candidate.
 template <int KS>
-__global__ __launch_bounds__(256, 2) void k_recheck_pairs(RecheckArgs a) {
+__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_recheck_pairs(RecheckArgs a) {
   if (*a.flags & kFlagDone) return;
   __shared__ __attribute__((aligned(16))) uint16_t Bs[T * (32 * KS + 8)];
   __shared__ uint64_t red[4];
@@ -315,7 +342,7 @@ __global__ __launch_bounds__(256, 2) void k_recheck_pairs(RecheckArgs a) {
     const double* c64 = a.cand64 + (size_t)slot * a.stride64;
     {
       u32x4 pf[2 * KS];
-      fetch_cols<KS>(base, a.ldk16, a.n, bj, pf);
+      fetch_cols<KS>(base, a.n, bj, pf);
       store_cols<KS>(pf, Bs);
     }
     ARows<KS> A;
