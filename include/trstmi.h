@@ -201,6 +201,78 @@ trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, vo
                            size_t workspace_bytes, int32_t chunk, hipStream_t stream);
 
 /*
+ * Batched form: `count` independent searches of different sizes advanced
+ * together, one persistent kernel launch per step.  Instance i has its own
+ * N_i, d_i, seed and stream (its draws are those of a single search with the
+ * same seed and stream_id), its own frame, radius, step and flags, and its own
+ * target / step limit; the candidate count, radius rule and near-tie threshold
+ * are shared.  Every candidate is screened in FP32 on MFMA and the pairs that
+ * can attain its maximum are re-evaluated in FP64, so each candidate's
+ * coherence, the selection and the accept test are exact FP64 (each instance
+ * follows the FP64 single search; its result does not depend on the other
+ * instances in the batch or on its waves_per_item).
+ * Limits: 2 <= n <= 256, 1 <= d <= 16, n * (ceil(2d/4)*4 + 1) <= 8448 * wpi / 4,
+ * 1 <= candidates <= 256.  All state lives in the caller's workspace.
+ */
+typedef struct trstmi_batch_instance {
+  int32_t n;
+  int32_t d;
+  uint32_t seed;
+  uint32_t stream_id;
+  double target_mu;        /* <= 0: no target */
+  int64_t max_steps;
+  int32_t waves_per_item;  /* wavefronts per candidate: 1, 2 or 4; 0 = smallest that fits */
+  int32_t reserved;
+} trstmi_batch_instance;
+
+typedef struct trstmi_batch_params {
+  int32_t count;
+  int32_t candidates;
+  double radius0;
+  double grow;
+  double shrink;
+  double radius_min;
+  double radius_max;
+  double near_tie;         /* <= 0: 2e-12 */
+} trstmi_batch_params;
+
+/* Workspace bytes for this batch (0 if invalid).  `inst` is a host array. */
+size_t trstmi_batch_workspace_bytes(const trstmi_batch_params* p, const trstmi_batch_instance* inst);
+
+/* Lays out the batch in the workspace and draws every instance's random start
+ * (tag 1) with its exact FP64 coherence.  Copies `inst` (host) to the device
+ * and returns after the copy; the rest is ordered on `stream`. */
+trstmi_status trstmi_batch_init(const trstmi_batch_params* p, const trstmi_batch_instance* inst, void* workspace,
+                                size_t workspace_bytes, hipStream_t stream);
+
+/* `launches` steps of every not-yet-DONE instance (one kernel launch each).
+ * rep_mu (device [count][candidates], nullable) receives the candidates'
+ * FP64 coherences and rep_best (device [count], nullable) c* (-1: none), both
+ * for the last launch. */
+trstmi_status trstmi_batch_step(const trstmi_batch_params* p, const trstmi_batch_instance* inst, void* workspace,
+                                size_t workspace_bytes, int32_t launches, double* rep_mu, int32_t* rep_best,
+                                hipStream_t stream);
+
+/* Steps until every instance is DONE or max_chunks chunks have run: `chunk`
+ * step launches are captured once into a HIP graph (on a non-null stream) and
+ * replayed; the DONE count is polled after each chunk.  *all_done (host,
+ * nullable) is set to 1 if every instance finished. */
+trstmi_status trstmi_batch_run(const trstmi_batch_params* p, const trstmi_batch_instance* inst, void* workspace,
+                               size_t workspace_bytes, int32_t chunk, int64_t max_chunks, int32_t* all_done,
+                               hipStream_t stream);
+
+/* Copies the per-instance scalars to host arrays (each nullable) and waits
+ * for the stream. */
+trstmi_status trstmi_batch_query(const trstmi_batch_params* p, const trstmi_batch_instance* inst,
+                                 const void* workspace, size_t workspace_bytes, double* mu, double* radius,
+                                 int64_t* step, int32_t* flags, int32_t* done_instances, hipStream_t stream);
+
+/* Copies instance i's frame (2 d_i n_i doubles, frame layout) to `out` (device). */
+trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batch_instance* inst,
+                                 const void* workspace, size_t workspace_bytes, int32_t i, double* out,
+                                 hipStream_t stream);
+
+/*
  * Kernel timing.  trstmi_timing_enable(1) makes every later kernel launch of
  * the library record a HIP event before and after it on the launch's stream
  * (launches under graph capture are not timed).  trstmi_timing_read waits for

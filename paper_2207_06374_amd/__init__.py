@@ -224,3 +224,76 @@ def timing_read(kernel):
     _abi.check(_abi.lib().trstmi_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
                "trstmi_timing_read")
     return ms.value, cnt.value
+
+
+class Batch:
+    """Many independent searches advanced together (one persistent launch per
+    step).  ``instances``: iterable of dicts with keys n, d and optionally seed,
+    stream_id, target_mu, max_steps, waves_per_item."""
+
+    def __init__(self, instances, candidates=64, radius0=0.1, grow=2.0, shrink=0.5, radius_min=1e-12,
+                 radius_max=1.0, near_tie=0.0, device="cuda"):
+        torch = _torch()
+        inst = list(instances)
+        self.count = len(inst)
+        self.inst = (_abi.BatchInstance * self.count)()
+        for k, spec in enumerate(inst):
+            I = self.inst[k]
+            I.n, I.d = int(spec["n"]), int(spec["d"])
+            I.seed = int(spec.get("seed", 0))
+            I.stream_id = int(spec.get("stream_id", k))
+            I.target_mu = float(spec.get("target_mu", 0.0))
+            I.max_steps = int(spec.get("max_steps", 1000))
+            I.waves_per_item = int(spec.get("waves_per_item", 0))
+        self.params = _abi.BatchParams(self.count, int(candidates), float(radius0), float(grow), float(shrink),
+                                       float(radius_min), float(radius_max), float(near_tie))
+        nbytes = _abi.lib().trstmi_batch_workspace_bytes(ctypes.byref(self.params), self.inst)
+        if nbytes == 0:
+            raise _abi.TrstmiError(_abi.E_INVALID_ARG, "trstmi_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.rep_mu = torch.empty(self.count * int(candidates), dtype=torch.float64, device=device)
+        self.rep_best = torch.empty(self.count, dtype=torch.int32, device=device)
+        self.device = device
+
+    def _args(self):
+        return ctypes.byref(self.params), self.inst, _ptr(self.workspace), self.workspace.numel()
+
+    def init(self, stream=None):
+        _abi.check(_abi.lib().trstmi_batch_init(*self._args(), _stream(stream)), "trstmi_batch_init")
+        return self
+
+    def step(self, launches=1, report=False, stream=None):
+        _abi.check(_abi.lib().trstmi_batch_step(*self._args(), int(launches),
+                                                _ptr(self.rep_mu) if report else None,
+                                                _ptr(self.rep_best) if report else None, _stream(stream)),
+                   "trstmi_batch_step")
+
+    def run(self, chunk=16, max_chunks=1000, stream=None):
+        done = ctypes.c_int32(0)
+        _abi.check(_abi.lib().trstmi_batch_run(*self._args(), int(chunk), int(max_chunks), ctypes.byref(done),
+                                               _stream(stream)), "trstmi_batch_run")
+        return bool(done.value)
+
+    def query(self, stream=None):
+        """Host numpy arrays (mu, radius, step, flags) and the DONE count."""
+        n = self.count
+        mu = np.zeros(n)
+        radius = np.zeros(n)
+        step = np.zeros(n, dtype=np.int64)
+        flags = np.zeros(n, dtype=np.int32)
+        done = ctypes.c_int32(0)
+        _abi.check(_abi.lib().trstmi_batch_query(*self._args(), mu.ctypes.data_as(ctypes.c_void_p),
+                                                 radius.ctypes.data_as(ctypes.c_void_p),
+                                                 step.ctypes.data_as(ctypes.c_void_p),
+                                                 flags.ctypes.data_as(ctypes.c_void_p), ctypes.byref(done),
+                                                 _stream(stream)), "trstmi_batch_query")
+        return mu, radius, step, flags, done.value
+
+    def frame(self, i, stream=None):
+        """Instance i's frame as a numpy (d, N) complex128 array."""
+        torch = _torch()
+        n, d = self.inst[i].n, self.inst[i].d
+        out = torch.empty(2 * n * d, dtype=torch.float64, device=self.device)
+        _abi.check(_abi.lib().trstmi_batch_frame(*self._args(), int(i), _ptr(out), _stream(stream)),
+                   "trstmi_batch_frame")
+        return frame_from_device(out, n, d)

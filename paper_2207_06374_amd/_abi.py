@@ -71,6 +71,32 @@ class Report(ctypes.Structure):
     ]
 
 
+class BatchInstance(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("seed", ctypes.c_uint32),
+        ("stream_id", ctypes.c_uint32),
+        ("target_mu", ctypes.c_double),
+        ("max_steps", ctypes.c_int64),
+        ("waves_per_item", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("radius0", ctypes.c_double),
+        ("grow", ctypes.c_double),
+        ("shrink", ctypes.c_double),
+        ("radius_min", ctypes.c_double),
+        ("radius_max", ctypes.c_double),
+        ("near_tie", ctypes.c_double),
+    ]
+
+
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -87,6 +113,13 @@ SIGNATURES = {
     "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),
     "trstmi_solve": (_i32, [_P(Params), _P(State), _vp, _sz, _i32, _vp]),
+    "trstmi_batch_workspace_bytes": (_sz, [_P(BatchParams), _P(BatchInstance)]),
+    "trstmi_batch_init": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _vp]),
+    "trstmi_batch_step": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _i32, _vp, _vp, _vp]),
+    "trstmi_batch_run": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _i32, _i64, _P(_i32), _vp]),
+    "trstmi_batch_query": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _vp, _vp, _vp, _vp, _P(_i32),
+                                  _vp]),
+    "trstmi_batch_frame": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _i32, _vp, _vp]),
     "trstmi_timing_enable": (_i32, [_i32]),
     "trstmi_timing_reset": (_i32, []),
     "trstmi_timing_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_i64)]),

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -413,6 +414,120 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   return TRSTMI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched form: layout of the workspace (computed on the host from the
+// parameters on every call).
+// ---------------------------------------------------------------------------
+constexpr int kBatchGridCap = 1024;   // persistent blocks (4 per CU)
+constexpr int kBatchMaxN = 256;
+constexpr int kBatchMaxD = 16;
+constexpr int kBatchMaxC = 256;
+
+struct BatchLayout {
+  size_t hdr = 0, inst = 0, state = 0, units = 0, frames = 0, cand = 0, scratch = 0, total = 0;
+  int nunits = 0;
+  int grid = 0;
+  int64_t scratch_stride = 0;
+  std::vector<int64_t> frame_off;
+  std::vector<int32_t> wpi;
+  std::vector<int2> unit_list;
+};
+
+int32_t batch_ldk(int32_t d) { return (2 * d + 3) / 4 * 4 + 1; }
+
+trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_instance* inst, BatchLayout& L) {
+  if (!p || !inst) return fail(TRSTMI_E_INVALID_ARG, "batch params or instances NULL");
+  if (p->count < 1 || p->count > (1 << 20)) return fail(TRSTMI_E_INVALID_ARG, "batch count must be in [1, 2^20]");
+  if (p->candidates < 1 || p->candidates > kBatchMaxC)
+    return fail(TRSTMI_E_INVALID_ARG, "batch candidates must be in [1, 256]");
+  const bool ok_r = std::isfinite(p->radius0) && std::isfinite(p->radius_min) && std::isfinite(p->radius_max) &&
+                    p->radius_min > 0 && p->radius_min <= p->radius0 && p->radius0 <= p->radius_max;
+  if (!ok_r) return fail(TRSTMI_E_INVALID_ARG, "need finite 0 < radius_min <= radius0 <= radius_max");
+  if (!(std::isfinite(p->grow) && p->grow >= 1.0) || !(std::isfinite(p->shrink) && p->shrink > 0 && p->shrink <= 1.0))
+    return fail(TRSTMI_E_INVALID_ARG, "need grow >= 1 and 0 < shrink <= 1");
+  const int lds = batch_lds_floats();
+  L.frame_off.resize(p->count);
+  L.wpi.resize(p->count);
+  int64_t off = 0, max_frame = 0;
+  std::vector<std::pair<int64_t, int32_t>> order;
+  for (int32_t i = 0; i < p->count; ++i) {
+    const trstmi_batch_instance& I = inst[i];
+    if (I.n < 2 || I.n > kBatchMaxN || I.d < 1 || I.d > kBatchMaxD)
+      return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": need 2 <= n <= 256, 1 <= d <= 16");
+    if (I.max_steps < 0 || std::isnan(I.target_mu))
+      return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": bad max_steps or target");
+    const int64_t need = (int64_t)I.n * batch_ldk(I.d);
+    int32_t w = I.waves_per_item;
+    if (w == 0) w = need * 4 <= lds ? 1 : (need * 2 <= lds ? 2 : 4);
+    if (w != 1 && w != 2 && w != 4)
+      return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": waves_per_item must be 0, 1, 2 or 4");
+    if (need * (4 / w) > lds)
+      return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": too large for waves_per_item");
+    L.wpi[i] = w;
+    L.frame_off[i] = off;
+    const int64_t fl = 2 * (int64_t)I.d * I.n;
+    off += (fl + 31) / 32 * 32;
+    max_frame = fl > max_frame ? fl : max_frame;
+    order.push_back({-(int64_t)I.n * I.n * I.d, i});
+  }
+  std::stable_sort(order.begin(), order.end());
+  L.unit_list.clear();
+  for (auto& o : order) {
+    const int32_t i = o.second;
+    const int per = 4 / L.wpi[i];
+    for (int c0 = 0; c0 < p->candidates; c0 += per) L.unit_list.push_back(make_int2(i, c0));
+  }
+  L.nunits = (int)L.unit_list.size();
+  L.grid = L.nunits < kBatchGridCap ? L.nunits : kBatchGridCap;
+  L.scratch_stride = (max_frame + 31) / 32 * 32;
+  size_t o = 0;
+  L.hdr = o;
+  o = align256(o + 256);
+  L.inst = o;
+  o = align256(o + (size_t)p->count * batch_inst_bytes());
+  L.state = o;
+  o = align256(o + (size_t)p->count * batch_state_bytes());
+  L.units = o;
+  o = align256(o + (size_t)L.nunits * sizeof(int2));
+  L.frames = o;
+  o = align256(o + (size_t)off * 8);
+  L.cand = o;
+  o = align256(o + (size_t)p->count * p->candidates * 8);
+  L.scratch = o;
+  o = align256(o + (size_t)kBatchGridCap * 4 * L.scratch_stride * 8);
+  L.total = o;
+  return TRSTMI_OK;
+}
+
+BatchArgs batch_args(const trstmi_batch_params* p, const BatchLayout& L, char* ws) {
+  BatchArgs b{};
+  b.inst = ws + L.inst;
+  b.state = ws + L.state;
+  b.units = (const int2*)(ws + L.units);
+  b.nunits = L.nunits;
+  b.C = p->candidates;
+  b.frames = (double*)(ws + L.frames);
+  b.cand_max = (uint64_t*)(ws + L.cand);
+  b.scratch = (double*)(ws + L.scratch);
+  b.scratch_stride = L.scratch_stride;
+  b.next_unit = (int32_t*)(ws + L.hdr);
+  b.blocks_done = (int32_t*)(ws + L.hdr) + 1;
+  b.done_instances = (int32_t*)(ws + L.hdr) + 2;
+  b.tau = p->near_tie > 0 ? p->near_tie : 2e-12;
+  b.grow = p->grow;
+  b.shrink = p->shrink;
+  b.radius_min = p->radius_min;
+  b.radius_max = p->radius_max;
+  return b;
+}
+
+trstmi_status batch_prepare(const trstmi_batch_params* p, const trstmi_batch_instance* inst, const void* ws,
+                            size_t ws_bytes, BatchLayout& L) {
+  trstmi_status st = batch_layout(p, inst, L);
+  if (st) return st;
+  return check_ws(const_cast<void*>(ws), ws_bytes, L.total);
+}
+
 }  // namespace
 
 extern "C" {
@@ -655,6 +770,139 @@ trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* 
   auto it = T.totals.find(kernel);
   *total_ms = it == T.totals.end() ? 0.0 : it->second.first;
   *launches = it == T.totals.end() ? 0 : it->second.second;
+  return TRSTMI_OK;
+}
+
+size_t trstmi_batch_workspace_bytes(const trstmi_batch_params* p, const trstmi_batch_instance* inst) {
+  BatchLayout L;
+  if (batch_layout(p, inst, L)) return 0;
+  return L.total;
+}
+
+trstmi_status trstmi_batch_init(const trstmi_batch_params* p, const trstmi_batch_instance* inst, void* workspace,
+                                size_t workspace_bytes, hipStream_t stream) {
+  BatchLayout L;
+  trstmi_status st = batch_prepare(p, inst, workspace, workspace_bytes, L);
+  if (st) return st;
+  char* ws = (char*)workspace;
+  std::vector<char> host_inst((size_t)p->count * batch_inst_bytes());
+  for (int32_t i = 0; i < p->count; ++i)
+    batch_fill_inst(host_inst.data() + (size_t)i * batch_inst_bytes(), inst[i].n, inst[i].d, L.wpi[i], inst[i].seed,
+                    inst[i].stream_id, L.frame_off[i], inst[i].target_mu, inst[i].max_steps);
+  std::vector<char> zeros(256 + (size_t)p->count * batch_state_bytes(), 0);
+  TRY_HIP(hipMemcpyAsync(ws + L.hdr, zeros.data(), 256, hipMemcpyHostToDevice, stream), "batch header");
+  TRY_HIP(hipMemcpyAsync(ws + L.state, zeros.data(), (size_t)p->count * batch_state_bytes(), hipMemcpyHostToDevice,
+                         stream), "batch state");
+  TRY_HIP(hipMemcpyAsync(ws + L.inst, host_inst.data(), host_inst.size(), hipMemcpyHostToDevice, stream), "batch inst");
+  TRY_HIP(hipMemcpyAsync(ws + L.units, L.unit_list.data(), L.unit_list.size() * sizeof(int2), hipMemcpyHostToDevice,
+                         stream), "batch units");
+  const BatchArgs b = batch_args(p, L, ws);
+  TRY_HIP(TIMED("batch_init", stream, launch_batch_init(b, p->count, p->radius0, stream)), "batch init");
+  TRY_HIP(hipStreamSynchronize(stream), "batch init sync");  // host buffers above must outlive the copies
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_batch_step(const trstmi_batch_params* p, const trstmi_batch_instance* inst, void* workspace,
+                                size_t workspace_bytes, int32_t launches, double* rep_mu, int32_t* rep_best,
+                                hipStream_t stream) {
+  BatchLayout L;
+  trstmi_status st = batch_prepare(p, inst, workspace, workspace_bytes, L);
+  if (st) return st;
+  if (launches < 0) return fail(TRSTMI_E_INVALID_ARG, "launches must be >= 0");
+  BatchArgs b = batch_args(p, L, (char*)workspace);
+  b.rep_mu = rep_mu;
+  b.rep_best = rep_best;
+  for (int32_t l = 0; l < launches; ++l)
+    TRY_HIP(TIMED("batch_step", stream, launch_batch_step(b, L.grid, stream)), "batch step");
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_batch_run(const trstmi_batch_params* p, const trstmi_batch_instance* inst, void* workspace,
+                               size_t workspace_bytes, int32_t chunk, int64_t max_chunks, int32_t* all_done,
+                               hipStream_t stream) {
+  BatchLayout L;
+  trstmi_status st = batch_prepare(p, inst, workspace, workspace_bytes, L);
+  if (st) return st;
+  if (chunk < 1 || max_chunks < 0) return fail(TRSTMI_E_INVALID_ARG, "chunk must be >= 1, max_chunks >= 0");
+  char* ws = (char*)workspace;
+  const BatchArgs b = batch_args(p, L, ws);
+  int32_t done = 0;
+  if (all_done) *all_done = 0;
+  TRY_HIP(hipMemcpyAsync(&done, b.done_instances, 4, hipMemcpyDeviceToHost, stream), "batch poll");
+  TRY_HIP(hipStreamSynchronize(stream), "batch poll");
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (stream != nullptr && done < p->count && max_chunks > 0) {
+    TRY_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "batch capture");
+    hipError_t le = hipSuccess;
+    for (int32_t l = 0; l < chunk && le == hipSuccess; ++l) le = launch_batch_step(b, L.grid, stream);
+    hipError_t ce = hipStreamEndCapture(stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(le != hipSuccess ? le : ce, "batch capture");
+    }
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(ie, "batch graph instantiate");
+    }
+  }
+  trstmi_status result = TRSTMI_OK;
+  for (int64_t k = 0; k < max_chunks && done < p->count; ++k) {
+    hipError_t e = hipSuccess;
+    if (exec) {
+      e = hipGraphLaunch(exec, stream);
+    } else {
+      for (int32_t l = 0; l < chunk && e == hipSuccess; ++l) e = launch_batch_step(b, L.grid, stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&done, b.done_instances, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      result = hip_fail(e, "batch run");
+      break;
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (result == TRSTMI_OK && all_done) *all_done = done >= p->count ? 1 : 0;
+  return result;
+}
+
+trstmi_status trstmi_batch_query(const trstmi_batch_params* p, const trstmi_batch_instance* inst,
+                                 const void* workspace, size_t workspace_bytes, double* mu, double* radius,
+                                 int64_t* step, int32_t* flags, int32_t* done_instances, hipStream_t stream) {
+  BatchLayout L;
+  trstmi_status st = batch_prepare(p, inst, workspace, workspace_bytes, L);
+  if (st) return st;
+  const char* ws = (const char*)workspace;
+  std::vector<char> buf((size_t)p->count * batch_state_bytes());
+  int32_t hdr[4] = {0, 0, 0, 0};
+  TRY_HIP(hipMemcpyAsync(buf.data(), ws + L.state, buf.size(), hipMemcpyDeviceToHost, stream), "batch query");
+  TRY_HIP(hipMemcpyAsync(hdr, ws + L.hdr, sizeof(hdr), hipMemcpyDeviceToHost, stream), "batch query");
+  TRY_HIP(hipStreamSynchronize(stream), "batch query");
+  const size_t sb = batch_state_bytes();
+  for (int32_t i = 0; i < p->count; ++i) {
+    const char* s = buf.data() + (size_t)i * sb;  // {double mu, double radius, int64 step, int32 flags, int32 count}
+    if (mu) std::memcpy(&mu[i], s, 8);
+    if (radius) std::memcpy(&radius[i], s + 8, 8);
+    if (step) std::memcpy(&step[i], s + 16, 8);
+    if (flags) std::memcpy(&flags[i], s + 24, 4);
+  }
+  if (done_instances) *done_instances = hdr[2];
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batch_instance* inst,
+                                 const void* workspace, size_t workspace_bytes, int32_t i, double* out,
+                                 hipStream_t stream) {
+  BatchLayout L;
+  trstmi_status st = batch_prepare(p, inst, workspace, workspace_bytes, L);
+  if (st) return st;
+  if (i < 0 || i >= p->count || !out) return fail(TRSTMI_E_INVALID_ARG, "bad instance index or output");
+  const char* ws = (const char*)workspace;
+  const size_t bytes = (size_t)2 * inst[i].d * inst[i].n * 8;
+  TRY_HIP(hipMemcpyAsync(out, ws + L.frames + (size_t)L.frame_off[i] * 8, bytes, hipMemcpyDeviceToDevice, stream),
+          "batch frame");
   return TRSTMI_OK;
 }
 

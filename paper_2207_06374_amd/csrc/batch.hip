@@ -1,0 +1,489 @@
+// Batched form: many independent, uneven searches advanced by one persistent
+// kernel per step.
+//
+// Every instance i is an independent search (its own N_i, d_i, frame, radius,
+// step and RNG stream) with the candidate rule of the single-frame path:
+// candidate c at step t is Y = Phi + (radius / sqrt(d)) Z(i, c, t),
+// renormalised; the best candidate by (mu_c, c) is accepted iff it lowers mu.
+//
+// Work: a unit is 1, 2 or 4 candidates of one instance, processed by one
+// block of 4 wavefronts split into groups of `wpi` waves per candidate (the
+// per-instance tile choice).  Blocks take units from an atomic counter,
+// largest instances first.  Per candidate the group
+//   1. draws and renormalises the candidate in FP64 (FP64 copy to global
+//      scratch, FP32 copy to LDS);
+//   2. screens every pair j < k with v_mfma_f32_16x16x4_f32 on the FP32 copy,
+//      keeping the maximum of every 16 x 16 pair block;
+//   3. re-evaluates exactly in FP64 the pairs whose screened |G| is within
+//      2 eps32 of the screened maximum (eps32 bounds |screened - exact| for
+//      unit columns, so the exact maximiser is among them): every candidate
+//      ends with its exact FP64 coherence.
+// The group that completes an instance's last candidate (atomic count)
+// selects, accepts, updates the radius and regenerates the accepted candidate
+// in FP64 into the frame with a single wavefront.  No block ever waits for
+// another; the last block to leave resets the counters for the next launch.
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace trstmi {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kLdsFloats = 8192 + 256;  // FP32 candidate(s): N * (ldk + 1) per group, summed over groups
+
+struct alignas(16) BInst {
+  int32_t n, d, wpi, ldk;  // ldk: FP32 column stride in LDS (2d rounded up to 4, +1 padding)
+  uint32_t seed, stream_id;
+  int64_t frame_off;       // doubles into the frame arena
+  double target_mu;
+  int64_t max_steps;
+};
+
+struct alignas(16) BState {
+  double mu;
+  double radius;
+  int64_t step;
+  int32_t flags;
+  int32_t done_count;      // candidates of the current step finished
+};
+
+__device__ __forceinline__ double eps32(int d) {
+  // |screened - exact| for unit columns: FP32 inputs (relative 2^-24) move each
+  // real dot product by at most 2u + u^2; FP32 accumulation of 2d products
+  // adds gamma_{2d}; Re and Im give sqrt 2; the tail covers the epilogue.
+  const double u = 0x1p-24;
+  const double nu = 2.0 * d * u;
+  const double g = nu / (1.0 - nu);
+  return 1.4142135623730951 * (2 * u + u * u + g * (1 + u) * (1 + u)) + 16 * u + 1e-12;
+}
+
+// Candidate c of instance I at step t, column col, Philox block q (entries 2q, 2q+1).
+__device__ __forceinline__ void draw_block(const BInst& I, const double* frame, double s, int c, int64_t t,
+                                           int64_t col, int q, double y[4], bool& two) {
+  const int d = I.d;
+  const int nb = (d + 1) >> 1;
+  const int i0 = 2 * q;
+  two = (i0 + 1) < d;
+  const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, 0u};
+  const u32x4 w = philox4x32_10(ctr, I.seed, I.stream_id);
+  double g0, g1, g2, g3;
+  box_muller(w.x, w.y, g0, g1);
+  box_muller(w.z, w.w, g2, g3);
+  const double h = 0.7071067811865476;
+  const double* bp = frame + 2 * ((size_t)col * d + i0);
+  y[0] = bp[0] + s * (g0 * h);
+  y[1] = bp[1] + s * (g1 * h);
+  y[2] = two ? bp[2] + s * (g2 * h) : 0.0;
+  y[3] = two ? bp[3] + s * (g3 * h) : 0.0;
+}
+
+// Lanes [0, nl) of the calling wave group regenerate candidate c (FP64, unit
+// columns) into `out` (column stride 2d) and, when lds != null, into the FP32
+// LDS copy.  Lanes of one column are LPC consecutive lanes; the norm is
+// reduced with xor-shuffles inside the column's lanes.
+template <int LPC>
+__device__ void gen_candidate(const BInst& I, const double* frame, double radius, int c, int64_t t, double* out,
+                              float* lds, int lane_g, int nl) {
+  const int d = I.d;
+  const int nb = (d + 1) >> 1;
+  const double s = radius / sqrt((double)d);
+  const int cols_per_pass = nl / LPC;
+  const int lq = lane_g % LPC;
+  for (int64_t col0 = 0; col0 < I.n; col0 += cols_per_pass) {
+    const int64_t col = col0 + lane_g / LPC;
+    const bool active = col < I.n && lq < nb;
+    double y[4] = {0.0, 0.0, 0.0, 0.0};
+    bool two = false;
+    if (active) draw_block(I, frame, s, c, t, col, lq, y, two);
+    double nrm2 = (y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]);
+#pragma unroll
+    for (int off = LPC / 2; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
+    if (!active) continue;
+    const double nrm = sqrt(nrm2);
+    const bool bad = !(nrm > 0.0 && nrm < __builtin_inf());
+    const double inv = bad ? __builtin_nan("") : 1.0 / nrm;
+    const int i0 = 2 * lq;
+    double* o = out + 2 * ((size_t)col * d + i0);
+    o[0] = y[0] * inv;
+    o[1] = y[1] * inv;
+    if (two) {
+      o[2] = y[2] * inv;
+      o[3] = y[3] * inv;
+    }
+    if (lds) {
+      float* l = lds + (size_t)col * I.ldk + 2 * i0;  // reals 2 i0 .. 2 i0 + 3 of the column
+      l[0] = (float)(y[0] * inv);
+      l[1] = (float)(y[1] * inv);
+      if (two) {
+        l[2] = (float)(y[2] * inv);
+        l[3] = (float)(y[3] * inv);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void gen_dispatch(const BInst& I, const double* frame, double radius, int c, int64_t t,
+                                             double* out, float* lds, int lane_g, int nl) {
+  // d <= 16: at most 8 blocks per column
+  const int nb = (I.d + 1) >> 1;
+  if (nb <= 1) gen_candidate<1>(I, frame, radius, c, t, out, lds, lane_g, nl);
+  else if (nb <= 2) gen_candidate<2>(I, frame, radius, c, t, out, lds, lane_g, nl);
+  else if (nb <= 4) gen_candidate<4>(I, frame, radius, c, t, out, lds, lane_g, nl);
+  else gen_candidate<8>(I, frame, radius, c, t, out, lds, lane_g, nl);
+}
+
+// |G|^2 of the 16 x 16 pair block (bi, bj) from the FP32 copy in LDS;
+// m[v] = output (row 4 (lane/16) + v, column lane % 16) of the block, 0 where
+// the pair is not (j > i, j < n).
+__device__ __forceinline__ void screen_block(const float* L, int ldk, int n, int d, int bi, int bj, float m[4]) {
+  const int lane = threadIdx.x & 63;
+  const int kl = lane >> 4;
+  const bool odd = kl & 1;
+  const float* ra = L + (size_t)(bi * 16 + (lane & 15)) * ldk;
+  const float* rb = L + (size_t)(bj * 16 + (lane & 15)) * ldk;
+  const bool ina = bi * 16 + (lane & 15) < n, inb = bj * 16 + (lane & 15) < n;
+  v4f32 accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+  const int K = 2 * d;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + kl;
+    const float a = (ina && k < K) ? ra[k] : 0.f;
+    const float bu = (inb && k < K) ? rb[k] : 0.f;
+    const int kx = k ^ 1;
+    const float x = (inb && kx < K) ? rb[kx] : 0.f;
+    const float bv = odd ? -x : x;
+    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bu, accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, accI, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = bi * 16 + 4 * (lane >> 4) + v;
+    const int j = bj * 16 + (lane & 15);
+    const float re = accR[v], im = accI[v];
+    m[v] = (i < j && j < n) ? fmaf(re, re, im * im) : 0.f;
+  }
+}
+
+__device__ __forceinline__ uint64_t pair_f64_b(const double* c64, int d, int j, int k) {
+  const double2* x = (const double2*)(c64 + 2 * (size_t)j * d);
+  const double2* y = (const double2*)(c64 + 2 * (size_t)k * d);
+  double re = 0.0, im = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const double2 p = x[i], q = y[i];
+    re += p.x * q.x + p.y * q.y;
+    im += p.x * q.y - p.y * q.x;
+  }
+  return (uint64_t)__double_as_longlong(re * re + im * im);
+}
+
+__device__ __forceinline__ double bits_mu(uint64_t b) {
+  if (b >= kInfBits64) return __builtin_inf();
+  return sqrt(__longlong_as_double((int64_t)b));
+}
+
+// Select / accept / radius update of instance i and the in-place FP64 commit,
+// by one wavefront.
+__device__ void finalize(const BatchArgs& a, int i) {
+  const BInst& I = ((const BInst*)a.inst)[i];
+  BState* S = (BState*)a.state + i;
+  const int lane = threadIdx.x & 63;
+  __threadfence();
+  double v1 = __builtin_inf(), v2 = __builtin_inf();
+  int c1 = 0x7fffffff;
+  for (int c = lane; c < a.C; c += 64) {
+    const uint64_t b = __hip_atomic_load(&a.cand_max[(size_t)i * a.C + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double mu = bits_mu(b);
+    if (a.rep_mu) a.rep_mu[(size_t)i * a.C + c] = mu;
+    if (!(mu < __builtin_inf())) continue;
+    if (mu < v1 || (mu == v1 && c < c1)) {
+      v2 = v1;
+      v1 = mu;
+      c1 = c;
+    } else if (mu < v2) {
+      v2 = mu;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov1 = __shfl_xor(v1, off, 64), ov2 = __shfl_xor(v2, off, 64);
+    const int oc1 = __shfl_xor(c1, off, 64);
+    if (ov1 < v1 || (ov1 == v1 && oc1 < c1)) {
+      v2 = fmin(v1, ov2);
+      v1 = ov1;
+      c1 = oc1;
+    } else {
+      v2 = fmin(v2, ov1);
+    }
+  }
+  const double mu_t = S->mu;
+  const double rad = S->radius;
+  const int64_t t = S->step;
+  const bool valid = c1 != 0x7fffffff;
+  const bool accept = valid && v1 < mu_t;
+  if (accept) {
+    // regenerate candidate c1 of step t into the frame, in place
+    double* frame = a.frames + I.frame_off;
+    gen_dispatch(I, frame, rad, c1, t, frame, nullptr, lane, 64);
+  }
+  if (lane == 0) {
+    bool near = valid && fabs(v1 - mu_t) <= a.tau;
+    if (valid && v2 - v1 <= a.tau) near = true;
+    const double new_mu = accept ? v1 : mu_t;
+    const double new_rad = accept ? fmin(rad * a.grow, a.radius_max) : fmax(rad * a.shrink, a.radius_min);
+    const int64_t nt = t + 1;
+    const bool done = (I.target_mu > 0.0 && new_mu <= I.target_mu) || nt >= I.max_steps;
+    S->mu = new_mu;
+    S->radius = new_rad;
+    S->step = nt;
+    S->flags = (accept ? kFlagAccepted : 0) | (near ? kFlagNearTie : 0) | (valid ? 0 : kFlagNoValid) |
+               (done ? kFlagDone : 0);
+    if (a.rep_best) a.rep_best[i] = valid ? c1 : -1;
+    S->done_count = 0;
+    if (done) atomicAdd(a.done_instances, 1);
+    __threadfence();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
+  __shared__ float lds[kLdsFloats];
+  __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
+  __shared__ uint32_t smax[4];
+  __shared__ unsigned long long umax[4];
+  __shared__ int unit_s;
+  __shared__ int fin_s[4];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+
+  for (;;) {
+    if (tid == 0) unit_s = atomicAdd(a.next_unit, 1);
+    __syncthreads();
+    const int u = unit_s;
+    if (u >= a.nunits) break;
+    const int2 unit = a.units[u];
+    const int i = unit.x;
+    const BInst I = ((const BInst*)a.inst)[i];
+    const BState S0 = ((const BState*)a.state)[i];
+    const bool skip_inst = S0.flags & kFlagDone;
+    const int wpi = I.wpi;
+    const int g = wave / wpi;                 // group of this wave
+    const int wg = wave % wpi;                // wave index inside the group
+    const int c = unit.y + g;
+    const bool work = !skip_inst && c < a.C;
+    const int groups = 4 / wpi;
+    float* L = lds + (size_t)g * (kLdsFloats / groups);
+    double* c64 = a.scratch + ((size_t)blockIdx.x * 4 + g) * a.scratch_stride;
+    const int n = I.n;
+    const int nbk = (n + 15) / 16;
+    const int nblk = nbk * (nbk + 1) / 2;
+
+    // 1. candidate (FP64 scratch + FP32 LDS copy; entries past 2d are never read)
+    if (tid < 4) {
+      smax[tid] = 0;
+      umax[tid] = 0;
+      fin_s[tid] = 0;
+    }
+    __syncthreads();
+    if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, wg * 64 + lane, wpi * 64);
+    __threadfence_block();
+    __syncthreads();
+
+    // 2. FP32 screen: block maxima and the candidate maximum
+    if (work) {
+      uint32_t wmax = 0;
+      for (int b = wg; b < nblk; b += wpi) {
+        int bi, bj;
+        tile_decode(b, nbk, bi, bj);
+        float m[4];
+        screen_block(L, I.ldk, n, I.d, bi, bj, m);
+        uint32_t bm = __float_as_uint(m[0]);
+#pragma unroll
+        for (int v = 1; v < 4; ++v) bm = __float_as_uint(m[v]) > bm ? __float_as_uint(m[v]) : bm;
+        bm = wave_max_u32_dpp(bm);
+        if (lane == 0) blkmax[g][b] = bm;
+        wmax = bm > wmax ? bm : wmax;
+      }
+      if (lane == 0) atomicMax(&smax[g], wmax);
+    }
+    __syncthreads();
+
+    // 3. certified FP64 recheck of the pairs that can attain the maximum
+    if (work) {
+      const uint32_t sb = smax[g];
+      if (sb >= kInfBits32) {
+        if (wg == 0 && lane == 0) umax[g] = ~0ull;  // non-finite column: invalid candidate
+      } else {
+        const double thr = sqrt((double)__uint_as_float(sb)) - 2.0 * eps32(I.d);
+        const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
+        uint64_t best = 0;
+        for (int b = wg; b < nblk; b += wpi) {
+          if (__uint_as_float(blkmax[g][b]) < thr_sq) continue;
+          int bi, bj;
+          tile_decode(b, nbk, bi, bj);
+          float m[4];
+          screen_block(L, I.ldk, n, I.d, bi, bj, m);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ii = bi * 16 + 4 * (lane >> 4) + v;
+            const int jj = bj * 16 + (lane & 15);
+            if (ii < jj && jj < n && !(m[v] < thr_sq)) {
+              const uint64_t pb = pair_f64_b(c64, I.d, ii, jj);
+              best = pb > best ? pb : best;
+            }
+          }
+        }
+        best = wave_max_u64(best);
+        if (lane == 0) atomicMax(&umax[g], (unsigned long long)best);
+      }
+    }
+    __syncthreads();
+
+    // 4. publish; the group finishing the instance's last candidate finalizes it
+    if (wg == 0 && lane == 0 && c < a.C) {
+      if (work) a.cand_max[(size_t)i * a.C + c] = umax[g];
+      __threadfence();
+      const int old = atomicAdd(&((BState*)a.state)[i].done_count, 1);
+      fin_s[g] = old == a.C - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (wg == 0 && fin_s[g]) {
+      if (skip_inst) {
+        if (lane == 0) ((BState*)a.state)[i].done_count = 0;
+      } else {
+        finalize(a, i);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(a.blocks_done, 1) == (int)gridDim.x - 1) {
+      *a.next_unit = 0;
+      *a.blocks_done = 0;
+      __threadfence();
+    }
+  }
+}
+
+// Random start of every instance (tag 1) and its exact FP64 coherence, one
+// block per instance (grid-stride).
+__global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count, double radius0) {
+  __shared__ unsigned long long umax;
+  const int tid = threadIdx.x;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const BInst I = ((const BInst*)a.inst)[i];
+    double* frame = a.frames + I.frame_off;
+    const int d = I.d;
+    const int nb = (d + 1) >> 1;
+    if (tid == 0) umax = 0;
+    __syncthreads();
+    // draw: one thread per (column, block); norm by a serial pass per column
+    for (int e = tid; e < I.n * nb; e += kThreads) {
+      const int col = e / nb, q = e % nb;
+      const u32x4 ctr = {(uint32_t)(col * nb + q), 0u, 0u, 1u};
+      const u32x4 w = philox4x32_10(ctr, I.seed, I.stream_id);
+      double g0, g1, g2, g3;
+      box_muller(w.x, w.y, g0, g1);
+      box_muller(w.z, w.w, g2, g3);
+      const double h = 0.7071067811865476;
+      double* o = frame + 2 * ((size_t)col * d + 2 * q);
+      o[0] = g0 * h;
+      o[1] = g1 * h;
+      if (2 * q + 1 < d) {
+        o[2] = g2 * h;
+        o[3] = g3 * h;
+      }
+    }
+    __syncthreads();
+    for (int col = tid; col < I.n; col += kThreads) {
+      double* o = frame + 2 * (size_t)col * d;
+      double s = 0.0;
+      for (int q = 0; q < nb; ++q) {
+        const int i0 = 2 * q;
+        double p = o[2 * i0] * o[2 * i0] + o[2 * i0 + 1] * o[2 * i0 + 1];
+        if (i0 + 1 < d) p += o[2 * i0 + 2] * o[2 * i0 + 2] + o[2 * i0 + 3] * o[2 * i0 + 3];
+        s += p;
+      }
+      const double inv = 1.0 / sqrt(s);
+      for (int k = 0; k < 2 * d; ++k) o[k] *= inv;
+    }
+    __threadfence_block();
+    __syncthreads();
+    uint64_t best = 0;
+    const int64_t pairs = (int64_t)I.n * (I.n - 1) / 2;
+    for (int64_t p = tid; p < pairs; p += kThreads) {
+      // p -> (j, k), j < k, row by row
+      int j = 0;
+      int64_t rem = p;
+      while (rem >= I.n - 1 - j) {
+        rem -= I.n - 1 - j;
+        ++j;
+      }
+      const int k = j + 1 + (int)rem;
+      const uint64_t b = pair_f64_b(frame, d, j, k);
+      best = b > best ? b : best;
+    }
+    best = wave_max_u64(best);
+    if ((tid & 63) == 0) atomicMax(&umax, (unsigned long long)best);
+    __syncthreads();
+    if (tid == 0) {
+      BState* S = (BState*)a.state + i;
+      const double mu = bits_mu(umax);
+      S->mu = mu;
+      S->radius = radius0;
+      S->step = 0;
+      S->done_count = 0;
+      const bool done = (I.target_mu > 0.0 && mu <= I.target_mu) || I.max_steps <= 0;
+      S->flags = done ? kFlagDone : 0;
+      if (done) atomicAdd(a.done_instances, 1);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(const BatchArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_step, dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const BatchArgs& a, int count, double radius0, hipStream_t s) {
+  const int grid = count < 4096 ? count : 4096;
+  hipLaunchKernelGGL(k_batch_init, dim3(grid), dim3(kThreads), 0, s, a, count, radius0);
+  return hipGetLastError();
+}
+
+int batch_step_max_blocks() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_step, kThreads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  return per_cu * cus;
+}
+
+size_t batch_inst_bytes() { return sizeof(BInst); }
+size_t batch_state_bytes() { return sizeof(BState); }
+
+void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed, uint32_t stream_id,
+                     int64_t frame_off, double target_mu, int64_t max_steps) {
+  BInst I{};
+  I.n = n;
+  I.d = d;
+  I.wpi = wpi;
+  I.ldk = (2 * d + 3) / 4 * 4 + 1;
+  I.seed = seed;
+  I.stream_id = stream_id;
+  I.frame_off = frame_off;
+  I.target_mu = target_mu;
+  I.max_steps = max_steps;
+  *(BInst*)dst = I;
+}
+
+int batch_lds_floats() { return kLdsFloats; }
+
+}  // namespace trstmi

@@ -131,6 +131,33 @@ struct InitFinishArgs {
   double* mu_out;            // coherence entry: write mu here instead (state pointers null)
 };
 
+// Batched form (batch.hip).
+struct BatchArgs {
+  const void* inst;          // [count] instance descriptors
+  void* state;               // [count] per-instance state
+  const int2* units;         // (instance, first candidate) work units, largest instances first
+  int32_t nunits;
+  int32_t C;                 // candidates per instance per step
+  double* frames;            // frame arena
+  uint64_t* cand_max;        // [count][C] exact FP64 max |G|^2 bits of the step's candidates
+  double* scratch;           // per block and group: one FP64 candidate
+  int64_t scratch_stride;    // doubles per scratch slot
+  int32_t* next_unit;        // work counter (reset by the last block)
+  int32_t* blocks_done;
+  int32_t* done_instances;   // instances that reached DONE
+  double tau, grow, shrink, radius_min, radius_max;
+  double* rep_mu;            // [count][C] or null
+  int32_t* rep_best;         // [count] or null
+};
+
+hipError_t launch_batch_step(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_init(const BatchArgs& a, int count, double radius0, hipStream_t s);
+size_t batch_inst_bytes();
+size_t batch_state_bytes();
+void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed, uint32_t stream_id,
+                     int64_t frame_off, double target_mu, int64_t max_steps);
+int batch_lds_floats();
+
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);

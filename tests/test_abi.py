@@ -127,3 +127,30 @@ def test_binding_refuses_without_gpu_or_library(monkeypatch):
     monkeypatch.setattr(abi, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         abi.lib()
+
+
+def _batch(L, specs, C=8):
+    inst = (abi.BatchInstance * len(specs))()
+    for k, s in enumerate(specs):
+        inst[k].n, inst[k].d = s[0], s[1]
+        inst[k].seed, inst[k].stream_id = 0, k
+        inst[k].max_steps = 10
+        inst[k].waves_per_item = s[2] if len(s) > 2 else 0
+    p = abi.BatchParams(len(specs), C, 0.1, 2.0, 0.5, 1e-12, 1.0, 0.0)
+    return p, inst
+
+
+@pytest.mark.parametrize("specs,ok", [([(16, 4)], True), ([(256, 16)], True), ([(257, 4)], False),
+                                      ([(16, 17)], False), ([(1, 3)], False), ([(256, 16, 1)], False),
+                                      ([(128, 16, 2)], True), ([(64, 16, 1)], True), ([(16, 4, 3)], False)])
+def test_batch_validation(L, specs, ok):
+    p, inst = _batch(L, specs)
+    assert (L.trstmi_batch_workspace_bytes(ctypes.byref(p), inst) > 0) == ok
+
+
+def test_batch_workspace_scales_with_instances(L):
+    p1, i1 = _batch(L, [(16, 4)] * 4)
+    p2, i2 = _batch(L, [(16, 4)] * 64)
+    assert L.trstmi_batch_workspace_bytes(ctypes.byref(p2), i2) > L.trstmi_batch_workspace_bytes(ctypes.byref(p1), i1)
+    p3, i3 = _batch(L, [(16, 4)], C=300)
+    assert L.trstmi_batch_workspace_bytes(ctypes.byref(p3), i3) == 0
