@@ -104,6 +104,37 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
     }
 
 
+def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
+    """The batched workload: 512 independent searches, d uniform in {3..16},
+    N uniform in [d+1, d^2], 64 candidates each, one persistent launch per
+    step; candidate evaluations per second over all instances."""
+    import inputs
+    specs = [{"n": n, "d": d, "seed": 0, "stream_id": k, "max_steps": 10 ** 9}
+             for k, (d, n) in enumerate(inputs.batched_instances(count, seed=0))]
+    b = lib.Batch(specs, candidates=candidates, radius0=0.1).init()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    lib.timing_reset()
+    lib.timing_enable(True)
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.timing_enable(False)
+    ms, cnt = lib.timing_read("batch_step")
+    flops = sum(candidates * flops_per_eval(n, d) for d, n in inputs.batched_instances(count, seed=0))
+    avg_us = 1e3 * ms / cnt
+    return {
+        "workload": f"{count} instances, d in {{3..16}}, N in [d+1, d^2], {candidates} candidates each, "
+                    "FP32 MFMA screen + certified FP64 pair recheck, one persistent launch per step",
+        "evals_per_s": count * candidates * steps / (t1 - t0),
+        "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "kernel_avg_us": avg_us,
+        "algorithmic_tflops": flops / (avg_us * 1e-6) / 1e12,
+        "frac_fp32_peak": flops / (avg_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp32"],
+    }
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle (numpy) on a bounded sample of the workload: one step of
     the BF16-screen form with c candidates, c chosen so the run takes about
@@ -148,6 +179,7 @@ def main():
     ap.add_argument("--other-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,6 +201,8 @@ def main():
         r = run_mode(lib, torch, wl, m, args.other_steps, 2)
         others[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
         others[m]["gram_avg_us"] = r["kernels"][GRAM_KERNEL[m]]["avg_us"]
+
+    batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
 
     g = main_res["kernels"]["gram_bf16"]
     traffic = load_traffic("gram_bf16")
@@ -205,6 +239,7 @@ def main():
         "kernels_avg_us": {k: round(v["avg_us"], 3) for k, v in main_res["kernels"].items()},
         "final_mu": main_res["final_mu"],
         "other_modes": others,
+        "batched": batched,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

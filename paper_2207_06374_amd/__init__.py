@@ -229,11 +229,14 @@ def timing_read(kernel):
 class Batch:
     """Many independent searches advanced together (one persistent launch per
     step).  ``instances``: iterable of dicts with keys n, d and optionally seed,
-    stream_id, target_mu, max_steps, waves_per_item."""
+    stream_id, target_mu, max_steps, waves_per_item (default: the autotuned
+    table, else the library's choice)."""
 
     def __init__(self, instances, candidates=64, radius0=0.1, grow=2.0, shrink=0.5, radius_min=1e-12,
                  radius_max=1.0, near_tie=0.0, device="cuda"):
         torch = _torch()
+        from . import autotune
+        tiles = autotune.load_table()
         inst = list(instances)
         self.count = len(inst)
         self.inst = (_abi.BatchInstance * self.count)()
@@ -244,7 +247,8 @@ class Batch:
             I.stream_id = int(spec.get("stream_id", k))
             I.target_mu = float(spec.get("target_mu", 0.0))
             I.max_steps = int(spec.get("max_steps", 1000))
-            I.waves_per_item = int(spec.get("waves_per_item", 0))
+            w = spec.get("waves_per_item")
+            I.waves_per_item = int(autotune.choose(tiles, I.n, I.d) if w is None else w)
         self.params = _abi.BatchParams(self.count, int(candidates), float(radius0), float(grow), float(shrink),
                                        float(radius_min), float(radius_max), float(near_tie))
         nbytes = _abi.lib().trstmi_batch_workspace_bytes(ctypes.byref(self.params), self.inst)

@@ -1,0 +1,104 @@
+"""Tile autotuner for the batched form.
+
+The batched kernel processes each candidate with 1, 2 or 4 wavefronts
+(``waves_per_item``).  The choice changes only speed, never results (each
+pair is computed by the same code whatever the split).  This module times
+every feasible choice on homogeneous batches of one (d, N) class and keeps the
+fastest per class in a JSON table; ``Batch`` consults the table for instances
+that do not fix ``waves_per_item`` themselves.
+
+Run on the GPU:  python -m paper_2207_06374_amd.autotune [--out PATH]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch_tiles.json")
+N_BUCKETS = (16, 32, 64, 128, 256)
+LDS_FLOATS = 8448
+
+
+def ldk(d):
+    return (2 * d + 3) // 4 * 4 + 1
+
+
+def feasible(n, d):
+    return [w for w in (1, 2, 4) if n * ldk(d) * (4 // w) <= LDS_FLOATS]
+
+
+def classes(d_lo=3, d_hi=16):
+    """(d, n_max) classes covering N in [d + 1, min(d^2, 256)]."""
+    out = []
+    for d in range(d_lo, d_hi + 1):
+        n_hi = min(d * d, 256)
+        lo = d + 1
+        for b in N_BUCKETS:
+            if b >= lo:
+                out.append((d, min(b, n_hi)))
+            if b >= n_hi:
+                break
+    return out
+
+
+def load_table(path=TABLE_PATH):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def choose(table, n, d):
+    """waves_per_item for an (n, d) instance: the entry of the same d with the
+    smallest n_max >= n; 0 (library default) when the table has none."""
+    if not table:
+        return 0
+    best = None
+    for e in table.get("entries", []):
+        if e["d"] == d and e["n_max"] >= n and (best is None or e["n_max"] < best["n_max"]):
+            best = e
+    if best is None or best["wpi"] not in feasible(n, d):
+        return 0
+    return int(best["wpi"])
+
+
+def time_class(lib, torch, d, n, wpi, count=128, candidates=64, steps=6):
+    specs = [{"n": n, "d": d, "seed": 0, "stream_id": k, "max_steps": 10 ** 9, "waves_per_item": wpi}
+             for k in range(count)]
+    b = lib.Batch(specs, candidates=candidates).init()
+    b.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e6
+
+
+def autotune(out=TABLE_PATH, candidates=64, count=128, steps=6, verbose=True):
+    import torch
+
+    import paper_2207_06374_amd as lib
+    entries = []
+    for d, n in classes():
+        times = {w: time_class(lib, torch, d, n, w, count, candidates, steps) for w in feasible(n, d)}
+        w = min(times, key=times.get)
+        entries.append({"d": d, "n_max": n, "wpi": w, "us_per_step": {str(k): round(v, 2) for k, v in times.items()}})
+        if verbose:
+            print(f"d={d:2d} n<={n:3d}: " + "  ".join(f"wpi={k}: {v:8.1f} us" for k, v in times.items())
+                  + f"  -> {w}", flush=True)
+    table = {"version": 1, "candidates": candidates, "instances_per_class": count, "entries": entries}
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    return table
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE_PATH)
+    ap.add_argument("--count", type=int, default=128)
+    ap.add_argument("--steps", type=int, default=6)
+    args = ap.parse_args()
+    autotune(args.out, count=args.count, steps=args.steps)

@@ -478,7 +478,7 @@ trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_inst
     for (int c0 = 0; c0 < p->candidates; c0 += per) L.unit_list.push_back(make_int2(i, c0));
   }
   L.nunits = (int)L.unit_list.size();
-  L.grid = L.nunits < kBatchGridCap ? L.nunits : kBatchGridCap;
+  L.grid = L.nunits < kBatchGridCap ? L.nunits : kBatchGridCap;  // scratch is sized for kBatchGridCap blocks
   L.scratch_stride = (max_frame + 31) / 32 * 32;
   size_t o = 0;
   L.hdr = o;
@@ -497,6 +497,18 @@ trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_inst
   o = align256(o + (size_t)kBatchGridCap * 4 * L.scratch_stride * 8);
   L.total = o;
   return TRSTMI_OK;
+}
+
+// Blocks of a step launch: the resident capacity of the device (queried once),
+// at most the number of units and the scratch slots of the workspace.
+int batch_grid(const BatchLayout& L) {
+  static int cap = 0;
+  if (cap == 0) {
+    const int m = batch_step_max_blocks();
+    cap = m > 0 ? m : 1;
+  }
+  int g = L.grid < cap ? L.grid : cap;
+  return g > 0 ? g : 1;
 }
 
 BatchArgs batch_args(const trstmi_batch_params* p, const BatchLayout& L, char* ws) {
@@ -700,24 +712,23 @@ trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, vo
   const int64_t left = p->max_steps > t0 ? p->max_steps - t0 : 0;
   const int64_t max_chunks = left / chunk + 2;
 
+  // Capture one chunk of steps into a graph (relaxed mode: calls made by other
+  // threads cannot invalidate it).  If capture is not possible the chunk is
+  // launched directly instead.
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  if (stream != nullptr) {
-    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      trstmi_status cst = TRSTMI_OK;
-      for (int i = 0; i < chunk && cst == TRSTMI_OK; ++i) cst = enqueue_step(p, state, ws, nullptr, nullptr, stream);
-      hipError_t e2 = hipStreamEndCapture(stream, &graph);
-      if (cst != TRSTMI_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cst;
-      }
-      TRY_HIP(e2, "end capture");
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return hip_fail(e, "graph instantiate");
-      }
+  if (stream != nullptr && hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+    trstmi_status cst = TRSTMI_OK;
+    for (int i = 0; i < chunk && cst == TRSTMI_OK; ++i) cst = enqueue_step(p, state, ws, nullptr, nullptr, stream);
+    const hipError_t e2 = hipStreamEndCapture(stream, &graph);
+    if (cst == TRSTMI_OK && e2 == hipSuccess && graph &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+      exec = nullptr;
+    if (!exec) {
+      if (graph) (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      (void)hipGetLastError();
+      g_last_error.clear();
     }
   }
   trstmi_status result = TRSTMI_OK;
@@ -812,8 +823,9 @@ trstmi_status trstmi_batch_step(const trstmi_batch_params* p, const trstmi_batch
   BatchArgs b = batch_args(p, L, (char*)workspace);
   b.rep_mu = rep_mu;
   b.rep_best = rep_best;
+  const int grid = batch_grid(L);
   for (int32_t l = 0; l < launches; ++l)
-    TRY_HIP(TIMED("batch_step", stream, launch_batch_step(b, L.grid, stream)), "batch step");
+    TRY_HIP(TIMED("batch_step", stream, launch_batch_step(b, grid, stream)), "batch step");
   return TRSTMI_OK;
 }
 
@@ -833,9 +845,9 @@ trstmi_status trstmi_batch_run(const trstmi_batch_params* p, const trstmi_batch_
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   if (stream != nullptr && done < p->count && max_chunks > 0) {
-    TRY_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "batch capture");
+    TRY_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed), "batch capture");
     hipError_t le = hipSuccess;
-    for (int32_t l = 0; l < chunk && le == hipSuccess; ++l) le = launch_batch_step(b, L.grid, stream);
+    for (int32_t l = 0; l < chunk && le == hipSuccess; ++l) le = launch_batch_step(b, batch_grid(L), stream);
     hipError_t ce = hipStreamEndCapture(stream, &graph);
     if (le != hipSuccess || ce != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -853,7 +865,7 @@ trstmi_status trstmi_batch_run(const trstmi_batch_params* p, const trstmi_batch_
     if (exec) {
       e = hipGraphLaunch(exec, stream);
     } else {
-      for (int32_t l = 0; l < chunk && e == hipSuccess; ++l) e = launch_batch_step(b, L.grid, stream);
+      for (int32_t l = 0; l < chunk && e == hipSuccess; ++l) e = launch_batch_step(b, batch_grid(L), stream);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&done, b.done_instances, 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -152,6 +152,7 @@ struct BatchArgs {
 
 hipError_t launch_batch_step(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_init(const BatchArgs& a, int count, double radius0, hipStream_t s);
+int batch_step_max_blocks();
 size_t batch_inst_bytes();
 size_t batch_state_bytes();
 void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed, uint32_t stream_id,

@@ -1,0 +1,59 @@
+"""GPU checks of the serving form: continuous admission under a memory cap,
+and every request's result equal to the same request solved alone."""
+
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2207_06374_amd")
+serve = pytest.importorskip("paper_2207_06374_amd.serve")
+
+
+def _requests(count, seed, dims=(4, 8), max_steps=120):
+    out = []
+    for r in inputs.serving_requests(count, seed=seed, mean_gap_s=0.003, dims=dims):
+        out.append(serve.Request(id=r["id"], arrival=r["arrival"], n=r["n"], d=r["d"], seed=r["seed"],
+                                 max_steps=max_steps))
+    return out
+
+
+def test_serving_mix_equals_alone_and_respects_pool_cap():
+    reqs = _requests(8, seed=2)
+    sizes = [serve.footprint(serve.request_params(r, 32, lib.MODE_BF16_SCREEN, 8, 0.05, 1.10)) for r in reqs]
+    cap = 2 * max(sizes) + 1024          # at most about two requests resident at a time
+    srv = serve.Server(pool_bytes=cap, max_active=8, streams=4, chunk=16, candidates=32, mode="bf16")
+    stats = srv.run(reqs)
+    print(stats, flush=True)
+    assert stats["done"] == len(reqs) and stats["rejected"] == 0 and stats["errors"] == 0
+    assert stats["pool_peak_bytes"] <= cap
+    for r in reqs:
+        assert r.admit >= r.arrival and r.finish >= r.admit
+        F, mu, radius, step, flags = serve.solve_alone(r, candidates=32, mode="bf16", chunk=16)
+        assert mu == r.mu and step == r.steps, f"request {r.id}"
+        assert r.steps <= r.max_steps
+        assert (mu <= serve.welch_bound(r.n, r.d) * 1.10) == r.reached
+
+
+def test_oversized_request_is_rejected_not_queued():
+    reqs = _requests(3, seed=4)
+    big = serve.Request(id=99, arrival=0.0, n=1024, d=128, max_steps=5)
+    small_cap = max(serve.footprint(serve.request_params(r, 32, lib.MODE_BF16_SCREEN, 8, 0.05, 1.10))
+                    for r in reqs) + 4096
+    srv = serve.Server(pool_bytes=small_cap, chunk=16, candidates=32)
+    stats = srv.run(reqs + [big])
+    assert big.status == "rejected" and "exceeds" in big.error
+    assert stats["done"] == 3 and stats["rejected"] == 1
+
+
+def test_serving_reaches_target_on_easy_requests():
+    """Generous targets are met before the step limit and stop the solve."""
+    reqs = [serve.Request(id=k, arrival=0.001 * k, n=8, d=4, seed=k, target_mu=0.95, max_steps=2000)
+            for k in range(4)]
+    srv = serve.Server(pool_bytes=1 << 26, chunk=8, candidates=32)
+    stats = srv.run(reqs)
+    assert stats["reached_target"] == 4
+    assert all(r.steps < 2000 and r.mu <= 0.95 for r in reqs)
