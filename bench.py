@@ -36,6 +36,10 @@ KERNEL_SOURCE = {"gram_bf16": "gram_bf16.hip", "gram_f32": "gram_f32.hip", "gram
 METRIC = "candidate coherence evals/s at N=4096,d=64 (% roofline); p50/p99 solve latency"
 
 
+def log(text):
+    print(f"[bench] {text}", file=sys.stderr, flush=True)
+
+
 def flops_per_eval(n, d):
     """Algorithmic flops of one candidate's Gram + coherence: the strict upper
     triangle has n(n-1)/2 complex inner products of length d, 8 real flops per
@@ -135,6 +139,23 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
     }
 
 
+def run_serving(lib, count, max_steps, pool_gib):
+    """The serving workload: Poisson arrivals (mean gap 5 ms), d in
+    {8, 16, 32, 64, 128}, N uniform in [2d, 8d], each solved to 1.10 x Welch or
+    max_steps with BF16-screened / FP64-verified steps, admitted by device
+    footprint into a capped pool."""
+    import inputs
+    from paper_2207_06374_amd import serve
+    reqs = [serve.Request(id=r["id"], arrival=r["arrival"], n=r["n"], d=r["d"], seed=r["seed"], max_steps=max_steps)
+            for r in inputs.serving_requests(count, seed=1)]
+    srv = serve.Server(pool_bytes=int(pool_gib * 2 ** 30), max_active=16, chunk=64, candidates=64, mode="bf16")
+    stats = srv.run(reqs, progress=log)
+    stats["workload"] = (f"{count} requests, Poisson arrivals mean gap 5 ms, d in {{8,16,32,64,128}}, N in [2d, 8d], "
+                         f"target 1.10 x Welch or {max_steps} steps, 64 candidates, BF16 screen + FP64 recheck, "
+                         f"pool {pool_gib} GiB, 16 slots (one stream each)")
+    return stats
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle (numpy) on a bounded sample of the workload: one step of
     the BF16-screen form with c candidates, c chosen so the run takes about
@@ -180,6 +201,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--serving-requests", type=int, default=16, help="requests of the serving run (0: skip)")
+    ap.add_argument("--serving-max-steps", type=int, default=5000)
+    ap.add_argument("--serving-pool-gib", type=float, default=8.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -196,13 +220,18 @@ def main():
 
     wl = inputs.LARGE
     main_res = run_mode(lib, torch, wl, "bf16", args.steps, args.warmup)
+    log(f"bf16 screen: {main_res['evals_per_s']:.0f} evals/s")
     others = {}
     for m in [x for x in args.other_modes.split(",") if x]:
         r = run_mode(lib, torch, wl, m, args.other_steps, 2)
+        log(f"{m}: {r['evals_per_s']:.0f} evals/s")
         others[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
         others[m]["gram_avg_us"] = r["kernels"][GRAM_KERNEL[m]]["avg_us"]
 
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
+    log("batched done")
+    serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib)
+               if args.serving_requests > 0 else None)
 
     g = main_res["kernels"]["gram_bf16"]
     traffic = load_traffic("gram_bf16")
@@ -240,8 +269,10 @@ def main():
         "final_mu": main_res["final_mu"],
         "other_modes": others,
         "batched": batched,
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         line["cpu_baseline"]["gpu_speedup"] = main_res["evals_per_s"] / line["cpu_baseline"]["value"]
     print(json.dumps(line), flush=True)

@@ -2,8 +2,8 @@
 
 Requests (N, d, seed, arrival time) arrive over time.  A request is admitted
 as soon as a slot is free and its device footprint (workspace + frame +
-scalars) fits in the memory pool; it then runs on the GPU on one of a few HIP
-streams, concurrently with the requests already running, until its
+scalars) fits in the memory pool; it then runs on the GPU on its slot's own
+HIP stream, concurrently with the requests already running, until its
 coherence reaches the target (default 1.10 x the Welch bound) or its step
 limit.  Frames, radii and step counters stay resident in device memory for
 the whole solve; the host only polls a done flag once per chunk of
@@ -115,14 +115,16 @@ def footprint(params):
 class Server:
     """Continuous-admission solve server on one GPU."""
 
-    def __init__(self, pool_bytes, max_active=8, streams=4, chunk=64, candidates=64, mode="bf16", recheck_topk=8,
+    def __init__(self, pool_bytes, max_active=8, chunk=64, candidates=64, mode="bf16", recheck_topk=8,
                  radius0=0.05, target_factor=1.10, device="cuda"):
         torch = _torch()
         self.torch = torch
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
         self.alloc = OffsetAllocator(pool_bytes)
         self.max_active = int(max_active)
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(int(streams))]
+        # one stream per slot: a stream is never shared by two running requests
+        # (each captures its chunk of steps into a graph on its own stream)
+        self.free_streams = [torch.cuda.Stream(device=device) for _ in range(self.max_active)]
         self.chunk = int(chunk)
         self.candidates = int(candidates)
         self.mode = MODES.get(mode, mode)
@@ -131,7 +133,6 @@ class Server:
         self.target_factor = float(target_factor)
         self.lock = threading.Condition()
         self.active = 0
-        self.next_stream = 0
 
     def _views(self, off, params):
         """State tensors and workspace carved out of the pool at `off`."""
@@ -164,19 +165,27 @@ class Server:
         req.finish = time.perf_counter() - t0
         with self.lock:
             self.alloc.release(off, size)
+            self.free_streams.append(stream)
             self.active -= 1
             self.lock.notify_all()
 
-    def run(self, requests: List[Request], poll_s=0.002):
+    def run(self, requests: List[Request], poll_s=0.002, progress=None, progress_every_s=10.0):
         """Serve `requests` (arrival times relative to now).  Returns a dict of
-        statistics; per-request results are written into the requests."""
+        statistics; per-request results are written into the requests.
+        `progress(text)`, if given, is called about every progress_every_s."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
         t0 = time.perf_counter()
+        last_report = t0
         queue = []
         threads = []
         k = 0
         while True:
             now = time.perf_counter() - t0
+            if progress and time.perf_counter() - last_report >= progress_every_s:
+                last_report = time.perf_counter()
+                finished = sum(r.status in ("done", "rejected", "error") for r in reqs)
+                progress(f"serving t={now:.1f}s finished={finished}/{len(reqs)} active={self.active} "
+                         f"queued={len(queue)}")
             while k < len(reqs) and reqs[k].arrival <= now:      # arrivals
                 r = reqs[k]
                 k += 1
@@ -200,8 +209,7 @@ class Server:
                     self.active += 1
                     r.status = "running"
                     r.admit = time.perf_counter() - t0
-                    stream = self.streams[self.next_stream % len(self.streams)]
-                    self.next_stream += 1
+                    stream = self.free_streams.pop()
                     th = threading.Thread(target=self._run_one, args=(r, params, off, size, stream, t0),
                                           daemon=True)
                     threads.append(th)
@@ -238,6 +246,7 @@ def summarize(reqs, wall, candidates, peak_bytes, cap_bytes):
         "wall_s": wall,
         "pool_peak_bytes": int(peak_bytes),
         "pool_cap_bytes": int(cap_bytes),
+        "first_error": next((r.error for r in reqs if r.status == "error"), ""),
     }
 
 

@@ -25,7 +25,7 @@ def test_serving_mix_equals_alone_and_respects_pool_cap():
     reqs = _requests(8, seed=2)
     sizes = [serve.footprint(serve.request_params(r, 32, lib.MODE_BF16_SCREEN, 8, 0.05, 1.10)) for r in reqs]
     cap = 2 * max(sizes) + 1024          # at most about two requests resident at a time
-    srv = serve.Server(pool_bytes=cap, max_active=8, streams=4, chunk=16, candidates=32, mode="bf16")
+    srv = serve.Server(pool_bytes=cap, max_active=8, chunk=16, candidates=32, mode="bf16")
     stats = srv.run(reqs)
     print(stats, flush=True)
     assert stats["done"] == len(reqs) and stats["rejected"] == 0 and stats["errors"] == 0
