@@ -190,6 +190,19 @@ def cpu_baseline(wl, budget_s):
     }
 
 
+def copy_calibration(torch, mib):
+    """Three device-to-device copies of ``mib`` MiB: the counter readings of a
+    kernel whose HBM traffic is known (read mib, write mib), which scale the
+    FETCH_SIZE / WRITE_SIZE readings of the Gram kernel to bytes."""
+    n = mib * 2 ** 20 // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +217,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=16, help="requests of the serving run (0: skip)")
     ap.add_argument("--serving-max-steps", type=int, default=5000)
     ap.add_argument("--serving-pool-gib", type=float, default=8.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run three plain device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -214,6 +229,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
+        return
 
     import inputs
     import paper_2207_06374_amd as lib
