@@ -45,13 +45,103 @@ __device__ __forceinline__ double word_to_unit(uint32_t w) {
   return ((double)w + 0.5) * 0x1p-32;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 elementary functions for the uniforms of word_to_unit, u in
+// [2^-33, 1 - 2^-33].  Written for this argument range only (no special
+// cases), each within a few ulp; the series are Taylor series truncated where
+// the first omitted term is below 2^-56 of the result.
+// ---------------------------------------------------------------------------
+
+// Reciprocal of d > 0: hardware estimate, two Newton steps, then the quotient
+// n / d with one residual correction.
+__device__ __forceinline__ double div_pos(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double q = n * r;
+  return fma(fma(-d, q, n), r, q);
+}
+
+// ln u.  u = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) with
+// s = (m - 1) / (m + 1), |s| <= 0.1716, so s^2 <= 0.0295 and the odd series
+// 2 (s + s^3/3 + ... + s^19/19) leaves < 2^-57; e ln 2 uses a two-part ln 2
+// whose leading part times e is exact.
+__device__ __forceinline__ double log_unit(double u) {
+  double m = __builtin_amdgcn_frexp_mant(u);  // [1/2, 1)
+  int e = __builtin_amdgcn_frexp_exp(u);
+  if (m < 0.7071067811865476) {
+    m += m;
+    e -= 1;
+  }
+  const double s = div_pos(m - 1.0, m + 1.0);
+  const double z = s * s;
+  double p = 2.0 / 19;
+  p = fma(p, z, 2.0 / 17);
+  p = fma(p, z, 2.0 / 15);
+  p = fma(p, z, 2.0 / 13);
+  p = fma(p, z, 2.0 / 11);
+  p = fma(p, z, 2.0 / 9);
+  p = fma(p, z, 2.0 / 7);
+  p = fma(p, z, 2.0 / 5);
+  p = fma(p, z, 2.0 / 3);
+  const double lnm = fma(s, z * p, s + s);
+  const double ln2_hi = 0x1.62e42feep-1;           // ln 2 to 32 bits
+  const double ln2_lo = 0x1.a39ef35793c76p-33;     // ln 2 - ln2_hi
+  const double fe = (double)e;
+  return fma(fe, ln2_hi, fma(fe, ln2_lo, lnm));
+}
+
+// sqrt(a) for a > 0 in the normal range: hardware 1/sqrt estimate, one
+// coupled Newton (Goldschmidt) step, one residual correction.
+__device__ __forceinline__ double sqrt_pos(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  return fma(fma(-g, g, a), h, g);
+}
+
+// (sin 2 pi u, cos 2 pi u).  j = rint(4u) quarter turns and t = u - j/4 in
+// [-1/8, 1/8] are exact; x = 2 pi t, |x| <= pi/4, sin x through x^17 and
+// cos x through x^16; the quarter turns rotate the pair.
+__device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
+  const double j = rint(4.0 * u);
+  const double t = fma(j, -0.25, u);
+  const double x = t * 6.283185307179586;  // 2 pi
+  const double z = x * x;
+  double ps = 1.0 / 355687428096000.0;                  // 1/17!
+  ps = fma(ps, z, -1.0 / 1307674368000.0);              // 1/15!
+  ps = fma(ps, z, 1.0 / 6227020800.0);                  // 1/13!
+  ps = fma(ps, z, -1.0 / 39916800.0);                   // 1/11!
+  ps = fma(ps, z, 1.0 / 362880.0);                      // 1/9!
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  const double sx = fma(x * z, ps, x);
+  double pc = 1.0 / 20922789888000.0;                   // 1/16!
+  pc = fma(pc, z, -1.0 / 87178291200.0);                // 1/14!
+  pc = fma(pc, z, 1.0 / 479001600.0);                   // 1/12!
+  pc = fma(pc, z, -1.0 / 3628800.0);                    // 1/10!
+  pc = fma(pc, z, 1.0 / 40320.0);
+  pc = fma(pc, z, -1.0 / 720.0);
+  pc = fma(pc, z, 1.0 / 24.0);
+  pc = fma(pc, z, -0.5);
+  const double cx = fma(z, pc, 1.0);
+  const int q = (int)j & 3;
+  const double a = (q & 1) ? cx : sx;
+  const double b = (q & 1) ? sx : cx;
+  sn = (q & 2) ? -a : a;
+  cs = ((q + 1) & 2) ? -b : b;
+}
+
 // Box-Muller (1958): (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0), in FP64.
 __device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, double& g0, double& g1) {
   const double u0 = word_to_unit(w0);
   const double u1 = word_to_unit(w1);
-  const double r = sqrt(-2.0 * log(u0));
+  const double r = sqrt_pos(-2.0 * log_unit(u0));
   double s, c;
-  sincospi(2.0 * u1, &s, &c);
+  sincos_2pi(u1, s, c);
   g0 = r * c;
   g1 = r * s;
 }

@@ -16,7 +16,9 @@
 // read and converted once per segment.  The 128 B columns of one tile sit in
 // LDS (16 bytes of padding per column: 16 lanes reading 16 columns at one k
 // offset hit distinct banks); the next tile's columns are prefetched into
-// registers while the current tile is computed.  Per tile, the wave sweeps 8
+// registers while the current tile is computed and stored into a second LDS
+// buffer, so each tile costs one barrier.  Per-tile wave maxima are kept in
+// lanes and written once per segment.  Per tile, the wave sweeps 8
 // column blocks of 16 columns: 2 x 2 x K/32 MFMAs per block, then
 // |G|^2 = Re^2 + Im^2 and a running max on the float bit patterns (integer
 // max keeps NaN, which marks an invalid candidate, above every finite
@@ -195,12 +197,15 @@ __device__ __forceinline__ uint32_t tile_max_wave(const ARows<KS>& A, const uint
   uint32_t m[8];
   if (!diag) {
     // fragments of block cb + 1 are read while block cb multiplies; the
-    // epilogue of block cb - 1 runs behind the MFMAs of block cb
+    // epilogue of block cb - 1 runs in the second half of block cb's MFMAs,
+    // when those results are complete.  The scheduling groups pin this order
+    // (the compiler would otherwise sink the LDS reads next to their use).
     v4f32 xR[2], xI[2], yR[2], yI[2];
     u32x4 bp[KS], bq[KS];
     read_frags<KS>(Bs, 0, bp);
     read_frags<KS>(Bs, 1, bq);
     mma_frags<KS>(A, bp, xR, xI);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int cb = 1; cb < T / 16; ++cb) {
       if (cb & 1) {
@@ -213,6 +218,20 @@ __device__ __forceinline__ uint32_t tile_max_wave(const ARows<KS>& A, const uint
         sq_mag(yR, yI, m);
       }
       best = max_of(best, m);
+#pragma unroll
+      for (int i = 0; i < KS; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+      }
+#pragma unroll
+      for (int i = KS; i < 2 * KS; ++i) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+      for (int i = 2 * KS; i < 4 * KS; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // epilogue VALU
+      }
+      __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     sq_mag(yR, yI, m);
     return max_of(best, m);
@@ -262,7 +281,12 @@ __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) 
   seg_decode(seg, a.nt, bi, bj0, bj1);
   const int tiles = a.nt * (a.nt + 1) / 2;
 
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * (32 * KS + 8)];
+  // Two B tiles while two blocks still fit in LDS (2d <= 128): tile bj + 1
+  // is stored into the buffer tile bj - 1 used, so one barrier per tile
+  // suffices.  One tile (and a barrier before the store) beyond that.
+  constexpr int kBuf = T * (32 * KS + 8);
+  constexpr int kNB = KS <= 4 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kNB * kBuf];
   __shared__ uint32_t red[4];
   const uint16_t* base = (const uint16_t*)a.cand + (size_t)slot * a.slot_stride;
   const int lane = threadIdx.x & 63;
@@ -277,21 +301,27 @@ __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) 
   if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.n, bj0 + 1, pf);
 
   uint32_t cmax = 0;
+  uint32_t tile_lane = 0;
   for (int bj = bj0; bj < bj1; ++bj) {
-    const uint32_t tmax = tile_max_wave<KS>(A, Bs, bj == bi);
+    const int buf = kNB == 2 ? (bj - bj0) & 1 : 0;
+    const uint32_t tmax = tile_max_wave<KS>(A, Bs + buf * kBuf, bj == bi);
     cmax = tmax > cmax ? tmax : cmax;
     if (a.tile_max) {
+      // lane k keeps the wave maximum of tile bj0 + k; stored after the
+      // segment, so no tile waits on a global store
       const uint32_t wm = wave_max_u32_dpp(tmax);
-      if (lane == 0) a.tile_max[((size_t)slot * tiles + tile_linear(bi, bj, a.nt)) * 4 + w] = wm;
+      if (lane == bj - bj0) tile_lane = wm;
     }
     if (bj + 1 < bj1) {
-      __syncthreads();  // every wave is done with this tile's columns
-      store_cols<KS>(pf, Bs);
-      __syncthreads();
+      if (kNB == 1) __syncthreads();  // every wave is done with this tile's columns
+      store_cols<KS>(pf, Bs + (kNB == 2 ? buf ^ 1 : 0) * kBuf);
+      __syncthreads();  // tile bj + 1 is in LDS; every wave is past tile bj
       if (bj + 2 < bj1) fetch_cols<KS>(base, a.n, bj + 2, pf);
     }
   }
 
+  if (a.tile_max && lane < bj1 - bj0)
+    a.tile_max[((size_t)slot * tiles + tile_linear(bi, bj0 + lane, a.nt)) * 4 + w] = tile_lane;
   cmax = wave_max_u32_dpp(cmax);
   if (lane == 0) red[w] = cmax;
   __syncthreads();
