@@ -9,33 +9,36 @@
 // so both parts share the B operand u_k, and v_j is formed in registers from
 // the A rows (one funnel shift and one sign flip per 32-bit (re, im) pair).
 //
-// Main kernel (2d <= 256): a 256-thread block owns a row segment: tile row
-// block bi (128 frame columns) against up to kSeg consecutive tile column
-// blocks bj >= bi of the strict upper triangle.  Each wave keeps its 32 rows
-// (u and v for the whole K) in VGPRs for the whole segment, so the A side is
-// read and converted once per segment.  The 128 B columns of one tile sit in
-// LDS (16 bytes of padding per column: 16 lanes reading 16 columns at one k
-// offset hit distinct banks); the next tile's columns are prefetched into
-// registers while the current tile is computed and stored into a second LDS
-// buffer, so each tile costs one barrier.  Per-tile wave maxima are kept in
-// lanes and written once per segment.  Per tile, the wave sweeps 8
-// column blocks of 16 columns: 2 x 2 x K/32 MFMAs per block, then
-// |G|^2 = Re^2 + Im^2 and a running max on the float bit patterns (integer
-// max keeps NaN, which marks an invalid candidate, above every finite
-// value).  Off-diagonal tiles run a straight-line loop that issues the MFMAs
-// of the next column block before the epilogue of the current one, so matrix
-// and vector work of one wave overlap.  Diagonal tiles skip the column blocks
-// wholly below the diagonal and keep j > i; rows/columns past N are zero and
+// Wide kernel (2d <= 128): a 256-thread block owns a row segment: two tile
+// rows (256 frame columns) against up to kSegK consecutive 128-column tiles
+// of the strict upper triangle.  Each wave keeps 64 rows (u and v for the
+// whole K) in VGPRs for the whole segment, so the A side is read and
+// converted once per segment, and every B column staged in LDS feeds 256
+// rows.  The 128 B columns of one tile sit in LDS (16 bytes of padding per
+// column: 16 lanes reading 16 columns at one k offset hit distinct banks);
+// the next tile's columns are prefetched into registers while the current
+// tile is computed and stored into a second LDS buffer, so each tile costs
+// one barrier.  Per tile, the wave sweeps 8 column blocks of 16 columns:
+// 4 x 2 x K/32 MFMAs per block.  The accumulators of block cb are folded
+// (|G|^2 = Re^2 + Im^2, running max on the float bit patterns; the integer
+// max keeps NaN, which marks an invalid candidate, above every finite value)
+// row block by row block just before the first MFMAs of block cb + 1 reuse
+// them, and scheduling groups interleave that epilogue and the LDS reads of
+// block cb + 2 with the MFMAs.  Diagonal tiles skip the column blocks wholly
+// below the wave's rows and keep j > i; rows/columns past N are zero and
 // contribute 0.
+//
+// Narrow kernel (128 < 2d <= 256): one tile row (128 frame columns) per
+// segment, 32 rows per wave, the same pipelining with two accumulator sets.
 //
 // Blocks are mapped XCD-aware: the dispatcher deals consecutive block ids to
 // the 8 XCDs in turn, so block b runs on XCD b mod 8; all segments of
 // candidate c go to blocks with b mod 8 = c mod 8, which keeps a candidate's
 // columns in one XCD's L2.
 //
-// Each wave writes its maximum for every tile (used to prune the FP64
-// recheck) and the block updates the candidate's running maximum with one
-// atomic.  The FP64 recheck of the best screened candidates (k_recheck_pairs)
+// Each wave keeps its maximum for every tile in a lane and writes them once
+// per segment (they prune the FP64 recheck); the block updates the
+// candidate's running maximum with one atomic.  The FP64 recheck of the best screened candidates (k_recheck_pairs)
 // reuses the per-tile code on the tiles that can hold the exact maximum and
 // evaluates only the pairs that can attain it in FP64.
 //
@@ -267,8 +270,8 @@ __device__ __forceinline__ void seg_decode(int s, int nt, int& bi, int& bj0, int
   bj1 = bj0 + kSeg < nt ? bj0 + kSeg : nt;
 }
 
-// Two blocks per CU while the whole-K rows fit (2d <= 160); one block with the
-// full register file (VGPRs and AGPRs) beyond that.
+// Narrow kernel.  Two blocks per CU while the whole-K rows fit (2d <= 160);
+// one block with the full register file (VGPRs and AGPRs) beyond that.
 template <int KS>
 __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) {
   if (a.flags && (*a.flags & kFlagDone)) return;
@@ -281,9 +284,9 @@ __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) 
   seg_decode(seg, a.nt, bi, bj0, bj1);
   const int tiles = a.nt * (a.nt + 1) / 2;
 
-  // Two B tiles while two blocks still fit in LDS (2d <= 128): tile bj + 1
-  // is stored into the buffer tile bj - 1 used, so one barrier per tile
-  // suffices.  One tile (and a barrier before the store) beyond that.
+  // Two B tiles while two blocks still fit in LDS: tile bj + 1 is stored
+  // into the buffer tile bj - 1 used, so one barrier per tile suffices.  One
+  // tile (and a barrier before the store) beyond that.
   constexpr int kBuf = T * (32 * KS + 8);
   constexpr int kNB = KS <= 4 ? 2 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t Bs[kNB * kBuf];
@@ -329,6 +332,210 @@ __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) 
     const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
     atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Wide kernel helpers: 64 rows per wave.
+// ---------------------------------------------------------------------------
+template <int KS>
+struct QRows {
+  u32x4 u[4][KS];
+  u32x4 v[4][KS];
+};
+
+template <int KS>
+__device__ __forceinline__ void load_rows_q(const uint16_t* base, int ldk, int n, int row0, QRows<KS>& A) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int row = row0 + rb * 16 + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      u32x4 u = {0u, 0u, 0u, 0u};
+      if (row < n) u = *(const u32x4*)(base + (size_t)row * ldk + ks * 32 + 8 * (lane >> 4));
+      A.u[rb][ks] = u;
+      A.v[rb][ks] = swap_negate(u);
+    }
+  }
+}
+
+// |G|^2 bits of row block rb's 16 x 16 outputs folded into best.
+__device__ __forceinline__ uint32_t fold_rb(uint32_t best, v4f32 R, v4f32 I) {
+  uint32_t m[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) m[v] = __float_as_uint(fmaf(R[v], R[v], I[v] * I[v]));
+  return max3u(max3u(m[0], m[1], m[2]), m[3], best);
+}
+
+// One column block: the epilogue of the previous block (R, I on entry) is
+// folded row block by row block just before the first MFMAs that overwrite
+// those accumulators, then the remaining K steps follow.
+template <int KS, bool EPI>
+__device__ __forceinline__ void qblock(const QRows<KS>& A, const u32x4 b[KS], v4f32 R[4], v4f32 I[4],
+                                       uint32_t& best) {
+  const v4f32 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    if (EPI) best = fold_rb(best, R[rb], I[rb]);
+    R[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.u[rb][0]), as_bf16x8(b[0]), z, 0, 0, 0);
+    I[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][0]), as_bf16x8(b[0]), z, 0, 0, 0);
+  }
+#pragma unroll
+  for (int ks = 1; ks < KS; ++ks)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      R[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.u[rb][ks]), as_bf16x8(b[ks]), R[rb], 0, 0, 0);
+      I[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][ks]), as_bf16x8(b[ks]), I[rb], 0, 0, 0);
+    }
+}
+
+template <int KS>
+__device__ __forceinline__ void sched_qblock(bool reads) {
+  // rb-interleaved epilogue with the first K step, LDS reads of the next
+  // block spread over the following MFMAs
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < KS; ++i) {
+    if (reads) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, 8 * KS, 0);
+}
+
+// Max |G|^2 bits over this wave's 64 rows (tile offset roff) against the 128
+// LDS columns of one tile; on a diagonal tile only pairs with j > i count.
+template <int KS>
+__device__ __forceinline__ uint32_t tile_max_k(const QRows<KS>& A, const uint16_t* Bs, bool diag, int roff) {
+  const int lane = threadIdx.x & 63;
+  uint32_t best = 0;
+  v4f32 R[4], I[4];
+  u32x4 b0[KS], b1[KS];
+  if (!diag) {
+    read_frags<KS>(Bs, 0, b0);
+    read_frags<KS>(Bs, 1, b1);
+    qblock<KS, false>(A, b0, R, I, best);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int cb = 1; cb < T / 16; ++cb) {
+      if (cb & 1) {
+        if (cb + 1 < T / 16) read_frags<KS>(Bs, cb + 1, b0);
+        qblock<KS, true>(A, b1, R, I, best);
+      } else {
+        if (cb + 1 < T / 16) read_frags<KS>(Bs, cb + 1, b1);
+        qblock<KS, true>(A, b0, R, I, best);
+      }
+      sched_qblock<KS>(cb + 1 < T / 16);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) best = fold_rb(best, R[rb], I[rb]);
+    return best;
+  }
+  // diagonal tile: column blocks wholly below this wave's rows are skipped
+  for (int c = roff / 16; c < T / 16; ++c) {
+    read_frags<KS>(Bs, c, b0);
+    qblock<KS, false>(A, b0, R, I, best);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      uint32_t m[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        m[v] = __float_as_uint(fmaf(R[rb][v], R[rb][v], I[rb][v] * I[rb][v]));
+        const int i = roff + rb * 16 + 4 * (lane >> 4) + v;
+        const int j = c * 16 + (lane & 15);
+        if (i >= j) m[v] = 0u;
+      }
+      best = max3u(max3u(m[0], m[1], m[2]), m[3], best);
+    }
+  }
+  return best;
+}
+
+// Row segments of 256-row blocks: row block r (tile rows 2r, 2r + 1) against
+// runs of at most kSegK column tiles bj >= 2r.
+constexpr int kSegK = 4;
+__device__ __forceinline__ void seg_decode_k(int s, int nt, int& r, int& bj0, int& bj1) {
+  r = 0;
+  int rem = s;
+  for (;;) {
+    const int ns = (nt - 2 * r + kSegK - 1) / kSegK;
+    if (rem < ns) break;
+    rem -= ns;
+    ++r;
+  }
+  bj0 = 2 * r + rem * kSegK;
+  bj1 = bj0 + kSegK < nt ? bj0 + kSegK : nt;
+}
+
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_gram_bf16_k(GramArgs a) {
+  if (a.flags && (*a.flags & kFlagDone)) return;
+  const int b = blockIdx.x;
+  const int local = b >> 3;
+  const int slot = (local / a.nseg) * 8 + (b & 7);
+  const int seg = local % a.nseg;
+  if (slot >= a.slots) return;
+  int r, bj0, bj1;
+  seg_decode_k(seg, a.nt, r, bj0, bj1);
+  const int tiles = a.nt * (a.nt + 1) / 2;
+
+  constexpr int kBuf = T * (32 * KS + 8);
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2 * kBuf];
+  __shared__ uint32_t red[4];
+  const uint16_t* base = (const uint16_t*)a.cand + (size_t)slot * a.slot_stride;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int tr = 2 * r + (w >> 1);   // this wave's tile row
+  const int roff = 64 * (w & 1);     // its rows' offset in that tile row
+
+  u32x4 pf[2 * KS];
+  fetch_cols<KS>(base, a.n, bj0, pf);
+  QRows<KS> A;
+  load_rows_q<KS>(base, a.ldk, a.n, tr * T + roff, A);
+  store_cols<KS>(pf, Bs);
+  __syncthreads();
+  if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.n, bj0 + 1, pf);
+
+  uint32_t cmax = 0;
+  uint32_t tile_lane = 0;
+  for (int bj = bj0; bj < bj1; ++bj) {
+    const int buf = (bj - bj0) & 1;
+    uint32_t tmax = 0;
+    if (bj >= tr && tr < a.nt) tmax = tile_max_k<KS>(A, Bs + buf * kBuf, bj == tr, roff);
+    cmax = tmax > cmax ? tmax : cmax;
+    if (a.tile_max) {
+      const uint32_t wm = wave_max_u32_dpp(tmax);
+      if (lane == bj - bj0) tile_lane = wm;
+    }
+    if (bj + 1 < bj1) {
+      store_cols<KS>(pf, Bs + (buf ^ 1) * kBuf);
+      __syncthreads();
+      if (bj + 2 < bj1) fetch_cols<KS>(base, a.n, bj + 2, pf);
+    }
+  }
+  // tile (tr, bj) is covered by the two waves of tile row tr: each fills two
+  // of its four entries
+  if (a.tile_max && lane < bj1 - bj0 && bj0 + lane >= tr && tr < a.nt) {
+    uint32_t* dst = a.tile_max + ((size_t)slot * tiles + tile_linear(tr, bj0 + lane, a.nt)) * 4 + 2 * (w & 1);
+    *(uint2*)dst = make_uint2(tile_lane, tile_lane);
+  }
+  cmax = wave_max_u32_dpp(cmax);
+  if (lane == 0) red[w] = cmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t mx = max3u(red[0], red[1], red[2] > red[3] ? red[2] : red[3]);
+    atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)mx);
+  }
+}
+
+int k_segments(int nt) {
+  int total = 0;
+  for (int r = 0; 2 * r < nt; ++r) total += (nt - 2 * r + kSegK - 1) / kSegK;
+  return total;
 }
 
 // Exact FP64 |<phi_j, phi_k>|^2 from the FP64 candidate (column stride ld).
@@ -521,7 +728,15 @@ hipError_t launch_rp(const RecheckArgs& a, int grid, hipStream_t s) {
 
 template <int KS>
 hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_bf16<KS>, dim3(grid), dim3(256), 0, s, a);
+  if constexpr (KS <= 4) {
+    (void)grid;
+    GramArgs k = a;
+    k.nseg = k_segments(a.nt);
+    const long g = (long)k.nseg * ((a.slots + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_gram_bf16_k<KS>, dim3((int)g), dim3(256), 0, s, k);
+  } else {
+    hipLaunchKernelGGL(k_gram_bf16<KS>, dim3(grid), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
