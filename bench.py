@@ -67,7 +67,14 @@ def load_traffic(name):
     return rec.get("bytes_per_launch")
 
 
-def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
+STEP_KERNELS = ("perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck", "recheck", "select",
+                "commit")
+
+
+def run_mode(lib, torch, wl, mode, steps, warmup, topk=8, breakdown_steps=10):
+    """Timed steps with HIP events around the Gram kernel only (the other
+    kernels' events would add to the step), then a few steps with every kernel
+    timed for the per-kernel breakdown."""
     s = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode=mode, recheck_topk=topk, radius0=wl.radius0,
                    max_steps=10 ** 12, seed=wl.seed, stream_id=wl.stream_id)
     s.init_haar()
@@ -75,6 +82,7 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
         s.step(with_report=False)
     torch.cuda.synchronize()
     lib.timing_reset()
+    lib.timing_only(GRAM_KERNEL[mode])
     lib.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -83,16 +91,23 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lib.timing_enable(False)
-    kernels = {}
-    for name in ("perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck", "recheck",
-                 "select", "commit"):
-        ms, cnt = lib.timing_read(name)
-        if cnt:
-            kernels[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
+    ms, cnt = lib.timing_read(GRAM_KERNEL[mode])
+    g = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
     mu = float(s.state.mu.item())
+    lib.timing_reset()
+    lib.timing_only(None)
+    lib.timing_enable(True)
+    for _ in range(breakdown_steps):
+        s.step(with_report=False)
+    torch.cuda.synchronize()
+    lib.timing_enable(False)
+    kernels = {}
+    for name in STEP_KERNELS:
+        kms, kcnt = lib.timing_read(name)
+        if kcnt:
+            kernels[name] = {"avg_us": 1e3 * kms / kcnt, "launches": kcnt}
     elapsed = t1 - t0
     evals = wl.candidates * steps / elapsed
-    g = kernels[GRAM_KERNEL[mode]]
     flops_launch = wl.candidates * flops_per_eval(wl.n, wl.d)
     achieved = flops_launch / (g["avg_us"] * 1e-6) / 1e12
     del s
@@ -101,6 +116,7 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8):
         "evals_per_s": evals,
         "ms_per_step": 1e3 * elapsed / steps,
         "final_mu": mu,
+        "gram": g,
         "kernels": kernels,
         "gram_tflops": achieved,
         "gram_frac": achieved / PEAK_TFLOPS[mode],
@@ -245,14 +261,14 @@ def main():
         r = run_mode(lib, torch, wl, m, args.other_steps, 2)
         log(f"{m}: {r['evals_per_s']:.0f} evals/s")
         others[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
-        others[m]["gram_avg_us"] = r["kernels"][GRAM_KERNEL[m]]["avg_us"]
+        others[m]["gram_avg_us"] = r["gram"]["avg_us"]
 
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
     serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib)
                if args.serving_requests > 0 else None)
 
-    g = main_res["kernels"]["gram_bf16"]
+    g = main_res["gram"]
     traffic = load_traffic("gram_bf16")
     line = {
         "metric": METRIC,
@@ -284,6 +300,7 @@ def main():
             "flops_per_launch": main_res["flops_per_launch"],
             "avg_launch_us": g["avg_us"],
         },
+        # every kernel timed, over a few extra steps after the timed region
         "kernels_avg_us": {k: round(v["avg_us"], 3) for k, v in main_res["kernels"].items()},
         "final_mu": main_res["final_mu"],
         "other_modes": others,

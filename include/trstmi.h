@@ -279,9 +279,13 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
  * the recorded events and returns, for one kernel name, the summed elapsed
  * milliseconds and the number of timed launches since the last reset.  Names:
  * "perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb_recheck",
- * "recheck", "select", "commit".
+ * "recheck", "select", "commit", "batch_step".  trstmi_timing_only(name)
+ * limits timing to launches of that kernel (NULL or "": every kernel), so
+ * that the events of the others do not add to a measured step.  Process-wide
+ * settings; returns TRSTMI_OK.
  */
 trstmi_status trstmi_timing_enable(int32_t on);
+trstmi_status trstmi_timing_only(const char* kernel);
 trstmi_status trstmi_timing_reset(void);
 trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* launches);
 

@@ -213,6 +213,11 @@ def timing_enable(on=True):
     _abi.check(_abi.lib().trstmi_timing_enable(1 if on else 0), "trstmi_timing_enable")
 
 
+def timing_only(kernel=None):
+    """Limit timing to launches of one kernel name (None: every kernel)."""
+    _abi.check(_abi.lib().trstmi_timing_only(kernel.encode() if kernel else None), "trstmi_timing_only")
+
+
 def timing_reset():
     _abi.check(_abi.lib().trstmi_timing_reset(), "trstmi_timing_reset")
 

@@ -121,6 +121,7 @@ SIGNATURES = {
                                   _vp]),
     "trstmi_batch_frame": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _i32, _vp, _vp]),
     "trstmi_timing_enable": (_i32, [_i32]),
+    "trstmi_timing_only": (_i32, [ctypes.c_char_p]),
     "trstmi_timing_reset": (_i32, []),
     "trstmi_timing_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_i64)]),
     "trstmi_last_error": (ctypes.c_char_p, []),

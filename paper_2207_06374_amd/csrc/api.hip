@@ -41,8 +41,9 @@ trstmi_status hip_fail(hipError_t e, const char* where) {
 // Kernel timing.  When enabled, every kernel launch of the library is
 // bracketed by two HIP events recorded on the launch's own stream; reading
 // the totals waits for those events and sums the elapsed times per kernel
-// name.  Launches made while a stream is being captured into a graph are not
-// timed.
+// name.  Timing can be limited to one kernel name (each timed launch adds two
+// event records to its stream).  Launches made while a stream is being
+// captured into a graph are not timed.
 // ---------------------------------------------------------------------------
 struct TimingRecord {
   const char* name;
@@ -52,6 +53,7 @@ struct TimingRecord {
 struct Timing {
   std::mutex mu;
   bool on = false;
+  std::string only;  // empty: every kernel
   std::vector<TimingRecord> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<double, int64_t>> totals;  // name -> (ms, launches)
@@ -85,7 +87,7 @@ class TimedLaunch {
   TimedLaunch(const char* name, hipStream_t s) : name_(name), s_(s) {
     Timing& T = timing();
     std::lock_guard<std::mutex> g(T.mu);
-    if (!T.on || capturing(s)) return;
+    if (!T.on || (!T.only.empty() && T.only != name) || capturing(s)) return;
     start_ = T.get();
     stop_ = T.get();
     if (start_ && stop_ && hipEventRecord(start_, s) == hipSuccess) active_ = true;
@@ -764,6 +766,13 @@ trstmi_status trstmi_timing_enable(int32_t on) {
   return TRSTMI_OK;
 }
 
+trstmi_status trstmi_timing_only(const char* kernel) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> g(T.mu);
+  T.only = kernel ? kernel : "";
+  return TRSTMI_OK;
+}
+
 trstmi_status trstmi_timing_reset(void) {
   trstmi_status st = drain_timing();
   Timing& T = timing();
@@ -920,6 +929,6 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
-int32_t trstmi_abi_version(void) { return 1; }
+int32_t trstmi_abi_version(void) { return 2; }
 
 }  // extern "C"

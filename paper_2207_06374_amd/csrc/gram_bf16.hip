@@ -38,9 +38,10 @@
 //
 // Each wave keeps its maximum for every tile in a lane and writes them once
 // per segment (they prune the FP64 recheck); the block updates the
-// candidate's running maximum with one atomic.  The FP64 recheck of the best screened candidates (k_recheck_pairs)
-// reuses the per-tile code on the tiles that can hold the exact maximum and
-// evaluates only the pairs that can attain it in FP64.
+// candidate's running maximum with one atomic.  The FP64 recheck of the best
+// screened candidates (k_recheck_pairs) reuses the narrow per-tile code on the
+// tiles that can hold the exact maximum and evaluates only the pairs that can
+// attain it in FP64.
 //
 // Fallback kernel (2d > 256, coherence entry point only): 128 x 128 tiles, K
 // looped in LDS chunks of 128.
@@ -551,6 +552,27 @@ __device__ __forceinline__ uint64_t pair_f64(const double* c64, int ld, int d, i
   return (uint64_t)__double_as_longlong(re * re + im * im);
 }
 
+// The same value with the whole wave on one pair: lane i takes entries
+// i, i + 64, ... and a butterfly sum (commutative, so every lane ends with the
+// same bits) combines them.
+__device__ __forceinline__ uint64_t pair_f64_wave(const double* c64, int ld, int d, int j, int k) {
+  const int lane = threadIdx.x & 63;
+  const double2* x = (const double2*)(c64 + (size_t)j * ld);
+  const double2* y = (const double2*)(c64 + (size_t)k * ld);
+  double re = 0.0, im = 0.0;
+  for (int i = lane; i < d; i += 64) {
+    const double2 p = x[i], q = y[i];
+    re += p.x * q.x + p.y * q.y;
+    im += p.x * q.y - p.y * q.x;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  return (uint64_t)__double_as_longlong(re * re + im * im);
+}
+
 // Pair-level FP64 recheck.  For a rechecked candidate with screened maximum s
 // and certified screen error eps, the exact maximiser has screened value
 // >= s - 2 eps = thr (its exact value is >= the exact value at the screened
@@ -577,13 +599,12 @@ __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_recheck_pairs(RecheckA
     const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
     const uint16_t* base = a.screen + (size_t)a.rechecked[slot] * a.screen_stride;
     const double* c64 = a.cand64 + (size_t)slot * a.stride64;
-    {
-      u32x4 pf[2 * KS];
-      fetch_cols<KS>(base, a.n, bj, pf);
-      store_cols<KS>(pf, Bs);
-    }
+    // A rows and B columns are loaded together, then B goes to LDS
+    u32x4 pf[2 * KS];
+    fetch_cols<KS>(base, a.n, bj, pf);
     ARows<KS> A;
     load_rows<KS>(base, a.ldk16, a.n, bi, A);
+    store_cols<KS>(pf, Bs);
     __syncthreads();
     uint64_t best = 0;
     for (int cb = 0; cb < T / 16; ++cb) {
@@ -591,11 +612,24 @@ __global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_recheck_pairs(RecheckA
       uint32_t m[8];
       mma_block<KS>(A, Bs, cb, xR, xI);
       sq_mag(xR, xI, m);
+      // a few qualifying pairs (the usual case) are evaluated one after the
+      // other by the whole wave; many at once, each by its own lane
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int i = bi * T + w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
         const int j = bj * T + cb * 16 + (lane & 15);
-        if (i < j && j < a.n && !(__uint_as_float(m[q]) < thr_sq)) {
+        const bool hit = i < j && j < a.n && !(__uint_as_float(m[q]) < thr_sq);
+        uint64_t bal = __ballot(hit);
+        if (__popcll(bal) <= 8) {
+          while (bal) {
+            const int l = __ffsll((unsigned long long)bal) - 1;
+            bal &= bal - 1;
+            const int pi = bi * T + w * 32 + (q >> 2) * 16 + 4 * (l >> 4) + (q & 3);
+            const int pj = bj * T + cb * 16 + (l & 15);
+            const uint64_t mb = pair_f64_wave(c64, a.ld64, a.d, pi, pj);
+            best = mb > best ? mb : best;
+          }
+        } else if (hit) {
           const uint64_t mb = pair_f64(c64, a.ld64, a.d, i, j);
           best = mb > best ? mb : best;
         }

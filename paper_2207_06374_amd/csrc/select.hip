@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBitmapWords = 65536 / 32;  // one bit per candidate
+constexpr int kRankMax = 1024;            // rank selection up to this many candidates
 
 __device__ __forceinline__ double bits_to_mu(uint64_t b, int is_f32) {
   if (is_f32) {
@@ -116,57 +117,90 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
   __shared__ int sel_c[64];
   __shared__ double sel_thr[64];
   __shared__ int list_n;
+  __shared__ uint64_t keys[kRankMax];
+  __shared__ double kth[2];
   const int tid = threadIdx.x;
   if (*a.flags & kFlagDone) return;
-  for (int q = tid; q < kBitmapWords; q += kThreads) taken[q] = 0;
   for (int c = tid; c < a.C && a.rep_cand_mu; c += kThreads) a.rep_cand_mu[c] = bits_to_mu(a.cand_max[c], 1);
-  __syncthreads();
-  double prev = 0.0;
-  for (int round = 0; round <= a.k && round < a.C; ++round) {
-    double bv = __builtin_inf();
-    int bc = 0x7fffffff;
+  if (a.C <= kRankMax) {
+    // Rank selection: key = (screened bits clamped at +inf, c) orders like
+    // (mu_screen, c); the candidate of rank r < k is the r-th rechecked one.
     for (int c = tid; c < a.C; c += kThreads) {
-      if (taken[c >> 5] & (1u << (c & 31))) continue;
-      const double mu = bits_to_mu(a.cand_max[c], 1);
-      if (mu < bv || (mu == bv && c < bc)) {
-        bv = mu;
-        bc = c;
+      const uint32_t b = (uint32_t)a.cand_max[c];
+      keys[c] = ((uint64_t)(b < kInfBits32 ? b : kInfBits32) << 32) | (uint32_t)c;
+    }
+    if (tid < 2) kth[tid] = 0.0;
+    __syncthreads();
+    for (int c = tid; c < a.C; c += kThreads) {
+      const uint64_t key = keys[c];
+      int rank = 0;
+      for (int o = 0; o < a.C; ++o) rank += keys[o] < key ? 1 : 0;
+      if (rank <= a.k) {
+        const double v = bits_to_mu(a.cand_max[c], 1);
+        if (rank < a.k) {
+          a.rechecked[rank] = c;
+          // an invalid (non-finite) screened value disables pruning for that candidate
+          a.thr[rank] = v < __builtin_inf() ? v - 2.0 * a.eps : -__builtin_inf();
+          sel_c[rank] = c;
+          sel_thr[rank] = a.thr[rank];
+          if (a.rep_rechecked) a.rep_rechecked[rank] = c;
+        }
+        if (rank == a.k - 1) kth[0] = v;
+        if (rank == a.k) kth[1] = v;
       }
     }
-    sv[tid] = bv;
-    sc[tid] = bc;
     __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        const double ov = sv[tid + off];
-        const int oc = sc[tid + off];
-        if (ov < sv[tid] || (ov == sv[tid] && oc < sc[tid])) {
-          sv[tid] = ov;
-          sc[tid] = oc;
+    if (tid == 0) a.dec->screen_near = (a.k < a.C && kth[1] - kth[0] <= a.screen_tie) ? 1 : 0;
+  } else {
+    for (int q = tid; q < kBitmapWords; q += kThreads) taken[q] = 0;
+    __syncthreads();
+    double prev = 0.0;
+    for (int round = 0; round <= a.k && round < a.C; ++round) {
+      double bv = __builtin_inf();
+      int bc = 0x7fffffff;
+      for (int c = tid; c < a.C; c += kThreads) {
+        if (taken[c >> 5] & (1u << (c & 31))) continue;
+        const double mu = bits_to_mu(a.cand_max[c], 1);
+        if (mu < bv || (mu == bv && c < bc)) {
+          bv = mu;
+          bc = c;
         }
+      }
+      sv[tid] = bv;
+      sc[tid] = bc;
+      __syncthreads();
+      for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+          const double ov = sv[tid + off];
+          const int oc = sc[tid + off];
+          if (ov < sv[tid] || (ov == sv[tid] && oc < sc[tid])) {
+            sv[tid] = ov;
+            sc[tid] = oc;
+          }
+        }
+        __syncthreads();
+      }
+      const double v = sv[0];
+      const int c = sc[0];
+      __syncthreads();
+      if (round < a.k) {
+        if (tid == 0) {
+          taken[c >> 5] |= 1u << (c & 31);
+          a.rechecked[round] = c;
+          // an invalid (non-finite) screened value disables pruning for that candidate
+          a.thr[round] = v < __builtin_inf() ? v - 2.0 * a.eps : -__builtin_inf();
+          sel_c[round] = c;
+          sel_thr[round] = a.thr[round];
+          if (a.rep_rechecked) a.rep_rechecked[round] = c;
+        }
+        prev = v;
+      } else if (tid == 0) {
+        a.dec->screen_near = (v - prev <= a.screen_tie) ? 1 : 0;
       }
       __syncthreads();
     }
-    const double v = sv[0];
-    const int c = sc[0];
-    __syncthreads();
-    if (round < a.k) {
-      if (tid == 0) {
-        taken[c >> 5] |= 1u << (c & 31);
-        a.rechecked[round] = c;
-        // an invalid (non-finite) screened value disables pruning for that candidate
-        a.thr[round] = v < __builtin_inf() ? v - 2.0 * a.eps : -__builtin_inf();
-        sel_c[round] = c;
-        sel_thr[round] = a.thr[round];
-        if (a.rep_rechecked) a.rep_rechecked[round] = c;
-      }
-      prev = v;
-    } else if (tid == 0) {
-      a.dec->screen_near = (v - prev <= a.screen_tie) ? 1 : 0;
-    }
-    __syncthreads();
+    if (tid == 0 && a.k >= a.C) a.dec->screen_near = 0;
   }
-  if (tid == 0 && a.k >= a.C) a.dec->screen_near = 0;
 
   // Certified pruning.  For every pair |screened - exact| <= eps, so a screen
   // tile whose screened maximum is below (candidate's screened max - 2 eps)
@@ -177,29 +211,43 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
   __syncthreads();
   const int sn = a.screen_nt * (a.screen_nt + 1) / 2;
   const int lane = tid & 63;
-  for (int e0 = 0; e0 < a.k * sn; e0 += kThreads) {
-    const int e = e0 + tid;
-    bool keep = false;
-    int slot = 0, st = 0;
-    if (e < a.k * sn) {
-      slot = e / sn;
-      st = e - slot * sn;
-      if (sel_thr[slot] > -__builtin_inf()) {
-        const uint32_t* tm = a.tile_max + ((size_t)sel_c[slot] * sn + st) * 4;
-        uint32_t mb = tm[0] > tm[1] ? tm[0] : tm[1];
-        mb = tm[2] > mb ? tm[2] : mb;
-        mb = tm[3] > mb ? tm[3] : mb;
-        const double m = sqrt((double)__uint_as_float(mb));
-        keep = !(m < sel_thr[slot]);
+  constexpr int kU = 8;  // entries per thread per pass, loaded before any is used
+  for (int e0 = 0; e0 < a.k * sn; e0 += kThreads * kU) {
+    uint4 tm[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * kThreads + tid;
+      tm[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < a.k * sn) {
+        const int slot = e / sn;
+        if (sel_thr[slot] > -__builtin_inf())
+          tm[u] = *(const uint4*)(a.tile_max + ((size_t)sel_c[slot] * sn + (e - slot * sn)) * 4);
       }
     }
-    const uint64_t ballot = __ballot(keep);
-    int base = 0;
-    if (lane == 0 && ballot) base = atomicAdd(&list_n, __popcll(ballot));
-    base = __shfl(base, 0, 64);
-    if (keep) {
-      const int pos = base + __popcll(ballot & ((1ull << lane) - 1));
-      if (pos < a.list_cap) a.list[pos] = make_int2(slot, st);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * kThreads + tid;
+      bool keep = false;
+      int slot = 0, st = 0;
+      if (e < a.k * sn) {
+        slot = e / sn;
+        st = e - slot * sn;
+        if (sel_thr[slot] > -__builtin_inf()) {
+          uint32_t mb = tm[u].x > tm[u].y ? tm[u].x : tm[u].y;
+          mb = tm[u].z > mb ? tm[u].z : mb;
+          mb = tm[u].w > mb ? tm[u].w : mb;
+          const double m = sqrt((double)__uint_as_float(mb));
+          keep = !(m < sel_thr[slot]);
+        }
+      }
+      const uint64_t ballot = __ballot(keep);
+      int base = 0;
+      if (lane == 0 && ballot) base = atomicAdd(&list_n, __popcll(ballot));
+      base = __shfl(base, 0, 64);
+      if (keep) {
+        const int pos = base + __popcll(ballot & ((1ull << lane) - 1));
+        if (pos < a.list_cap) a.list[pos] = make_int2(slot, st);
+      }
     }
   }
   __syncthreads();

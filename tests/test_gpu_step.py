@@ -79,7 +79,8 @@ def test_fp32_step_parity_with_resync(n, d, C):
             assert np.max(np.abs(F - new.frame)) <= 1e-13
 
 
-@pytest.mark.parametrize("n,d,C,k", [(64, 8, 32, 4), (300, 16, 24, 8), (260, 64, 16, 8), (129, 3, 40, 8)])
+@pytest.mark.parametrize("n,d,C,k", [(64, 8, 32, 4), (300, 16, 24, 8), (260, 64, 16, 8), (129, 3, 40, 8),
+                                     (16, 4, 1100, 8)])
 def test_bf16_screen_step_parity(n, d, C, k):
     s, p = _pair(n, d, C, mode="bf16", k=k, radius0=0.2)
     s.init_haar()
@@ -108,6 +109,24 @@ def test_bf16_screen_step_parity(n, d, C, k):
         assert radius == new.radius
         assert abs(mu - new.mu) <= 1e-12
         assert np.max(np.abs(F - new.frame)) <= 1e-13
+
+
+def test_bf16_recheck_with_many_near_maximal_pairs():
+    """Candidates near an equiangular frame (Hesse SIC, 9 lines in C^3): every
+    pair lies within the screen's error band of the maximum, so the FP64
+    recheck evaluates many pairs per tile (both its one-pair-per-wave and its
+    one-pair-per-lane paths) and must still return the exact FP64 values."""
+    F0 = frames.hesse_sic()
+    n, d, C, k = 9, 3, 16, 8
+    s, p = _pair(n, d, C, mode="bf16", k=k, radius0=1e-3)
+    s.set_frame(F0, mu=oracle.coherence(F0), radius=1e-3)
+    for _ in range(3):
+        st = _sync_oracle(s, p)
+        s.step()
+        new, rep = oracle.step(p, st)
+        rechecked = s.report["rechecked"].cpu().numpy()[:k]
+        recheck_mu = s.report["recheck_mu"].cpu().numpy()[:k]
+        assert np.max(np.abs(recheck_mu - rep.cand_mu_fp64[rechecked])) <= 1e-12
 
 
 def test_known_winner_through_abi():
