@@ -11,8 +11,10 @@
 // block = 4 words = 2 complex entries).  LPC lanes (a power of two <= 64)
 // share a column, each holding up to kMaxQ blocks in registers; the norm is
 // reduced across the LPC lanes with xor-shuffles, so a column never leaves
-// the wavefront.  Loads and stores are 16-byte and consecutive lanes touch
-// consecutive entries of a column.
+// the wavefront.  BF16/FP32 screen copies put 4 blocks on a lane; FP64
+// outputs use one split per d, so a candidate's FP64 bits are the same in
+// every launch that writes it.  Loads and stores are 16-byte and consecutive
+// lanes touch consecutive entries of a column.
 
 #include "device_common.h"
 #include "launch.h"
@@ -196,6 +198,19 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
   const int nb = (a.d + 1) / 2;
+  if (a.out_kind != kOutF64) {
+    // screen copies: 4 blocks per lane, so the column norm's square root and
+    // division are shared by more entries
+    if (nb <= 4) return launch_lpc<1, 4>(a, slots, s);
+    if (nb <= 8) return launch_lpc<2, 4>(a, slots, s);
+    if (nb <= 16) return launch_lpc<4, 4>(a, slots, s);
+    if (nb <= 32) return launch_lpc<8, 4>(a, slots, s);
+    if (nb <= 64) return launch_lpc<16, 4>(a, slots, s);
+    if (nb <= 128) return launch_lpc<32, 4>(a, slots, s);
+    return launch_lpc<64, kMaxQ>(a, slots, s);
+  }
+  // FP64 frames and candidates (every launch that writes one candidate in
+  // FP64 uses this same split, so its bits do not depend on the launch)
   if (nb <= 1) return launch_lpc<1, 1>(a, slots, s);
   if (nb <= 2) return launch_lpc<2, 1>(a, slots, s);
   if (nb <= 4) return launch_lpc<4, 1>(a, slots, s);
