@@ -169,6 +169,16 @@ trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state
                                void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * The rounding the BF16 screen applies to its inputs (precision form of the
+ * step): x[i] (device, count doubles) -> out[i] (device, count bfloat16 bit
+ * patterns), round to nearest with ties to even, taken directly from the
+ * double (as if with unbounded precision); subnormal bfloat16 results are
+ * kept, a NaN gives a NaN.  Stream-ordered.  count >= 0; NULL or misaligned
+ * pointers (count > 0) return TRSTMI_E_INVALID_ARG.
+ */
+trstmi_status trstmi_round_bf16(const double* x, int64_t count, uint16_t* out, hipStream_t stream);
+
+/*
  * The normalised FP64 candidates of one step, for inspection: for
  * i = 0..count-1, out + i*2*d*n <- normalise(frame + (radius / sqrt(d)) Z)
  * with Z the draws of candidate (c0 + i) at step t (or explicit_z, see

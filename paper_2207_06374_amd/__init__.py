@@ -118,6 +118,18 @@ def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, s
     return out
 
 
+def round_bf16(x, out=None, stream=None):
+    """bfloat16 bit patterns (int16 tensor) of a float64 device tensor, rounded
+    as the BF16 screen rounds its inputs."""
+    torch = _torch()
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty(x.numel(), dtype=torch.int16, device=x.device)
+    _abi.check(_abi.lib().trstmi_round_bf16(_ptr(x), int(x.numel()), _ptr(out), _stream(stream)),
+               "trstmi_round_bf16")
+    return out
+
+
 @dataclasses.dataclass
 class DeviceState:
     frame: object

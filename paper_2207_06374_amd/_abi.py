@@ -120,6 +120,7 @@ SIGNATURES = {
     "trstmi_batch_query": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _vp, _vp, _vp, _vp, _P(_i32),
                                   _vp]),
     "trstmi_batch_frame": (_i32, [_P(BatchParams), _P(BatchInstance), _vp, _sz, _i32, _vp, _vp]),
+    "trstmi_round_bf16": (_i32, [_vp, _i64, _vp, _vp]),
     "trstmi_timing_enable": (_i32, [_i32]),
     "trstmi_timing_only": (_i32, [ctypes.c_char_p]),
     "trstmi_timing_reset": (_i32, []),

@@ -576,6 +576,15 @@ size_t trstmi_coherence_workspace_bytes(int64_t n, int64_t d, int32_t mode) {
   return align256((size_t)n * ld_mode(d, mode) * elem_of_mode(mode)) + 256;
 }
 
+trstmi_status trstmi_round_bf16(const double* x, int64_t count, uint16_t* out, hipStream_t stream) {
+  if (count < 0) return fail(TRSTMI_E_INVALID_ARG, "count must be >= 0");
+  if (count == 0) return TRSTMI_OK;
+  if (!x || !out) return fail(TRSTMI_E_INVALID_ARG, "x and out must be device pointers");
+  if (((uintptr_t)x & 7) || ((uintptr_t)out & 1)) return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  TRY_HIP(launch_round_bf16(x, count, out, stream), "round_bf16");
+  return TRSTMI_OK;
+}
+
 trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double* frame, double* mu_out,
                                void* workspace, size_t workspace_bytes, hipStream_t stream) {
   trstmi_status st = check_size(n, d);
@@ -929,6 +938,6 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
-int32_t trstmi_abi_version(void) { return 2; }
+int32_t trstmi_abi_version(void) { return 3; }
 
 }  // extern "C"

@@ -164,6 +164,26 @@ __device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
   return (uint16_t)(__float_as_uint(f) >> 16);
 }
 
+// Two doubles -> two bfloat16 (round to nearest even, as if rounded directly
+// from the double), packed with x0 in the low half.  Rounding to FP32 first
+// and then to bfloat16 gives the same result unless the FP32 value lands
+// exactly on a bfloat16 midpoint (x may lie on either side of it) or is an
+// FP32 subnormal; those rare lanes use f64_to_bf16_rne.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ bool bf16_via_f32_unsafe(uint32_t b) {
+  return (b & 0xFFFFu) == 0x8000u || ((b & 0x7F800000u) == 0 && (b & 0x007FFFFFu) != 0);
+}
+
+__device__ __forceinline__ uint32_t bf16x2_rne(double x0, double x1) {
+  const f32x2 f = {(float)x0, (float)x1};
+  const bool slow = bf16_via_f32_unsafe(__float_as_uint(f[0])) || bf16_via_f32_unsafe(__float_as_uint(f[1]));
+  if (__ballot(slow) && slow)
+    return (uint32_t)f64_to_bf16_rne(x0) | ((uint32_t)f64_to_bf16_rne(x1) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+}
+
 // ---------------------------------------------------------------------------
 // Upper-triangle tile enumeration: tile t in [0, nt(nt+1)/2) <-> (bi, bj),
 // bi <= bj, row by row.

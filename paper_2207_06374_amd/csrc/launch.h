@@ -167,6 +167,7 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
 hipError_t launch_recheck_pairs(const RecheckArgs& a, hipStream_t s);
 hipError_t launch_init_finish(const InitFinishArgs& a, hipStream_t s);
+hipError_t launch_round_bf16(const double* x, int64_t count, uint16_t* out, hipStream_t s);
 hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,
                               uint64_t* zero_max, hipStream_t s);
 

@@ -42,9 +42,9 @@ __device__ __forceinline__ void store_pair(const PerturbArgs& a, size_t slot, in
     }
   } else {
     uint16_t* o = (uint16_t*)a.out + off;
-    const uint32_t w0 = (uint32_t)f64_to_bf16_rne(re0) | ((uint32_t)f64_to_bf16_rne(im0) << 16);
+    const uint32_t w0 = bf16x2_rne(re0, im0);
+    const uint32_t w1 = bf16x2_rne(re1, im1);
     if (two) {
-      const uint32_t w1 = (uint32_t)f64_to_bf16_rne(re1) | ((uint32_t)f64_to_bf16_rne(im1) << 16);
       *(uint2*)o = make_uint2(w0, w1);
     } else {
       *(uint32_t*)o = w0;
@@ -182,6 +182,18 @@ __global__ __launch_bounds__(kThreads) void k_convert_f32(const double* frame, i
   }
 }
 
+// x[i] -> bfloat16 bits, the rounding of the BF16 screen copies (pairs of
+// entries; an odd count pads the last pair with 0).
+__global__ __launch_bounds__(kThreads) void k_round_bf16(const double* x, int64_t count, uint16_t* out) {
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; 2 * p < count;
+       p += (int64_t)gridDim.x * kThreads) {
+    const bool two = 2 * p + 1 < count;
+    const uint32_t w = bf16x2_rne(x[2 * p], two ? x[2 * p + 1] : 0.0);
+    out[2 * p] = (uint16_t)w;
+    if (two) out[2 * p + 1] = (uint16_t)(w >> 16);
+  }
+}
+
 template <int LPC, int Q>
 hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
@@ -228,6 +240,14 @@ hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* 
   int64_t blocks = (total + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_convert_f32, dim3((int)blocks), dim3(kThreads), 0, s, frame, n, d, out, out_ld, zero_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_bf16(const double* x, int64_t count, uint16_t* out, hipStream_t s) {
+  int64_t blocks = (count / 2 + kThreads) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_round_bf16, dim3((int)blocks), dim3(kThreads), 0, s, x, count, out);
   return hipGetLastError();
 }
 

@@ -154,3 +154,10 @@ def test_batch_workspace_scales_with_instances(L):
     assert L.trstmi_batch_workspace_bytes(ctypes.byref(p2), i2) > L.trstmi_batch_workspace_bytes(ctypes.byref(p1), i1)
     p3, i3 = _batch(L, [(16, 4)], C=300)
     assert L.trstmi_batch_workspace_bytes(ctypes.byref(p3), i3) == 0
+
+
+def test_round_bf16_argument_checks(L):
+    assert L.trstmi_round_bf16(None, 0, None, None) == abi.OK
+    assert L.trstmi_round_bf16(None, -1, None, None) == abi.E_INVALID_ARG
+    assert L.trstmi_round_bf16(None, 4, ctypes.c_void_p(256), None) == abi.E_INVALID_ARG
+    assert L.trstmi_round_bf16(ctypes.c_void_p(260), 4, ctypes.c_void_p(256), None) == abi.E_INVALID_ARG

@@ -133,3 +133,31 @@ def test_candidates_explicit_z_and_invalid_column():
     assert np.max(np.abs(got[0] - ref[0])) <= 1e-15
     assert np.all(np.isnan(got[1][:, 4]))
     assert np.max(np.abs(np.delete(got[1], 4, axis=1) - np.delete(ref[1], 4, axis=1))) <= 1e-15
+
+
+def test_round_bf16_matches_oracle_bitwise():
+    """The rounding of the BF16 screen copies equals the oracle's direct
+    round-to-nearest-even from FP64, bit for bit, including exact bfloat16
+    midpoints, values within a float32 ulp of them (where rounding through
+    float32 first would go wrong) and the subnormal ranges."""
+    rng = np.random.default_rng(5)
+    parts = [rng.standard_normal(200000) * np.exp2(rng.integers(-140, 40, 200000).astype(np.float64))]
+    b = rng.standard_normal(50000).astype(np.float32)
+    b = (b.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)            # bfloat16 values
+    up = (b.view(np.uint32) + np.uint32(0x10000)).view(np.float32)              # next one away from 0
+    m = (b.astype(np.float64) + up.astype(np.float64)) / 2                     # exact midpoints
+    tiny = np.abs(m) * 2.0 ** -40
+    parts += [m, m + tiny, m - tiny, np.nextafter(m, np.inf), np.nextafter(m, -np.inf)]
+    parts.append(rng.standard_normal(20000) * 2.0 ** -130)
+    parts.append(rng.standard_normal(20000) * 2.0 ** -145)
+    parts.append(np.array([0.0, -0.0, 1.0, -1.0, 2.0 ** -126, 2.0 ** -133, 2.0 ** -134, 3 * 2.0 ** -135]))
+    x = np.concatenate(parts)
+    got = lib.round_bf16(torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint16)
+    ref = oracle.round_to_bf16(x)
+    ref_bits = (ref.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    bad = np.flatnonzero(got != ref_bits)
+    assert bad.size == 0, (x[bad[:5]], got[bad[:5]], ref_bits[bad[:5]])
+    y = np.array([np.nan, np.inf, -np.inf])  # odd count
+    g = lib.round_bf16(torch.from_numpy(y).cuda()).cpu().numpy().view(np.uint16)
+    assert (g[0] & 0x7F80) == 0x7F80 and (g[0] & 0x7F) != 0
+    assert g[1] == 0x7F80 and g[2] == 0xFF80
