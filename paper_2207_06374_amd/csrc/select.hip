@@ -17,6 +17,7 @@ namespace trstmi {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kTopkThreads = 1024;  // the tile list of the top-k is built in one or two passes
 constexpr int kBitmapWords = 65536 / 32;  // one bit per candidate
 constexpr int kRankMax = 1024;            // rank selection up to this many candidates
 
@@ -110,9 +111,9 @@ __global__ __launch_bounds__(kThreads) void k_select(SelectArgs a) {
 }
 
 // k smallest screened values by (mu_screen, c); thresholds for certified pruning.
-__global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
-  __shared__ double sv[kThreads];
-  __shared__ int sc[kThreads];
+__global__ __launch_bounds__(kTopkThreads) void k_topk(TopkArgs a) {
+  __shared__ double sv[kTopkThreads];
+  __shared__ int sc[kTopkThreads];
   __shared__ uint32_t taken[kBitmapWords];
   __shared__ int sel_c[64];
   __shared__ double sel_thr[64];
@@ -121,17 +122,17 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
   __shared__ double kth[2];
   const int tid = threadIdx.x;
   if (*a.flags & kFlagDone) return;
-  for (int c = tid; c < a.C && a.rep_cand_mu; c += kThreads) a.rep_cand_mu[c] = bits_to_mu(a.cand_max[c], 1);
+  for (int c = tid; c < a.C && a.rep_cand_mu; c += kTopkThreads) a.rep_cand_mu[c] = bits_to_mu(a.cand_max[c], 1);
   if (a.C <= kRankMax) {
     // Rank selection: key = (screened bits clamped at +inf, c) orders like
     // (mu_screen, c); the candidate of rank r < k is the r-th rechecked one.
-    for (int c = tid; c < a.C; c += kThreads) {
+    for (int c = tid; c < a.C; c += kTopkThreads) {
       const uint32_t b = (uint32_t)a.cand_max[c];
       keys[c] = ((uint64_t)(b < kInfBits32 ? b : kInfBits32) << 32) | (uint32_t)c;
     }
     if (tid < 2) kth[tid] = 0.0;
     __syncthreads();
-    for (int c = tid; c < a.C; c += kThreads) {
+    for (int c = tid; c < a.C; c += kTopkThreads) {
       const uint64_t key = keys[c];
       int rank = 0;
       for (int o = 0; o < a.C; ++o) rank += keys[o] < key ? 1 : 0;
@@ -152,13 +153,13 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
     __syncthreads();
     if (tid == 0) a.dec->screen_near = (a.k < a.C && kth[1] - kth[0] <= a.screen_tie) ? 1 : 0;
   } else {
-    for (int q = tid; q < kBitmapWords; q += kThreads) taken[q] = 0;
+    for (int q = tid; q < kBitmapWords; q += kTopkThreads) taken[q] = 0;
     __syncthreads();
     double prev = 0.0;
     for (int round = 0; round <= a.k && round < a.C; ++round) {
       double bv = __builtin_inf();
       int bc = 0x7fffffff;
-      for (int c = tid; c < a.C; c += kThreads) {
+      for (int c = tid; c < a.C; c += kTopkThreads) {
         if (taken[c >> 5] & (1u << (c & 31))) continue;
         const double mu = bits_to_mu(a.cand_max[c], 1);
         if (mu < bv || (mu == bv && c < bc)) {
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
       sv[tid] = bv;
       sc[tid] = bc;
       __syncthreads();
-      for (int off = kThreads / 2; off > 0; off >>= 1) {
+      for (int off = kTopkThreads / 2; off > 0; off >>= 1) {
         if (tid < off) {
           const double ov = sv[tid + off];
           const int oc = sc[tid + off];
@@ -211,12 +212,12 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
   __syncthreads();
   const int sn = a.screen_nt * (a.screen_nt + 1) / 2;
   const int lane = tid & 63;
-  constexpr int kU = 8;  // entries per thread per pass, loaded before any is used
-  for (int e0 = 0; e0 < a.k * sn; e0 += kThreads * kU) {
+  constexpr int kU = 4;  // entries per thread per pass, loaded before any is used
+  for (int e0 = 0; e0 < a.k * sn; e0 += kTopkThreads * kU) {
     uint4 tm[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u * kThreads + tid;
+      const int e = e0 + u * kTopkThreads + tid;
       tm[u] = make_uint4(0u, 0u, 0u, 0u);
       if (e < a.k * sn) {
         const int slot = e / sn;
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_topk(TopkArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int e = e0 + u * kThreads + tid;
+      const int e = e0 + u * kTopkThreads + tid;
       bool keep = false;
       int slot = 0, st = 0;
       if (e < a.k * sn) {
@@ -276,7 +277,7 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_topk, dim3(1), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(kTopkThreads), 0, s, a);
   return hipGetLastError();
 }
 
