@@ -39,9 +39,9 @@
 // Each wave keeps its maximum for every tile in a lane and writes them once
 // per segment (they prune the FP64 recheck); the block updates the
 // candidate's running maximum with one atomic.  The FP64 recheck of the best
-// screened candidates (k_recheck_pairs) reuses the narrow per-tile code on the
-// tiles that can hold the exact maximum and evaluates only the pairs that can
-// attain it in FP64.
+// screened candidates (k_recheck_pairs) screens again the tiles that can hold
+// the exact maximum, one wave per 32 x 32 sub-block, and evaluates only the
+// pairs that can attain it in FP64.
 //
 // Fallback kernel (2d > 256, coherence entry point only): 128 x 128 tiles, K
 // looped in LDS chunks of 128.
@@ -579,71 +579,94 @@ __device__ __forceinline__ uint64_t pair_f64_wave(const double* c64, int ld, int
 // maximiser >= s - eps).  Each listed screen tile is screened again (any
 // screen within eps of the exact values serves) and every pair whose screened
 // value reaches thr is evaluated exactly in FP64 from the FP64 candidate.
+// One wave per work item: 32 rows x 32 columns (sub-block sb of 16) of a
+// listed screen tile, A and B fragments read straight from global memory (no
+// LDS, no barrier), so every item of every listed tile runs at once.
 template <int KS>
-__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_recheck_pairs(RecheckArgs a) {
+__global__ __launch_bounds__(64) void k_recheck_pairs(RecheckArgs a) {
   if (*a.flags & kFlagDone) return;
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * (32 * KS + 8)];
-  __shared__ uint64_t red[4];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  if (blockIdx.x == 0 && tid < a.k && !(a.thr[tid] > -__builtin_inf()))
-    atomicMax((unsigned long long*)&a.recheck_max[tid], ~0ull);  // invalid candidate
-  const int count = *a.count;
-  for (int e = blockIdx.x; e < count; e += gridDim.x) {
-    const int2 item = a.list[e];
-    const int slot = item.x;
+  __shared__ int2 hits[32 * 32];
+  __shared__ int nhits;
+  const int lane = threadIdx.x;
+  if (blockIdx.x == 0 && lane < a.k && !(a.thr[lane] > -__builtin_inf()))
+    atomicMax((unsigned long long*)&a.recheck_max[lane], ~0ull);  // invalid candidate
+  const int items = *a.count * 16;
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    const int2 item = a.list[it >> 4];
+    const int rq = (it >> 2) & 3, cq = it & 3;
     int bi, bj;
     tile_decode(item.y, a.nt, bi, bj);
+    if (bi == bj && rq > cq) continue;  // wholly below the diagonal (uniform: no barrier skipped unevenly)
+    const int slot = item.x;
     const double thr = a.thr[slot];
     const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
     const uint16_t* base = a.screen + (size_t)a.rechecked[slot] * a.screen_stride;
     const double* c64 = a.cand64 + (size_t)slot * a.stride64;
-    // A rows and B columns are loaded together, then B goes to LDS
-    u32x4 pf[2 * KS];
-    fetch_cols<KS>(base, a.n, bj, pf);
-    ARows<KS> A;
-    load_rows<KS>(base, a.ldk16, a.n, bi, A);
-    store_cols<KS>(pf, Bs);
-    __syncthreads();
-    uint64_t best = 0;
-    for (int cb = 0; cb < T / 16; ++cb) {
-      v4f32 xR[2], xI[2];
-      uint32_t m[8];
-      mma_block<KS>(A, Bs, cb, xR, xI);
-      sq_mag(xR, xI, m);
-      // a few qualifying pairs (the usual case) are evaluated one after the
-      // other by the whole wave; many at once, each by its own lane
+    const int r0 = bi * T + 32 * rq, c0 = bj * T + 32 * cq;
+    u32x4 au[2][KS], av[2][KS], bu[2][KS];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = bi * T + w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
-        const int j = bj * T + cb * 16 + (lane & 15);
-        const bool hit = i < j && j < a.n && !(__uint_as_float(m[q]) < thr_sq);
-        uint64_t bal = __ballot(hit);
-        if (__popcll(bal) <= 8) {
-          while (bal) {
-            const int l = __ffsll((unsigned long long)bal) - 1;
-            bal &= bal - 1;
-            const int pi = bi * T + w * 32 + (q >> 2) * 16 + 4 * (l >> 4) + (q & 3);
-            const int pj = bj * T + cb * 16 + (l & 15);
-            const uint64_t mb = pair_f64_wave(c64, a.ld64, a.d, pi, pj);
-            best = mb > best ? mb : best;
-          }
-        } else if (hit) {
-          const uint64_t mb = pair_f64(c64, a.ld64, a.d, i, j);
-          best = mb > best ? mb : best;
-        }
+    for (int h = 0; h < 2; ++h) {
+      const int row = r0 + 16 * h + (lane & 15);
+      const int col = c0 + 16 * h + (lane & 15);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = ks * 32 + 8 * (lane >> 4);
+        au[h][ks] = row < a.n ? *(const u32x4*)(base + (size_t)row * a.ldk16 + k) : u32x4{0u, 0u, 0u, 0u};
+        bu[h][ks] = col < a.n ? *(const u32x4*)(base + (size_t)col * a.ldk16 + k) : u32x4{0u, 0u, 0u, 0u};
       }
     }
-    best = wave_max_u64(best);
-    if (lane == 0) red[w] = best;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) av[h][ks] = swap_negate(au[h][ks]);
+    // qualifying pairs go to a list first, so the FP64 code below exists once
+    // (it runs rarely and would otherwise be fetched cold in many copies)
+    if (lane == 0) nhits = 0;
     __syncthreads();
-    if (tid == 0) {
-      uint64_t mx = red[0];
-      for (int q = 1; q < 4; ++q) mx = red[q] > mx ? red[q] : mx;
-      if (mx) atomicMax((unsigned long long*)&a.recheck_max[slot], (unsigned long long)mx);
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      v4f32 xR[2], xI[2];
+      uint32_t m[8];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        xR[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
+        xI[rb] = v4f32{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          xR[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(au[rb][ks]), as_bf16x8(bu[cb][ks]), xR[rb], 0, 0, 0);
+          xI[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av[rb][ks]), as_bf16x8(bu[cb][ks]), xI[rb], 0, 0, 0);
+        }
+      sq_mag(xR, xI, m);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = r0 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
+        const int j = c0 + cb * 16 + (lane & 15);
+        if (i < j && j < a.n && !(__uint_as_float(m[q]) < thr_sq)) hits[atomicAdd(&nhits, 1)] = make_int2(i, j);
+      }
     }
     __syncthreads();
+    const int nh = nhits;
+    uint64_t best = 0;
+    if (nh <= 16) {
+      // the usual case: a few pairs, each by the whole wave
+      for (int e = 0; e < nh; ++e) {
+        const int2 h = hits[e];
+        const uint64_t mb = pair_f64_wave(c64, a.ld64, a.d, h.x, h.y);
+        best = mb > best ? mb : best;
+      }
+    } else {
+      for (int e = lane; e < nh; e += 64) {
+        const int2 h = hits[e];
+        const uint64_t mb = pair_f64(c64, a.ld64, a.d, h.x, h.y);
+        best = mb > best ? mb : best;
+      }
+    }
+    __syncthreads();  // the list is rebuilt by the next item
+    best = wave_max_u64(best);
+    if (lane == 0 && best) atomicMax((unsigned long long*)&a.recheck_max[slot], (unsigned long long)best);
   }
 }
 
@@ -756,7 +779,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16_chunked(GramArgs a) {
 
 template <int KS>
 hipError_t launch_rp(const RecheckArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_recheck_pairs<KS>, dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_recheck_pairs<KS>, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -807,7 +830,8 @@ hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
 }
 
 hipError_t launch_recheck_pairs(const RecheckArgs& a, hipStream_t s) {
-  const int grid = a.list_cap < 1024 ? a.list_cap : 1024;
+  const long items = 16L * a.list_cap;
+  const int grid = (int)(items < 4096 ? items : 4096);
   switch (a.ldk16 / 32) {
     case 1: return launch_rp<1>(a, grid, s);
     case 2: return launch_rp<2>(a, grid, s);
