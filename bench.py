@@ -126,7 +126,8 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8, breakdown_steps=10):
 
 def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
     """The batched workload: 512 independent searches, d uniform in {3..16},
-    N uniform in [d+1, d^2], 64 candidates each, one persistent launch per
+    N uniform in [d+1, d^2], 64 candidates each, one persistent launch (plus a
+    finalizing launch) per
     step; candidate evaluations per second over all instances."""
     import inputs
     specs = [{"n": n, "d": d, "seed": 0, "stream_id": k, "max_steps": 10 ** 9}
@@ -146,7 +147,8 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
     avg_us = 1e3 * ms / cnt
     return {
         "workload": f"{count} instances, d in {{3..16}}, N in [d+1, d^2], {candidates} candidates each, "
-                    "FP32 MFMA screen + certified FP64 pair recheck, one persistent launch per step",
+                    "FP32 MFMA screen + certified FP64 pair recheck, one persistent launch and one finalizing launch "
+                    "per step",
         "evals_per_s": count * candidates * steps / (t1 - t0),
         "ms_per_step": 1e3 * (t1 - t0) / steps,
         "kernel_avg_us": avg_us,

@@ -212,7 +212,9 @@ trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, vo
 
 /*
  * Batched form: `count` independent searches of different sizes advanced
- * together, one persistent kernel launch per step.  Instance i has its own
+ * together: per step, one persistent kernel launch evaluates every candidate
+ * of every instance and one finalizing launch selects, accepts and commits
+ * for every instance.  Instance i has its own
  * N_i, d_i, seed and stream (its draws are those of a single search with the
  * same seed and stream_id), its own frame, radius, step and flags, and its own
  * target / step limit; the candidate count, radius rule and near-tie threshold

@@ -244,8 +244,8 @@ def timing_read(kernel):
 
 
 class Batch:
-    """Many independent searches advanced together (one persistent launch per
-    step).  ``instances``: iterable of dicts with keys n, d and optionally seed,
+    """Many independent searches advanced together (per step, one persistent
+    launch over every candidate of every instance and one finalizing launch).  ``instances``: iterable of dicts with keys n, d and optionally seed,
     stream_id, target_mu, max_steps, waves_per_item (default: the autotuned
     table, else the library's choice)."""
 

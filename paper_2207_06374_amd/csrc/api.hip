@@ -524,8 +524,7 @@ BatchArgs batch_args(const trstmi_batch_params* p, const BatchLayout& L, char* w
   b.cand_max = (uint64_t*)(ws + L.cand);
   b.scratch = (double*)(ws + L.scratch);
   b.scratch_stride = L.scratch_stride;
-  b.next_unit = (int32_t*)(ws + L.hdr);
-  b.blocks_done = (int32_t*)(ws + L.hdr) + 1;
+  b.count = p->count;
   b.done_instances = (int32_t*)(ws + L.hdr) + 2;
   b.tau = p->near_tie > 0 ? p->near_tie : 2e-12;
   b.grow = p->grow;

@@ -1,5 +1,6 @@
-// Batched form: many independent, uneven searches advanced by one persistent
-// kernel per step.
+// Batched form: many independent, uneven searches advanced together, one
+// persistent kernel launch for every candidate of every instance plus one
+// finalizing launch per step.
 //
 // Every instance i is an independent search (its own N_i, d_i, frame, radius,
 // step and RNG stream) with the candidate rule of the single-frame path:
@@ -8,8 +9,10 @@
 //
 // Work: a unit is 1, 2 or 4 candidates of one instance, processed by one
 // block of 4 wavefronts split into groups of `wpi` waves per candidate (the
-// per-instance tile choice).  Blocks take units from an atomic counter,
-// largest instances first.  Per candidate the group
+// per-instance tile choice).  The step kernel is launched with at most as
+// many blocks as the device holds at once; block b takes units b, b + grid,
+// ... of the list (largest instances first), so no work counter is shared.
+// Per candidate the group
 //   1. draws and renormalises the candidate in FP64 (FP64 copy to global
 //      scratch, FP32 copy to LDS);
 //   2. screens every pair j < k with v_mfma_f32_16x16x4_f32 on the FP32 copy,
@@ -17,11 +20,12 @@
 //   3. re-evaluates exactly in FP64 the pairs whose screened |G| is within
 //      2 eps32 of the screened maximum (eps32 bounds |screened - exact| for
 //      unit columns, so the exact maximiser is among them): every candidate
-//      ends with its exact FP64 coherence.
-// The group that completes an instance's last candidate (atomic count)
-// selects, accepts, updates the radius and regenerates the accepted candidate
-// in FP64 into the frame with a single wavefront.  No block ever waits for
-// another; the last block to leave resets the counters for the next launch.
+//      ends with its exact FP64 coherence, stored with a plain write.
+// The finalizing kernel (one block per instance) then selects, accepts,
+// updates the radius and regenerates the accepted candidate in FP64 into the
+// frame.  Handing the candidates' values over at the kernel boundary replaces
+// a device-scope release per candidate (each of which writes back the L2 of
+// its XCD) by the one at the end of the launch.
 
 #include "device_common.h"
 #include "launch.h"
@@ -46,7 +50,7 @@ struct alignas(16) BState {
   double radius;
   int64_t step;
   int32_t flags;
-  int32_t done_count;      // candidates of the current step finished
+  int32_t pad;
 };
 
 __device__ __forceinline__ double eps32(int d) {
@@ -182,66 +186,74 @@ __device__ __forceinline__ double bits_mu(uint64_t b) {
   return sqrt(__longlong_as_double((int64_t)b));
 }
 
-// Select / accept / radius update of instance i and the in-place FP64 commit,
-// by one wavefront.
-__device__ void finalize(const BatchArgs& a, int i) {
-  const BInst& I = ((const BInst*)a.inst)[i];
-  BState* S = (BState*)a.state + i;
-  const int lane = threadIdx.x & 63;
-  __threadfence();
-  double v1 = __builtin_inf(), v2 = __builtin_inf();
-  int c1 = 0x7fffffff;
-  for (int c = lane; c < a.C; c += 64) {
-    const uint64_t b = __hip_atomic_load(&a.cand_max[(size_t)i * a.C + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double mu = bits_mu(b);
-    if (a.rep_mu) a.rep_mu[(size_t)i * a.C + c] = mu;
-    if (!(mu < __builtin_inf())) continue;
-    if (mu < v1 || (mu == v1 && c < c1)) {
-      v2 = v1;
-      v1 = mu;
-      c1 = c;
-    } else if (mu < v2) {
-      v2 = mu;
-    }
-  }
+// Select / accept / radius update and the in-place FP64 commit, one block per
+// instance (grid-stride): wave 0 reduces the candidates' exact values, the
+// whole block regenerates the accepted candidate.
+__global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
+  __shared__ int acc_s;
+  __shared__ int best_s;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  for (int i = blockIdx.x; i < a.count; i += gridDim.x) {
+    const BInst I = ((const BInst*)a.inst)[i];
+    BState* S = (BState*)a.state + i;
+    const BState S0 = *S;
+    if (S0.flags & kFlagDone) continue;  // uniform across the block
+    if (tid < 64) {
+      double v1 = __builtin_inf(), v2 = __builtin_inf();
+      int c1 = 0x7fffffff;
+      for (int c = lane; c < a.C; c += 64) {
+        const double mu = bits_mu(a.cand_max[(size_t)i * a.C + c]);
+        if (a.rep_mu) a.rep_mu[(size_t)i * a.C + c] = mu;
+        if (!(mu < __builtin_inf())) continue;
+        if (mu < v1 || (mu == v1 && c < c1)) {
+          v2 = v1;
+          v1 = mu;
+          c1 = c;
+        } else if (mu < v2) {
+          v2 = mu;
+        }
+      }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov1 = __shfl_xor(v1, off, 64), ov2 = __shfl_xor(v2, off, 64);
-    const int oc1 = __shfl_xor(c1, off, 64);
-    if (ov1 < v1 || (ov1 == v1 && oc1 < c1)) {
-      v2 = fmin(v1, ov2);
-      v1 = ov1;
-      c1 = oc1;
-    } else {
-      v2 = fmin(v2, ov1);
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov1 = __shfl_xor(v1, off, 64), ov2 = __shfl_xor(v2, off, 64);
+        const int oc1 = __shfl_xor(c1, off, 64);
+        if (ov1 < v1 || (ov1 == v1 && oc1 < c1)) {
+          v2 = fmin(v1, ov2);
+          v1 = ov1;
+          c1 = oc1;
+        } else {
+          v2 = fmin(v2, ov1);
+        }
+      }
+      const bool valid = c1 != 0x7fffffff;
+      const bool accept = valid && v1 < S0.mu;
+      if (lane == 0) {
+        acc_s = accept ? 1 : 0;
+        best_s = c1;
+        bool near = valid && fabs(v1 - S0.mu) <= a.tau;
+        if (valid && v2 - v1 <= a.tau) near = true;
+        const double new_mu = accept ? v1 : S0.mu;
+        const double new_rad = accept ? fmin(S0.radius * a.grow, a.radius_max) : fmax(S0.radius * a.shrink, a.radius_min);
+        const int64_t nt = S0.step + 1;
+        const bool done = (I.target_mu > 0.0 && new_mu <= I.target_mu) || nt >= I.max_steps;
+        S->mu = new_mu;
+        S->radius = new_rad;
+        S->step = nt;
+        S->flags = (accept ? kFlagAccepted : 0) | (near ? kFlagNearTie : 0) | (valid ? 0 : kFlagNoValid) |
+                   (done ? kFlagDone : 0);
+        if (a.rep_best) a.rep_best[i] = valid ? c1 : -1;
+        if (done) atomicAdd(a.done_instances, 1);
+      }
     }
-  }
-  const double mu_t = S->mu;
-  const double rad = S->radius;
-  const int64_t t = S->step;
-  const bool valid = c1 != 0x7fffffff;
-  const bool accept = valid && v1 < mu_t;
-  if (accept) {
-    // regenerate candidate c1 of step t into the frame, in place
-    double* frame = a.frames + I.frame_off;
-    gen_dispatch(I, frame, rad, c1, t, frame, nullptr, lane, 64);
-  }
-  if (lane == 0) {
-    bool near = valid && fabs(v1 - mu_t) <= a.tau;
-    if (valid && v2 - v1 <= a.tau) near = true;
-    const double new_mu = accept ? v1 : mu_t;
-    const double new_rad = accept ? fmin(rad * a.grow, a.radius_max) : fmax(rad * a.shrink, a.radius_min);
-    const int64_t nt = t + 1;
-    const bool done = (I.target_mu > 0.0 && new_mu <= I.target_mu) || nt >= I.max_steps;
-    S->mu = new_mu;
-    S->radius = new_rad;
-    S->step = nt;
-    S->flags = (accept ? kFlagAccepted : 0) | (near ? kFlagNearTie : 0) | (valid ? 0 : kFlagNoValid) |
-               (done ? kFlagDone : 0);
-    if (a.rep_best) a.rep_best[i] = valid ? c1 : -1;
-    S->done_count = 0;
-    if (done) atomicAdd(a.done_instances, 1);
-    __threadfence();
+    __syncthreads();
+    if (acc_s) {
+      // regenerate candidate best of step t into the frame, in place (each
+      // column is read and rewritten by the same lanes)
+      double* frame = a.frames + I.frame_off;
+      gen_dispatch(I, frame, S0.radius, best_s, S0.step, frame, nullptr, tid, kThreads);
+    }
+    __syncthreads();
   }
 }
 
@@ -250,17 +262,11 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
   __shared__ uint32_t smax[4];
   __shared__ unsigned long long umax[4];
-  __shared__ int unit_s;
-  __shared__ int fin_s[4];
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
 
-  for (;;) {
-    if (tid == 0) unit_s = atomicAdd(a.next_unit, 1);
-    __syncthreads();
-    const int u = unit_s;
-    if (u >= a.nunits) break;
+  for (int u = blockIdx.x; u < a.nunits; u += gridDim.x) {
     const int2 unit = a.units[u];
     const int i = unit.x;
     const BInst I = ((const BInst*)a.inst)[i];
@@ -282,7 +288,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
     if (tid < 4) {
       smax[tid] = 0;
       umax[tid] = 0;
-      fin_s[tid] = 0;
     }
     __syncthreads();
     if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, wg * 64 + lane, wpi * 64);
@@ -339,31 +344,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
     }
     __syncthreads();
 
-    // 4. publish; the group finishing the instance's last candidate finalizes it
-    if (wg == 0 && lane == 0 && c < a.C) {
-      if (work) a.cand_max[(size_t)i * a.C + c] = umax[g];
-      __threadfence();
-      const int old = atomicAdd(&((BState*)a.state)[i].done_count, 1);
-      fin_s[g] = old == a.C - 1 ? 1 : 0;
-    }
+    // 4. publish (read by the finalizing launch)
+    if (work && wg == 0 && lane == 0) a.cand_max[(size_t)i * a.C + c] = umax[g];
     __syncthreads();
-    if (wg == 0 && fin_s[g]) {
-      if (skip_inst) {
-        if (lane == 0) ((BState*)a.state)[i].done_count = 0;
-      } else {
-        finalize(a, i);
-      }
-    }
-    __syncthreads();
-  }
-
-  if (tid == 0) {
-    __threadfence();
-    if (atomicAdd(a.blocks_done, 1) == (int)gridDim.x - 1) {
-      *a.next_unit = 0;
-      *a.blocks_done = 0;
-      __threadfence();
-    }
   }
 }
 
@@ -434,7 +417,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count,
       S->mu = mu;
       S->radius = radius0;
       S->step = 0;
-      S->done_count = 0;
       const bool done = (I.target_mu > 0.0 && mu <= I.target_mu) || I.max_steps <= 0;
       S->flags = done ? kFlagDone : 0;
       if (done) atomicAdd(a.done_instances, 1);
@@ -447,6 +429,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count,
 
 hipError_t launch_batch_step(const BatchArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_step, dim3(grid), dim3(kThreads), 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int fgrid = a.count < 4096 ? a.count : 4096;
+  hipLaunchKernelGGL(k_batch_finalize, dim3(fgrid > 0 ? fgrid : 1), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

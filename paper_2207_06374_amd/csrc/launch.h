@@ -131,7 +131,8 @@ struct InitFinishArgs {
   double* mu_out;            // coherence entry: write mu here instead (state pointers null)
 };
 
-// Batched form (batch.hip).
+// Batched form (batch.hip).  launch_batch_step enqueues the step kernel
+// (`grid` blocks, at most the resident capacity) and the finalizing kernel.
 struct BatchArgs {
   const void* inst;          // [count] instance descriptors
   void* state;               // [count] per-instance state
@@ -142,8 +143,7 @@ struct BatchArgs {
   uint64_t* cand_max;        // [count][C] exact FP64 max |G|^2 bits of the step's candidates
   double* scratch;           // per block and group: one FP64 candidate
   int64_t scratch_stride;    // doubles per scratch slot
-  int32_t* next_unit;        // work counter (reset by the last block)
-  int32_t* blocks_done;
+  int32_t count;             // instances
   int32_t* done_instances;   // instances that reached DONE
   double tau, grow, shrink, radius_min, radius_max;
   double* rep_mu;            // [count][C] or null
