@@ -127,8 +127,8 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8, breakdown_steps=10):
 def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
     """The batched workload: 512 independent searches, d uniform in {3..16},
     N uniform in [d+1, d^2], 64 candidates each, one persistent launch (plus a
-    finalizing launch) per
-    step; candidate evaluations per second over all instances."""
+    finalizing launch) per step; candidate evaluations per second over all
+    instances."""
     import inputs
     specs = [{"n": n, "d": d, "seed": 0, "stream_id": k, "max_steps": 10 ** 9}
              for k, (d, n) in enumerate(inputs.batched_instances(count, seed=0))]
