@@ -138,34 +138,52 @@ __device__ __forceinline__ void gen_dispatch(const BInst& I, const double* frame
   else gen_candidate<8>(I, frame, radius, c, t, out, lds, lane_g, nl);
 }
 
-// |G|^2 of the 16 x 16 pair block (bi, bj) from the FP32 copy in LDS;
-// m[v] = output (row 4 (lane/16) + v, column lane % 16) of the block, 0 where
-// the pair is not (j > i, j < n).
-__device__ __forceinline__ void screen_block(const float* L, int ldk, int n, int d, int bi, int bj, float m[4]) {
+// FP32 fragments from the LDS copy for v_mfma_f32_16x16x4_f32, KSt steps of
+// 4 over K = 2d: lane l holds row / column 16 blk + l % 16 at k = 4 s + l / 16.
+// The A side is u (row block bi); the B side is u and v = (b, -a) of column
+// block bj, so that Re = u_i . u_j and Im = u_i . v_j.
+template <int KSt>
+__device__ __forceinline__ void frag_a(const float* L, int ldk, int n, int K, int bi, float a[KSt]) {
   const int lane = threadIdx.x & 63;
-  const int kl = lane >> 4;
-  const bool odd = kl & 1;
-  const float* ra = L + (size_t)(bi * 16 + (lane & 15)) * ldk;
-  const float* rb = L + (size_t)(bj * 16 + (lane & 15)) * ldk;
-  const bool ina = bi * 16 + (lane & 15) < n, inb = bj * 16 + (lane & 15) < n;
+  const int row = bi * 16 + (lane & 15);
+#pragma unroll
+  for (int st = 0; st < KSt; ++st) {
+    const int k = 4 * st + (lane >> 4);
+    a[st] = (row < n && k < K) ? L[(size_t)row * ldk + k] : 0.f;
+  }
+}
+
+template <int KSt>
+__device__ __forceinline__ void frag_b(const float* L, int ldk, int n, int K, int bj, float bu[KSt], float bv[KSt]) {
+  const int lane = threadIdx.x & 63;
+  const int col = bj * 16 + (lane & 15);
+  const bool odd = (lane >> 4) & 1;
+#pragma unroll
+  for (int st = 0; st < KSt; ++st) {
+    const int k = 4 * st + (lane >> 4);
+    bu[st] = (col < n && k < K) ? L[(size_t)col * ldk + k] : 0.f;
+    const float x = (col < n && (k ^ 1) < K) ? L[(size_t)col * ldk + (k ^ 1)] : 0.f;
+    bv[st] = odd ? -x : x;
+  }
+}
+
+// |G|^2 of the 16 x 16 pair block (bi, bj): m[v] = output (row 4 (lane/16) + v,
+// column lane % 16), 0 where the pair is not (j > i, j < n).
+template <int KSt>
+__device__ __forceinline__ void screen_frags(const float a[KSt], const float bu[KSt], const float bv[KSt], int n,
+                                             int bi, int bj, float m[4]) {
+  const int lane = threadIdx.x & 63;
   v4f32 accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-  const int K = 2 * d;
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + kl;
-    const float a = (ina && k < K) ? ra[k] : 0.f;
-    const float bu = (inb && k < K) ? rb[k] : 0.f;
-    const int kx = k ^ 1;
-    const float x = (inb && kx < K) ? rb[kx] : 0.f;
-    const float bv = odd ? -x : x;
-    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bu, accR, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, accI, 0, 0, 0);
+#pragma unroll
+  for (int st = 0; st < KSt; ++st) {
+    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], bu[st], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], bv[st], accI, 0, 0, 0);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = bi * 16 + 4 * (lane >> 4) + v;
     const int j = bj * 16 + (lane & 15);
-    const float re = accR[v], im = accI[v];
-    m[v] = (i < j && j < n) ? fmaf(re, re, im * im) : 0.f;
+    m[v] = (i < j && j < n) ? fmaf(accR[v], accR[v], accI[v] * accI[v]) : 0.f;
   }
 }
 
@@ -173,6 +191,7 @@ __device__ __forceinline__ uint64_t pair_f64_b(const double* c64, int d, int j, 
   const double2* x = (const double2*)(c64 + 2 * (size_t)j * d);
   const double2* y = (const double2*)(c64 + 2 * (size_t)k * d);
   double re = 0.0, im = 0.0;
+#pragma unroll 4
   for (int i = 0; i < d; ++i) {
     const double2 p = x[i], q = y[i];
     re += p.x * q.x + p.y * q.y;
@@ -257,6 +276,85 @@ __global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
   }
 }
 
+template <int KSt>
+__device__ void screen_phase(const BInst& I, const float* L, const double* c64, int nbk, int nblk, int wg, int wpi,
+                             bool work, uint32_t* blkmax, uint32_t* smax, unsigned long long* umax) {
+  const int lane = threadIdx.x & 63;
+  const int n = I.n, K = 2 * I.d;
+  float a[KSt], bu[KSt], bv[KSt];
+  if (work) {
+    uint32_t wmax = 0;
+    int cur = -1;
+    for (int b = wg; b < nblk; b += wpi) {
+      int bi, bj;
+      tile_decode(b, nbk, bi, bj);
+      if (bi != cur) {  // the A fragments serve the whole row of blocks
+        frag_a<KSt>(L, I.ldk, n, K, bi, a);
+        cur = bi;
+      }
+      frag_b<KSt>(L, I.ldk, n, K, bj, bu, bv);
+      float m[4];
+      screen_frags<KSt>(a, bu, bv, n, bi, bj, m);
+      uint32_t bm = __float_as_uint(m[0]);
+#pragma unroll
+      for (int v = 1; v < 4; ++v) bm = __float_as_uint(m[v]) > bm ? __float_as_uint(m[v]) : bm;
+      bm = wave_max_u32_dpp(bm);
+      if (lane == 0) blkmax[b] = bm;
+      wmax = bm > wmax ? bm : wmax;
+    }
+    if (lane == 0) atomicMax(smax, wmax);
+  }
+  __syncthreads();
+  if (work) {
+    const uint32_t sb = *smax;
+    if (sb >= kInfBits32) {
+      if (wg == 0 && lane == 0) *umax = ~0ull;  // non-finite column: invalid candidate
+    } else {
+      const double thr = sqrt((double)__uint_as_float(sb)) - 2.0 * eps32(I.d);
+      const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
+      uint64_t best = 0;
+      for (int b = wg; b < nblk; b += wpi) {
+        if (__uint_as_float(blkmax[b]) < thr_sq) continue;
+        int bi, bj;
+        tile_decode(b, nbk, bi, bj);
+        frag_a<KSt>(L, I.ldk, n, K, bi, a);
+        frag_b<KSt>(L, I.ldk, n, K, bj, bu, bv);
+        float m[4];
+        screen_frags<KSt>(a, bu, bv, n, bi, bj, m);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ii = bi * 16 + 4 * (lane >> 4) + v;
+          const int jj = bj * 16 + (lane & 15);
+          if (ii < jj && jj < n && !(m[v] < thr_sq)) {
+            const uint64_t pb = pair_f64_b(c64, I.d, ii, jj);
+            best = pb > best ? pb : best;
+          }
+        }
+      }
+      best = wave_max_u64(best);
+      if (lane == 0) atomicMax(umax, (unsigned long long)best);
+    }
+  }
+  __syncthreads();
+}
+
+// K = 2d <= 32: ceil(d / 2) steps of 4.
+__device__ __forceinline__ void screen_dispatch(const BInst& I, const float* L, const double* c64, int nbk, int nblk,
+                                                int wg, int wpi, int g, bool work, uint32_t* blkmax, uint32_t* smax,
+                                                unsigned long long* umax) {
+  (void)g;
+  switch ((I.d + 1) >> 1) {
+    case 1: screen_phase<1>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    case 2: screen_phase<2>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    case 3: screen_phase<3>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    case 4: screen_phase<4>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    case 5: screen_phase<5>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    case 6: screen_phase<6>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    case 7: screen_phase<7>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+    default: screen_phase<8>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
   __shared__ float lds[kLdsFloats];
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
@@ -294,55 +392,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
     __threadfence_block();
     __syncthreads();
 
-    // 2. FP32 screen: block maxima and the candidate maximum
-    if (work) {
-      uint32_t wmax = 0;
-      for (int b = wg; b < nblk; b += wpi) {
-        int bi, bj;
-        tile_decode(b, nbk, bi, bj);
-        float m[4];
-        screen_block(L, I.ldk, n, I.d, bi, bj, m);
-        uint32_t bm = __float_as_uint(m[0]);
-#pragma unroll
-        for (int v = 1; v < 4; ++v) bm = __float_as_uint(m[v]) > bm ? __float_as_uint(m[v]) : bm;
-        bm = wave_max_u32_dpp(bm);
-        if (lane == 0) blkmax[g][b] = bm;
-        wmax = bm > wmax ? bm : wmax;
-      }
-      if (lane == 0) atomicMax(&smax[g], wmax);
-    }
-    __syncthreads();
-
+    // 2. FP32 screen: block maxima and the candidate maximum;
     // 3. certified FP64 recheck of the pairs that can attain the maximum
-    if (work) {
-      const uint32_t sb = smax[g];
-      if (sb >= kInfBits32) {
-        if (wg == 0 && lane == 0) umax[g] = ~0ull;  // non-finite column: invalid candidate
-      } else {
-        const double thr = sqrt((double)__uint_as_float(sb)) - 2.0 * eps32(I.d);
-        const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
-        uint64_t best = 0;
-        for (int b = wg; b < nblk; b += wpi) {
-          if (__uint_as_float(blkmax[g][b]) < thr_sq) continue;
-          int bi, bj;
-          tile_decode(b, nbk, bi, bj);
-          float m[4];
-          screen_block(L, I.ldk, n, I.d, bi, bj, m);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int ii = bi * 16 + 4 * (lane >> 4) + v;
-            const int jj = bj * 16 + (lane & 15);
-            if (ii < jj && jj < n && !(m[v] < thr_sq)) {
-              const uint64_t pb = pair_f64_b(c64, I.d, ii, jj);
-              best = pb > best ? pb : best;
-            }
-          }
-        }
-        best = wave_max_u64(best);
-        if (lane == 0) atomicMax(&umax[g], (unsigned long long)best);
-      }
-    }
-    __syncthreads();
+    screen_dispatch(I, L, c64, nbk, nblk, wg, wpi, g, work, blkmax[g], &smax[g], &umax[g]);
 
     // 4. publish (read by the finalizing launch)
     if (work && wg == 0 && lane == 0) a.cand_max[(size_t)i * a.C + c] = umax[g];
