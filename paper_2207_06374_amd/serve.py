@@ -244,6 +244,7 @@ def summarize(reqs, wall, candidates, peak_bytes, cap_bytes):
         "mean_queue_s": float(np.mean([r.admit - r.arrival for r in done])) if done else math.nan,
         "evals_per_s": evals / wall if wall > 0 else math.nan,
         "wall_s": wall,
+        "median_mu_over_welch": float(np.median([r.mu / welch_bound(r.n, r.d) for r in done])) if done else math.nan,
         "pool_peak_bytes": int(peak_bytes),
         "pool_cap_bytes": int(cap_bytes),
         "first_error": next((r.error for r in reqs if r.status == "error"), ""),
