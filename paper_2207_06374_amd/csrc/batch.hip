@@ -65,7 +65,7 @@ __device__ __forceinline__ double eps32(int d) {
 
 // Candidate c of instance I at step t, column col, Philox block q (entries 2q, 2q+1).
 __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, double s, int c, int64_t t,
-                                           int64_t col, int q, double y[4], bool& two) {
+                                           int64_t col, int q, const double2* tab, double y[4], bool& two) {
   const int d = I.d;
   const int nb = (d + 1) >> 1;
   const int i0 = 2 * q;
@@ -73,8 +73,8 @@ __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, 
   const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, 0u};
   const u32x4 w = philox4x32_10(ctr, I.seed, I.stream_id);
   double g0, g1, g2, g3;
-  box_muller(w.x, w.y, g0, g1);
-  box_muller(w.z, w.w, g2, g3);
+  box_muller(w.x, w.y, tab, g0, g1);
+  box_muller(w.z, w.w, tab, g2, g3);
   const double h = 0.7071067811865476;
   const double* bp = frame + 2 * ((size_t)col * d + i0);
   y[0] = bp[0] + s * (g0 * h);
@@ -89,7 +89,7 @@ __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, 
 // reduced with xor-shuffles inside the column's lanes.
 template <int LPC>
 __device__ void gen_candidate(const BInst& I, const double* frame, double radius, int c, int64_t t, double* out,
-                              float* lds, int lane_g, int nl) {
+                              float* lds, const double2* tab, int lane_g, int nl) {
   const int d = I.d;
   const int nb = (d + 1) >> 1;
   const double s = radius / sqrt((double)d);
@@ -100,7 +100,7 @@ __device__ void gen_candidate(const BInst& I, const double* frame, double radius
     const bool active = col < I.n && lq < nb;
     double y[4] = {0.0, 0.0, 0.0, 0.0};
     bool two = false;
-    if (active) draw_block(I, frame, s, c, t, col, lq, y, two);
+    if (active) draw_block(I, frame, s, c, t, col, lq, tab, y, two);
     double nrm2 = (y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]);
 #pragma unroll
     for (int off = LPC / 2; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
@@ -129,13 +129,13 @@ __device__ void gen_candidate(const BInst& I, const double* frame, double radius
 }
 
 __device__ __forceinline__ void gen_dispatch(const BInst& I, const double* frame, double radius, int c, int64_t t,
-                                             double* out, float* lds, int lane_g, int nl) {
+                                             double* out, float* lds, const double2* tab, int lane_g, int nl) {
   // d <= 16: at most 8 blocks per column
   const int nb = (I.d + 1) >> 1;
-  if (nb <= 1) gen_candidate<1>(I, frame, radius, c, t, out, lds, lane_g, nl);
-  else if (nb <= 2) gen_candidate<2>(I, frame, radius, c, t, out, lds, lane_g, nl);
-  else if (nb <= 4) gen_candidate<4>(I, frame, radius, c, t, out, lds, lane_g, nl);
-  else gen_candidate<8>(I, frame, radius, c, t, out, lds, lane_g, nl);
+  if (nb <= 1) gen_candidate<1>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
+  else if (nb <= 2) gen_candidate<2>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
+  else if (nb <= 4) gen_candidate<4>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
+  else gen_candidate<8>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
 }
 
 // FP32 fragments from the LDS copy for v_mfma_f32_16x16x4_f32, KSt steps of
@@ -211,8 +211,11 @@ __device__ __forceinline__ double bits_mu(uint64_t b) {
 __global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
   __shared__ int acc_s;
   __shared__ int best_s;
+  __shared__ double2 sctab[kSinCosTab];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  fill_sincos_tab(sctab);
+  __syncthreads();
   for (int i = blockIdx.x; i < a.count; i += gridDim.x) {
     const BInst I = ((const BInst*)a.inst)[i];
     BState* S = (BState*)a.state + i;
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
       // regenerate candidate best of step t into the frame, in place (each
       // column is read and rewritten by the same lanes)
       double* frame = a.frames + I.frame_off;
-      gen_dispatch(I, frame, S0.radius, best_s, S0.step, frame, nullptr, tid, kThreads);
+      gen_dispatch(I, frame, S0.radius, best_s, S0.step, frame, nullptr, sctab, tid, kThreads);
     }
     __syncthreads();
   }
@@ -360,9 +363,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
   __shared__ uint32_t smax[4];
   __shared__ unsigned long long umax[4];
+  __shared__ double2 sctab[kSinCosTab];
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
+  fill_sincos_tab(sctab);
+  __syncthreads();
 
   for (int u = blockIdx.x; u < a.nunits; u += gridDim.x) {
     const int2 unit = a.units[u];
@@ -388,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
       umax[tid] = 0;
     }
     __syncthreads();
-    if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, wg * 64 + lane, wpi * 64);
+    if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, sctab, wg * 64 + lane, wpi * 64);
     __threadfence_block();
     __syncthreads();
 
@@ -406,7 +412,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
 // block per instance (grid-stride).
 __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count, double radius0) {
   __shared__ unsigned long long umax;
+  __shared__ double2 sctab[kSinCosTab];
   const int tid = threadIdx.x;
+  fill_sincos_tab(sctab);
+  __syncthreads();
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const BInst I = ((const BInst*)a.inst)[i];
     double* frame = a.frames + I.frame_off;
@@ -420,8 +429,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count,
       const u32x4 ctr = {(uint32_t)(col * nb + q), 0u, 0u, 1u};
       const u32x4 w = philox4x32_10(ctr, I.seed, I.stream_id);
       double g0, g1, g2, g3;
-      box_muller(w.x, w.y, g0, g1);
-      box_muller(w.z, w.w, g2, g3);
+      box_muller(w.x, w.y, sctab, g0, g1);
+      box_muller(w.z, w.w, sctab, g2, g3);
       const double h = 0.7071067811865476;
       double* o = frame + 2 * ((size_t)col * d + 2 * q);
       o[0] = g0 * h;

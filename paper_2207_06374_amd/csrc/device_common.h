@@ -135,13 +135,40 @@ __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
   cs = ((q + 1) & 2) ? -b : b;
 }
 
+// Table of (cos, sin)(2 pi i / 256), i = 0..255, filled into LDS by every
+// kernel that draws Gaussians (the same function fills it everywhere).
+constexpr int kSinCosTab = 256;
+
+__device__ __forceinline__ void fill_sincos_tab(double2* tab) {
+  for (int i = threadIdx.x; i < kSinCosTab; i += blockDim.x) {
+    double sn, cs;
+    sincos_2pi(i * (1.0 / kSinCosTab), sn, cs);
+    tab[i] = make_double2(cs, sn);
+  }
+}
+
+// (sin, cos)(2 pi u) for u = (w + 1/2) 2^-32: the top 8 bits of w select the
+// table angle a = 2 pi i / 256, the rest give b = 2 pi ((w mod 2^24) + 1/2)
+// 2^-32 in (0, 2 pi / 256), exactly reduced; sin b through b^7 and 1 - cos b
+// through b^8 (first omitted terms below 2^-60 of the result), then the
+// angle-sum rotation.
+__device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double2* tab, double& sn, double& cs) {
+  const double2 t = tab[w >> 24];
+  const double rho = ((double)(w & 0xFFFFFFu) + 0.5) * 0x1p-32;
+  const double b = rho * 6.283185307179586;
+  const double z = b * b;
+  const double sb = fma(b * z, fma(z, fma(z, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), b);
+  const double cm = z * fma(z, fma(z, fma(z, -1.0 / 40320.0, 1.0 / 720.0), -1.0 / 24.0), 0.5);
+  cs = fma(-t.y, sb, fma(-t.x, cm, t.x));
+  sn = fma(t.x, sb, fma(-t.y, cm, t.y));
+}
+
 // Box-Muller (1958): (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0), in FP64.
-__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, double& g0, double& g1) {
+__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, const double2* tab, double& g0, double& g1) {
   const double u0 = word_to_unit(w0);
-  const double u1 = word_to_unit(w1);
   const double r = sqrt_pos(-2.0 * log_unit(u0));
   double s, c;
-  sincos_2pi(u1, s, c);
+  sincos_2pi_word(w1, tab, s, c);
   g0 = r * c;
   g1 = r * s;
 }

@@ -69,6 +69,9 @@ __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot
 template <int LPC, int Q>
 __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   if (a.gate && ((*a.gate & a.gate_mask) != a.gate_want)) return;
+  __shared__ double2 sctab[kSinCosTab];
+  fill_sincos_tab(sctab);
+  __syncthreads();
   const int slot = blockIdx.y;
   if (a.zero_max && blockIdx.x == 0 && threadIdx.x == 0) a.zero_max[slot] = 0;
 
@@ -112,8 +115,8 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
           const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, a.tag};
           const u32x4 w = philox4x32_10(ctr, a.seed, a.stream_id);
           double g0, g1, g2, g3;
-          box_muller(w.x, w.y, g0, g1);
-          box_muller(w.z, w.w, g2, g3);
+          box_muller(w.x, w.y, sctab, g0, g1);
+          box_muller(w.z, w.w, sctab, g2, g3);
           const double h = 0.7071067811865476;  // sqrt(1/2), correctly rounded
           z[0] = g0 * h;
           z[1] = g1 * h;
