@@ -161,3 +161,18 @@ def test_round_bf16_argument_checks(L):
     assert L.trstmi_round_bf16(None, -1, None, None) == abi.E_INVALID_ARG
     assert L.trstmi_round_bf16(None, 4, ctypes.c_void_p(256), None) == abi.E_INVALID_ARG
     assert L.trstmi_round_bf16(ctypes.c_void_p(260), 4, ctypes.c_void_p(256), None) == abi.E_INVALID_ARG
+
+
+def test_timing_controls_without_device(L):
+    """Timing settings are host-side: enabling, limiting to one kernel and
+    reading totals work (and read zero) with nothing launched."""
+    assert L.trstmi_timing_only(b"gram_bf16") == abi.OK
+    assert L.trstmi_timing_enable(1) == abi.OK
+    assert L.trstmi_timing_enable(0) == abi.OK
+    assert L.trstmi_timing_only(None) == abi.OK
+    ms = ctypes.c_double(-1.0)
+    cnt = ctypes.c_int64(-1)
+    assert L.trstmi_timing_read(b"perturb", ctypes.byref(ms), ctypes.byref(cnt)) == abi.OK
+    assert ms.value == 0.0 and cnt.value == 0
+    assert L.trstmi_timing_read(None, ctypes.byref(ms), ctypes.byref(cnt)) == abi.E_INVALID_ARG
+    assert L.trstmi_abi_version() >= 3

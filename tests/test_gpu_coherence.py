@@ -22,7 +22,7 @@ def _gpu_mu(F, mode):
 
 
 SHAPES = [(2, 1), (3, 2), (16, 4), (65, 3), (100, 7), (129, 5), (200, 16), (257, 33), (300, 64), (64, 128),
-          (130, 100), (1000, 32)]
+          (130, 100), (1000, 32), (70, 200), (40, 300), (33, 512)]
 
 
 @pytest.mark.parametrize("n,d", SHAPES)
