@@ -24,8 +24,13 @@ constexpr uint32_t kInfBits32 = 0x7F800000u;
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds on a 4-word
 // counter, 2-word key bumped by the Weyl constants between rounds.
-// One 32x32->64 multiply per product (v_mad_u64_u32) gives both halves.
+// One 32x32->64 multiply per product (v_mad_u64_u32) gives both halves, and
+// each three-way xor is one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -33,9 +38,30 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
     const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
     const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    c = u32x4{xor3(hi1, c.y, k0), lo1, xor3(hi0, c.w, k1), lo0};
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// The same generator for key words that are uniform across the wavefront.
+// The round keys are bumped in scalar registers inside every round: left to
+// itself the compiler precomputes all twenty of them once per kernel, and in
+// a kernel with many live scalars they spill to vector lanes and are read
+// back with one vector instruction each.  The empty asm hides the bumped key
+// from that hoisting; it emits no instruction.
+__device__ __forceinline__ u32x4 philox4x32_10_uniform_key(u32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = u32x4{xor3(hi1, c.y, k0), lo1, xor3(hi0, c.w, k1), lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    asm volatile("" : "+s"(k0), "+s"(k1));
   }
   return c;
 }

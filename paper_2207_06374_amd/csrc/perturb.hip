@@ -26,14 +26,15 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kMaxQ = 4;  // blocks per lane: d <= 2 * 64 * kMaxQ = 512 (Q below is the compiled bound)
 
+template <int OUT>
 __device__ __forceinline__ void store_pair(const PerturbArgs& a, size_t slot, int64_t col, int i,
                                            double re0, double im0, double re1, double im1, bool two) {
   const size_t off = slot * (size_t)a.out_slot_stride + (size_t)col * a.out_ld + 2 * (size_t)i;
-  if (a.out_kind == kOutF64) {
+  if constexpr (OUT == kOutF64) {
     double* o = (double*)a.out + off;
     *(double2*)o = make_double2(re0, im0);
     if (two) *(double2*)(o + 2) = make_double2(re1, im1);
-  } else if (a.out_kind == kOutF32) {
+  } else if constexpr (OUT == kOutF32) {
     float* o = (float*)a.out + off;
     if (two) {
       *(float4*)o = make_float4((float)re0, (float)im0, (float)re1, (float)im1);
@@ -52,13 +53,14 @@ __device__ __forceinline__ void store_pair(const PerturbArgs& a, size_t slot, in
   }
 }
 
+template <int OUT>
 __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot, int64_t col) {
   // elements [2d, out_ld) of the column
   const size_t off = slot * (size_t)a.out_slot_stride + (size_t)col * a.out_ld;
   for (int k = 2 * a.d; k < a.out_ld; ++k) {
-    if (a.out_kind == kOutF64) {
+    if constexpr (OUT == kOutF64) {
       ((double*)a.out)[off + k] = 0.0;
-    } else if (a.out_kind == kOutF32) {
+    } else if constexpr (OUT == kOutF32) {
       ((float*)a.out)[off + k] = 0.0f;
     } else {
       ((uint16_t*)a.out)[off + k] = 0;
@@ -66,9 +68,15 @@ __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot
   }
 }
 
-template <int LPC, int Q>
+// DRAW: compiled for the candidate form only (base frame present, Philox
+// draws, no explicit perturbation); otherwise the three fields decide.
+template <int LPC, int Q, int OUT, bool DRAW>
 __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   if (a.gate && ((*a.gate & a.gate_mask) != a.gate_want)) return;
+  const double* const base = a.base;
+  const bool has_base = DRAW || a.base != nullptr;
+  const bool have_z = DRAW || a.have_z != 0;
+  const double* const z_explicit = DRAW ? nullptr : a.z_explicit;
   __shared__ double2 sctab[kSinCosTab];
   fill_sincos_tab(sctab);
   __syncthreads();
@@ -80,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   const int d = a.d;
   const int nb = (d + 1) >> 1;
   double s = 0.0;
-  if (a.base && a.have_z) s = *a.radius / sqrt((double)d);
+  if (has_base && have_z) s = *a.radius / sqrt((double)d);
 
   constexpr int kColsPerWave = 64 / LPC;
   constexpr int kColsPerIter = (kThreads / 64) * kColsPerWave;
@@ -102,9 +110,9 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
       const int i0 = 2 * q;
       const bool two = (i0 + 1) < d;
       double z[4] = {0.0, 0.0, 0.0, 0.0};
-      if (a.have_z || !a.base) {
-        if (a.z_explicit) {
-          const double* zp = a.z_explicit + 2 * (((size_t)c * a.n + col) * d + i0);
+      if (have_z || !has_base) {
+        if (z_explicit) {
+          const double* zp = z_explicit + 2 * (((size_t)c * a.n + col) * d + i0);
           z[0] = zp[0];
           z[1] = zp[1];
           if (two) {
@@ -113,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
           }
         } else {
           const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, a.tag};
-          const u32x4 w = philox4x32_10(ctr, a.seed, a.stream_id);
+          const u32x4 w = philox4x32_10_uniform_key(ctr, a.seed, a.stream_id);
           double g0, g1, g2, g3;
           box_muller(w.x, w.y, sctab, g0, g1);
           box_muller(w.z, w.w, sctab, g2, g3);
@@ -124,12 +132,12 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
           z[3] = g3 * h;
         }
       }
-      if (a.base) {
-        const double* bp = a.base + 2 * ((size_t)col * d + i0);
+      if (has_base) {
+        const double* bp = base + 2 * ((size_t)col * d + i0);
         const double2 p0 = *(const double2*)bp;
         double2 p1 = make_double2(0.0, 0.0);
         if (two) p1 = *(const double2*)(bp + 2);
-        if (a.have_z) {
+        if (have_z) {
           y[qi][0] = p0.x + s * z[0];
           y[qi][1] = p0.y + s * z[1];
           y[qi][2] = p1.x + s * z[2];
@@ -167,8 +175,8 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
       double o[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) o[e] = y[qi][e] * inv;
-      store_pair(a, slot, col, i0, o[0], o[1], o[2], o[3], two);
-      if (q == nb - 1 && a.out_ld > 2 * d) store_zero_pad(a, slot, col);
+      store_pair<OUT>(a, slot, col, i0, o[0], o[1], o[2], o[3], two);
+      if (q == nb - 1 && a.out_ld > 2 * d) store_zero_pad<OUT>(a, slot, col);
     }
   }
 }
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_round_bf16(const double* x, int64_
   }
 }
 
-template <int LPC, int Q>
+template <int LPC, int Q, int OUT, bool DRAW = false>
 hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
   int64_t groups = (a.n + kColsPerIter - 1) / kColsPerIter;
@@ -205,36 +213,48 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   int64_t want = (8192 + slots - 1) / slots;
   if (want < 1) want = 1;
   const int gx = (int)(groups < want ? groups : want);
-  hipLaunchKernelGGL((k_perturb<LPC, Q>), dim3(gx, slots), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_perturb<LPC, Q, OUT, DRAW>), dim3(gx, slots), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+// Screen copies (FP32 or BF16): 4 blocks per lane, so the column norm's
+// square root and division are shared by more entries.
+template <int OUT, bool DRAW>
+hipError_t launch_screen_copies(const PerturbArgs& a, int nb, int slots, hipStream_t s) {
+  if (nb <= 4) return launch_lpc<1, 4, OUT, DRAW>(a, slots, s);
+  if (nb <= 8) return launch_lpc<2, 4, OUT, DRAW>(a, slots, s);
+  if (nb <= 16) return launch_lpc<4, 4, OUT, DRAW>(a, slots, s);
+  if (nb <= 32) return launch_lpc<8, 4, OUT, DRAW>(a, slots, s);
+  if (nb <= 64) return launch_lpc<16, 4, OUT, DRAW>(a, slots, s);
+  if (nb <= 128) return launch_lpc<32, 4, OUT, DRAW>(a, slots, s);
+  return launch_lpc<64, kMaxQ, OUT, DRAW>(a, slots, s);
 }
 
 }  // namespace
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
   const int nb = (a.d + 1) / 2;
-  if (a.out_kind != kOutF64) {
-    // screen copies: 4 blocks per lane, so the column norm's square root and
-    // division are shared by more entries
-    if (nb <= 4) return launch_lpc<1, 4>(a, slots, s);
-    if (nb <= 8) return launch_lpc<2, 4>(a, slots, s);
-    if (nb <= 16) return launch_lpc<4, 4>(a, slots, s);
-    if (nb <= 32) return launch_lpc<8, 4>(a, slots, s);
-    if (nb <= 64) return launch_lpc<16, 4>(a, slots, s);
-    if (nb <= 128) return launch_lpc<32, 4>(a, slots, s);
-    return launch_lpc<64, kMaxQ>(a, slots, s);
+  const bool draw = a.base && a.have_z && !a.z_explicit;
+  if (a.out_kind == kOutF32) {
+    return draw ? launch_screen_copies<kOutF32, true>(a, nb, slots, s)
+                : launch_screen_copies<kOutF32, false>(a, nb, slots, s);
+  }
+  if (a.out_kind == kOutBF16) {
+    return draw ? launch_screen_copies<kOutBF16, true>(a, nb, slots, s)
+                : launch_screen_copies<kOutBF16, false>(a, nb, slots, s);
   }
   // FP64 frames and candidates (every launch that writes one candidate in
   // FP64 uses this same split, so its bits do not depend on the launch)
-  if (nb <= 1) return launch_lpc<1, 1>(a, slots, s);
-  if (nb <= 2) return launch_lpc<2, 1>(a, slots, s);
-  if (nb <= 4) return launch_lpc<4, 1>(a, slots, s);
-  if (nb <= 8) return launch_lpc<8, 1>(a, slots, s);
-  if (nb <= 16) return launch_lpc<16, 1>(a, slots, s);
-  if (nb <= 32) return launch_lpc<32, 1>(a, slots, s);
-  if (nb <= 64) return launch_lpc<64, 1>(a, slots, s);
-  if (nb <= 128) return launch_lpc<64, 2>(a, slots, s);
-  return launch_lpc<64, kMaxQ>(a, slots, s);
+  constexpr int F = kOutF64;
+  if (nb <= 1) return launch_lpc<1, 1, F>(a, slots, s);
+  if (nb <= 2) return launch_lpc<2, 1, F>(a, slots, s);
+  if (nb <= 4) return launch_lpc<4, 1, F>(a, slots, s);
+  if (nb <= 8) return launch_lpc<8, 1, F>(a, slots, s);
+  if (nb <= 16) return launch_lpc<16, 1, F>(a, slots, s);
+  if (nb <= 32) return launch_lpc<32, 1, F>(a, slots, s);
+  if (nb <= 64) return launch_lpc<64, 1, F>(a, slots, s);
+  if (nb <= 128) return launch_lpc<64, 2, F>(a, slots, s);
+  return launch_lpc<64, kMaxQ, F>(a, slots, s);
 }
 
 hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,
