@@ -65,22 +65,23 @@ __device__ __forceinline__ double eps32(int d) {
 
 // Candidate c of instance I at step t, column col, Philox block q (entries 2q, 2q+1).
 __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, double s, int c, int64_t t,
-                                           int64_t col, int q, const double2* tab, double y[4], bool& two) {
+                                           int64_t col, int q, const GaussTab& tab, double y[4], bool& two) {
   const int d = I.d;
   const int nb = (d + 1) >> 1;
   const int i0 = 2 * q;
   two = (i0 + 1) < d;
   const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, 0u};
   const u32x4 w = philox4x32_10(ctr, I.seed, I.stream_id);
-  double g0, g1, g2, g3;
-  box_muller(w.x, w.y, tab, g0, g1);
-  box_muller(w.z, w.w, tab, g2, g3);
-  const double h = 0.7071067811865476;
+  double r0, c0, s0, r1, c1, s1;
+  cn_polar(w.x, w.y, tab, r0, c0, s0);
+  cn_polar(w.z, w.w, tab, r1, c1, s1);
+  r0 *= s;
+  r1 *= s;
   const double* bp = frame + 2 * ((size_t)col * d + i0);
-  y[0] = bp[0] + s * (g0 * h);
-  y[1] = bp[1] + s * (g1 * h);
-  y[2] = two ? bp[2] + s * (g2 * h) : 0.0;
-  y[3] = two ? bp[3] + s * (g3 * h) : 0.0;
+  y[0] = fma(r0, c0, bp[0]);
+  y[1] = fma(r0, s0, bp[1]);
+  y[2] = two ? fma(r1, c1, bp[2]) : 0.0;
+  y[3] = two ? fma(r1, s1, bp[3]) : 0.0;
 }
 
 // Lanes [0, nl) of the calling wave group regenerate candidate c (FP64, unit
@@ -89,7 +90,7 @@ __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, 
 // reduced with xor-shuffles inside the column's lanes.
 template <int LPC>
 __device__ void gen_candidate(const BInst& I, const double* frame, double radius, int c, int64_t t, double* out,
-                              float* lds, const double2* tab, int lane_g, int nl) {
+                              float* lds, const GaussTab& tab, int lane_g, int nl) {
   const int d = I.d;
   const int nb = (d + 1) >> 1;
   const double s = radius / sqrt((double)d);
@@ -129,7 +130,7 @@ __device__ void gen_candidate(const BInst& I, const double* frame, double radius
 }
 
 __device__ __forceinline__ void gen_dispatch(const BInst& I, const double* frame, double radius, int c, int64_t t,
-                                             double* out, float* lds, const double2* tab, int lane_g, int nl) {
+                                             double* out, float* lds, const GaussTab& tab, int lane_g, int nl) {
   // d <= 16: at most 8 blocks per column
   const int nb = (I.d + 1) >> 1;
   if (nb <= 1) gen_candidate<1>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
@@ -211,10 +212,10 @@ __device__ __forceinline__ double bits_mu(uint64_t b) {
 __global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
   __shared__ int acc_s;
   __shared__ int best_s;
-  __shared__ double2 sctab[kSinCosTab];
+  __shared__ GaussTab gtab;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  fill_sincos_tab(sctab);
+  fill_gauss_tab(&gtab);
   __syncthreads();
   for (int i = blockIdx.x; i < a.count; i += gridDim.x) {
     const BInst I = ((const BInst*)a.inst)[i];
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
       // regenerate candidate best of step t into the frame, in place (each
       // column is read and rewritten by the same lanes)
       double* frame = a.frames + I.frame_off;
-      gen_dispatch(I, frame, S0.radius, best_s, S0.step, frame, nullptr, sctab, tid, kThreads);
+      gen_dispatch(I, frame, S0.radius, best_s, S0.step, frame, nullptr, gtab, tid, kThreads);
     }
     __syncthreads();
   }
@@ -363,11 +364,11 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
   __shared__ uint32_t smax[4];
   __shared__ unsigned long long umax[4];
-  __shared__ double2 sctab[kSinCosTab];
+  __shared__ GaussTab gtab;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  fill_sincos_tab(sctab);
+  fill_gauss_tab(&gtab);
   __syncthreads();
 
   for (int u = blockIdx.x; u < a.nunits; u += gridDim.x) {
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
       umax[tid] = 0;
     }
     __syncthreads();
-    if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, sctab, wg * 64 + lane, wpi * 64);
+    if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, gtab, wg * 64 + lane, wpi * 64);
     __threadfence_block();
     __syncthreads();
 
@@ -412,9 +413,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
 // block per instance (grid-stride).
 __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count, double radius0) {
   __shared__ unsigned long long umax;
-  __shared__ double2 sctab[kSinCosTab];
+  __shared__ GaussTab gtab;
   const int tid = threadIdx.x;
-  fill_sincos_tab(sctab);
+  fill_gauss_tab(&gtab);
   __syncthreads();
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const BInst I = ((const BInst*)a.inst)[i];
@@ -428,16 +429,15 @@ __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count,
       const int col = e / nb, q = e % nb;
       const u32x4 ctr = {(uint32_t)(col * nb + q), 0u, 0u, 1u};
       const u32x4 w = philox4x32_10(ctr, I.seed, I.stream_id);
-      double g0, g1, g2, g3;
-      box_muller(w.x, w.y, sctab, g0, g1);
-      box_muller(w.z, w.w, sctab, g2, g3);
-      const double h = 0.7071067811865476;
+      double r0, c0, s0, r1, c1, s1;
+      cn_polar(w.x, w.y, gtab, r0, c0, s0);
+      cn_polar(w.z, w.w, gtab, r1, c1, s1);
       double* o = frame + 2 * ((size_t)col * d + 2 * q);
-      o[0] = g0 * h;
-      o[1] = g1 * h;
+      o[0] = r0 * c0;
+      o[1] = r0 * s0;
       if (2 * q + 1 < d) {
-        o[2] = g2 * h;
-        o[3] = g3 * h;
+        o[2] = r1 * c1;
+        o[3] = r1 * s1;
       }
     }
     __syncthreads();

@@ -88,11 +88,12 @@ __device__ __forceinline__ double div_pos(double n, double d) {
   return fma(fma(-d, q, n), r, q);
 }
 
-// ln u.  u = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) with
+// ln x for a positive normal x (used to fill the log table below).
+// x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) with
 // s = (m - 1) / (m + 1), |s| <= 0.1716, so s^2 <= 0.0295 and the odd series
 // 2 (s + s^3/3 + ... + s^19/19) leaves < 2^-57; e ln 2 uses a two-part ln 2
 // whose leading part times e is exact.
-__device__ __forceinline__ double log_unit(double u) {
+__device__ __forceinline__ double log_pos(double u) {
   double m = __builtin_amdgcn_frexp_mant(u);  // [1/2, 1)
   int e = __builtin_amdgcn_frexp_exp(u);
   if (m < 0.7071067811865476) {
@@ -161,15 +162,31 @@ __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
   cs = ((q + 1) & 2) ? -b : b;
 }
 
-// Table of (cos, sin)(2 pi i / 256), i = 0..255, filled into LDS by every
-// kernel that draws Gaussians (the same function fills it everywhere).
+// Tables of the Gaussian draws, filled into LDS by every kernel that draws
+// (the same function fills them everywhere).
+//  sc[i] = (cos, sin)(2 pi i / 256), i = 0..255.
+//  lg[i] = (r_i, ln r_i) for the mantissa bin m in [(256 + i)/512,
+//          (257 + i)/512): r_i is 1/c_i (c_i the bin centre) rounded to a
+//          multiple of 2^-12, except r_255 = 1 so that the bin just below 1
+//          reduces exactly; |m r_i - 1| <= 2^-9 + 2^-13 in every bin.
 constexpr int kSinCosTab = 256;
+constexpr int kLogTab = 256;
 
-__device__ __forceinline__ void fill_sincos_tab(double2* tab) {
+struct GaussTab {
+  double2 sc[kSinCosTab];
+  double2 lg[kLogTab];
+};
+
+__device__ __forceinline__ void fill_gauss_tab(GaussTab* tab) {
   for (int i = threadIdx.x; i < kSinCosTab; i += blockDim.x) {
     double sn, cs;
     sincos_2pi(i * (1.0 / kSinCosTab), sn, cs);
-    tab[i] = make_double2(cs, sn);
+    tab->sc[i] = make_double2(cs, sn);
+  }
+  for (int i = threadIdx.x; i < kLogTab; i += blockDim.x) {
+    double r = 1.0;
+    if (i < kLogTab - 1) r = rint(0x1p12 * 512.0 / (256.5 + i)) * 0x1p-12;
+    tab->lg[i] = make_double2(r, log_pos(r));
   }
 }
 
@@ -189,14 +206,37 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double2* tab, 
   sn = fma(t.x, sb, fma(-t.y, cm, t.y));
 }
 
-// Box-Muller (1958): (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0), in FP64.
-__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, const double2* tab, double& g0, double& g1) {
-  const double u0 = word_to_unit(w0);
-  const double r = sqrt_pos(-2.0 * log_unit(u0));
-  double s, c;
-  sincos_2pi_word(w1, tab, s, c);
-  g0 = r * c;
-  g1 = r * s;
+// -ln u for u = (w + 1/2) 2^-32 (Tang's table-driven reduction): u = m 2^e
+// with m in [1/2, 1) (so e <= 0 and ln m <= 0: no term cancels another);
+// eight mantissa bits pick the bin, t = m r_i - 1 (one rounding, exact in
+// the last bin where r = 1) and ln m = ln(1 + t) - ln r_i, with ln(1 + t)
+// through t^6 (first omitted term below 2^-56 of it for |t| <= 2^-8.9).
+__device__ __forceinline__ double neg_log_word(uint32_t w, const double2* lg) {
+  const double u = word_to_unit(w);
+  const double m = __builtin_amdgcn_frexp_mant(u);
+  const int e = __builtin_amdgcn_frexp_exp(u);
+  const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(m) >> 32);
+  const double2 T = lg[(hi >> 12) & 0xFFu];
+  const double t = fma(m, T.x, -1.0);
+  double q = fma(t, -1.0 / 6.0, 1.0 / 5.0);
+  q = fma(q, t, -0.25);
+  q = fma(q, t, 1.0 / 3.0);
+  q = fma(q, t, -0.5);
+  const double lp = fma(t * t, q, t);               // ln(1 + t)
+  const double ln2_hi = 0x1.62e42feep-1;            // ln 2 to 32 bits
+  const double ln2_lo = 0x1.a39ef35793c76p-33;      // ln 2 - ln2_hi
+  const double fe = (double)e;
+  return fma(-fe, ln2_hi, fma(-fe, ln2_lo, T.y - lp));
+}
+
+// One complex CN(0, 1) draw in polar form (Box-Muller 1958, each part of
+// variance 1/2): modulus rho = sqrt(-ln u0) = sqrt(-2 ln u0) sqrt(1/2) and
+// angle 2 pi u1; the draw is rho (cos, sin).  Callers scale rho first when
+// they add a multiple of the draw.
+__device__ __forceinline__ void cn_polar(uint32_t w0, uint32_t w1, const GaussTab& tab, double& rho, double& cs,
+                                         double& sn) {
+  rho = sqrt_pos(neg_log_word(w0, tab.lg));
+  sincos_2pi_word(w1, tab.sc, sn, cs);
 }
 
 // ---------------------------------------------------------------------------

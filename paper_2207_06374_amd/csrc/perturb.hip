@@ -77,8 +77,9 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   const bool has_base = DRAW || a.base != nullptr;
   const bool have_z = DRAW || a.have_z != 0;
   const double* const z_explicit = DRAW ? nullptr : a.z_explicit;
-  __shared__ double2 sctab[kSinCosTab];
-  fill_sincos_tab(sctab);
+  __shared__ GaussTab gtab_s;
+  GaussTab* const gtab = &gtab_s;
+  fill_gauss_tab(gtab);
   __syncthreads();
   const int slot = blockIdx.y;
   if (a.zero_max && blockIdx.x == 0 && threadIdx.x == 0) a.zero_max[slot] = 0;
@@ -109,50 +110,51 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
       if (!active || q >= nb) continue;
       const int i0 = 2 * q;
       const bool two = (i0 + 1) < d;
-      double z[4] = {0.0, 0.0, 0.0, 0.0};
-      if (have_z || !has_base) {
-        if (z_explicit) {
-          const double* zp = z_explicit + 2 * (((size_t)c * a.n + col) * d + i0);
-          z[0] = zp[0];
-          z[1] = zp[1];
-          if (two) {
-            z[2] = zp[2];
-            z[3] = zp[3];
-          }
-        } else {
-          const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, a.tag};
-          const u32x4 w = philox4x32_10_uniform_key(ctr, a.seed, a.stream_id);
-          double g0, g1, g2, g3;
-          box_muller(w.x, w.y, sctab, g0, g1);
-          box_muller(w.z, w.w, sctab, g2, g3);
-          const double h = 0.7071067811865476;  // sqrt(1/2), correctly rounded
-          z[0] = g0 * h;
-          z[1] = g1 * h;
-          z[2] = g2 * h;
-          z[3] = g3 * h;
-        }
-      }
+      double p[4] = {0.0, 0.0, 0.0, 0.0};
       if (has_base) {
         const double* bp = base + 2 * ((size_t)col * d + i0);
         const double2 p0 = *(const double2*)bp;
-        double2 p1 = make_double2(0.0, 0.0);
-        if (two) p1 = *(const double2*)(bp + 2);
-        if (have_z) {
-          y[qi][0] = p0.x + s * z[0];
-          y[qi][1] = p0.y + s * z[1];
-          y[qi][2] = p1.x + s * z[2];
-          y[qi][3] = p1.y + s * z[3];
-        } else {
-          y[qi][0] = p0.x;
-          y[qi][1] = p0.y;
-          y[qi][2] = p1.x;
-          y[qi][3] = p1.y;
+        p[0] = p0.x;
+        p[1] = p0.y;
+        if (two) {
+          const double2 p1 = *(const double2*)(bp + 2);
+          p[2] = p1.x;
+          p[3] = p1.y;
         }
+      }
+      if (has_base && !have_z) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[qi][e] = p[e];
+      } else if (z_explicit) {
+        const double* zp = z_explicit + 2 * (((size_t)c * a.n + col) * d + i0);
+        double z[4] = {zp[0], zp[1], 0.0, 0.0};
+        if (two) {
+          z[2] = zp[2];
+          z[3] = zp[3];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[qi][e] = has_base ? p[e] + s * z[e] : z[e];
       } else {
-        y[qi][0] = z[0];
-        y[qi][1] = z[1];
-        y[qi][2] = z[2];
-        y[qi][3] = z[3];
+        // two complex draws; y = Phi + s z with the step scale folded into
+        // the modulus of each draw
+        const u32x4 ctr = {(uint32_t)(col * nb + q), (uint32_t)c, (uint32_t)t, a.tag};
+        const u32x4 w = philox4x32_10_uniform_key(ctr, a.seed, a.stream_id);
+        double r0, c0, s0, r1, c1, s1;
+        cn_polar(w.x, w.y, *gtab, r0, c0, s0);
+        cn_polar(w.z, w.w, *gtab, r1, c1, s1);
+        if (has_base) {
+          r0 *= s;
+          r1 *= s;
+          y[qi][0] = fma(r0, c0, p[0]);
+          y[qi][1] = fma(r0, s0, p[1]);
+          y[qi][2] = fma(r1, c1, p[2]);
+          y[qi][3] = fma(r1, s1, p[3]);
+        } else {
+          y[qi][0] = r0 * c0;
+          y[qi][1] = r0 * s0;
+          y[qi][2] = r1 * c1;
+          y[qi][3] = r1 * s1;
+        }
       }
       if (!two) {
         y[qi][2] = 0.0;
