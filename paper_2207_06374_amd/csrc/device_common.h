@@ -129,6 +129,43 @@ __device__ __forceinline__ double sqrt_pos(double a) {
   return fma(fma(-g, g, a), h, g);
 }
 
+// 1/sqrt(x) for a positive normal x: hardware estimate, one coupled Newton
+// (Goldschmidt) step on g ~ sqrt(x) and h ~ 1/(2 sqrt(x)), then one more on
+// h.  Zero, infinite and NaN x give NaN (0 inf or inf 0 in g).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  h = fma(h, r, h);
+  return h + h;
+}
+
+// One FP64 value from the lane selected by a DPP row permute (dpp_ctrl).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sum over each aligned group of G consecutive lanes (G a power of two <= 64),
+// left in every lane of the group with the same bits: quad swaps, half-row
+// and row mirrors inside a 16-lane row, then xor-shuffles across rows.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+  if constexpr (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // (sin 2 pi u, cos 2 pi u).  j = rint(4u) quarter turns and t = u - j/4 in
 // [-1/8, 1/8] are exact; x = 2 pi t, |x| <= pi/4, sin x through x^17 and
 // cos x through x^16; the quarter turns rotate the pair.
@@ -197,8 +234,7 @@ __device__ __forceinline__ void fill_gauss_tab(GaussTab* tab) {
 // angle-sum rotation.
 __device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double2* tab, double& sn, double& cs) {
   const double2 t = tab[w >> 24];
-  const double rho = ((double)(w & 0xFFFFFFu) + 0.5) * 0x1p-32;
-  const double b = rho * 6.283185307179586;
+  const double b = ((double)(w & 0xFFFFFFu) + 0.5) * (6.283185307179586 * 0x1p-32);  // exact power-of-two scaling
   const double z = b * b;
   const double sb = fma(b * z, fma(z, fma(z, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), b);
   const double cm = z * fma(z, fma(z, fma(z, -1.0 / 40320.0, 1.0 / 720.0), -1.0 / 24.0), 0.5);
@@ -212,9 +248,9 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double2* tab, 
 // the last bin where r = 1) and ln m = ln(1 + t) - ln r_i, with ln(1 + t)
 // through t^6 (first omitted term below 2^-56 of it for |t| <= 2^-8.9).
 __device__ __forceinline__ double neg_log_word(uint32_t w, const double2* lg) {
-  const double u = word_to_unit(w);
-  const double m = __builtin_amdgcn_frexp_mant(u);
-  const int e = __builtin_amdgcn_frexp_exp(u);
+  const double v = (double)w + 0.5;  // u 2^32: same mantissa as u, exponent larger by 32
+  const double m = __builtin_amdgcn_frexp_mant(v);
+  const int e = __builtin_amdgcn_frexp_exp(v) - 32;
   const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(m) >> 32);
   const double2 T = lg[(hi >> 12) & 0xFFu];
   const double t = fma(m, T.x, -1.0);
@@ -265,13 +301,16 @@ __device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ bool bf16_via_f32_unsafe(uint32_t b) {
-  return (b & 0xFFFFu) == 0x8000u || ((b & 0x7F800000u) == 0 && (b & 0x007FFFFFu) != 0);
+// A float f is unsafe for the second rounding when it is a bfloat16 midpoint
+// (low 16 bits exactly 0x8000) or an FP32 subnormal (class mask 0x90: the
+// negative and positive subnormal classes of v_cmp_class_f32).
+__device__ __forceinline__ bool bf16_via_f32_unsafe(float f) {
+  return ((__float_as_uint(f) & 0xFFFFu) == 0x8000u) | __builtin_amdgcn_classf(f, 0x90);
 }
 
 __device__ __forceinline__ uint32_t bf16x2_rne(double x0, double x1) {
   const f32x2 f = {(float)x0, (float)x1};
-  const bool slow = bf16_via_f32_unsafe(__float_as_uint(f[0])) || bf16_via_f32_unsafe(__float_as_uint(f[1]));
+  const bool slow = bf16_via_f32_unsafe(f[0]) | bf16_via_f32_unsafe(f[1]);
   if (__ballot(slow) && slow)
     return (uint32_t)f64_to_bf16_rne(x0) | ((uint32_t)f64_to_bf16_rne(x1) << 16);
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));

@@ -10,8 +10,8 @@
 // Work split: a column of d complex entries is ceil(d/2) Philox blocks (one
 // block = 4 words = 2 complex entries).  LPC lanes (a power of two <= 64)
 // share a column, each holding up to kMaxQ blocks in registers; the norm is
-// reduced across the LPC lanes with xor-shuffles, so a column never leaves
-// the wavefront.  BF16/FP32 screen copies put 4 blocks on a lane; FP64
+// reduced across the LPC lanes with DPP row permutes (xor-shuffles across
+// rows), so a column never leaves the wavefront.  BF16/FP32 screen copies put 4 blocks on a lane; FP64
 // outputs use one split per d, so a candidate's FP64 bits are the same in
 // every launch that writes it.  Loads and stores are 16-byte and consecutive
 // lanes touch consecutive entries of a column.
@@ -70,8 +70,12 @@ __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot
 
 // DRAW: compiled for the candidate form only (base frame present, Philox
 // draws, no explicit perturbation); otherwise the three fields decide.
-template <int LPC, int Q, int OUT, bool DRAW>
+// FULL (with DRAW): d is even and the LPC lanes of a column hold exactly its
+// ceil(d/2) blocks (LPC * Q == d / 2), so no block is partial or missing;
+// lanes of columns past n compute on the last column and store nothing.
+template <int LPC, int Q, int OUT, bool DRAW, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
+  static_assert(DRAW || !FULL, "the full split is compiled for the candidate form only");
   if (a.gate && ((*a.gate & a.gate_mask) != a.gate_want)) return;
   const double* const base = a.base;
   const bool has_base = DRAW || a.base != nullptr;
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   const int c = a.cand_idx ? a.cand_idx[slot] : a.c0 + slot;
   const int64_t t = a.tstep ? *a.tstep : a.t_const;
   const int d = a.d;
-  const int nb = (d + 1) >> 1;
+  const int nb = FULL ? LPC * Q : (d + 1) >> 1;
   double s = 0.0;
   if (has_base && have_z) s = *a.radius / sqrt((double)d);
 
@@ -101,18 +105,21 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
        col0 += (int64_t)gridDim.x * kColsPerIter) {
     const int64_t col = col0 + wave * kColsPerWave + lane / LPC;
     const bool active = col < a.n;  // whole LPC groups share `active`
+    const int64_t colr = FULL ? (active ? col : a.n - 1) : col;  // column read
     double y[Q][4];
     double nrm2 = 0.0;
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
       const int q = lq + qi * LPC;
-      y[qi][0] = y[qi][1] = y[qi][2] = y[qi][3] = 0.0;
-      if (!active || q >= nb) continue;
+      if constexpr (!FULL) {
+        y[qi][0] = y[qi][1] = y[qi][2] = y[qi][3] = 0.0;
+        if (!active || q >= nb) continue;
+      }
       const int i0 = 2 * q;
-      const bool two = (i0 + 1) < d;
+      const bool two = FULL || (i0 + 1) < d;
       double p[4] = {0.0, 0.0, 0.0, 0.0};
       if (has_base) {
-        const double* bp = base + 2 * ((size_t)col * d + i0);
+        const double* bp = base + 2 * ((size_t)colr * d + i0);
         const double2 p0 = *(const double2*)bp;
         p[0] = p0.x;
         p[1] = p0.y;
@@ -160,20 +167,19 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
         y[qi][2] = 0.0;
         y[qi][3] = 0.0;
       }
-      nrm2 += (y[qi][0] * y[qi][0] + y[qi][1] * y[qi][1]) + (y[qi][2] * y[qi][2] + y[qi][3] * y[qi][3]);
+      nrm2 = fma(y[qi][3], y[qi][3], fma(y[qi][2], y[qi][2], fma(y[qi][1], y[qi][1], fma(y[qi][0], y[qi][0], nrm2))));
     }
-#pragma unroll
-    for (int off = LPC / 2; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
+    nrm2 = group_sum<LPC>(nrm2);
     if (!active) continue;
-    const double nrm = sqrt(nrm2);
-    const bool bad = !(nrm > 0.0 && nrm < __builtin_inf());
-    const double inv = bad ? __builtin_nan("") : 1.0 / nrm;  // one IEEE division per column and lane
+    // 1 / ||y||; NaN for a zero or non-finite norm, which makes the column
+    // (and so the candidate) invalid
+    const double inv = rsqrt_pos(nrm2);
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
       const int q = lq + qi * LPC;
-      if (q >= nb) continue;
+      if (!FULL && q >= nb) continue;
       const int i0 = 2 * q;
-      const bool two = (i0 + 1) < d;
+      const bool two = FULL || (i0 + 1) < d;
       double o[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) o[e] = y[qi][e] * inv;
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_round_bf16(const double* x, int64_
   }
 }
 
-template <int LPC, int Q, int OUT, bool DRAW = false>
+template <int LPC, int Q, int OUT, bool DRAW = false, bool FULL = false>
 hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
   int64_t groups = (a.n + kColsPerIter - 1) / kColsPerIter;
@@ -215,14 +221,27 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   int64_t want = (8192 + slots - 1) / slots;
   if (want < 1) want = 1;
   const int gx = (int)(groups < want ? groups : want);
-  hipLaunchKernelGGL((k_perturb<LPC, Q, OUT, DRAW>), dim3(gx, slots), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_perturb<LPC, Q, OUT, DRAW, FULL>), dim3(gx, slots), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-// Screen copies (FP32 or BF16): 4 blocks per lane, so the column norm's
-// square root and division are shared by more entries.
+// Screen copies (FP32 or BF16): 4 blocks per lane, so the column's inverse
+// norm is shared by more entries.
 template <int OUT, bool DRAW>
 hipError_t launch_screen_copies(const PerturbArgs& a, int nb, int slots, hipStream_t s) {
+  if (DRAW && a.d % 2 == 0) {
+    // full splits: d = 8, 16, 32, 64, 128, 256, 512
+    switch (nb) {
+      case 4: return launch_lpc<1, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 8: return launch_lpc<2, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 16: return launch_lpc<4, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 32: return launch_lpc<8, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 64: return launch_lpc<16, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 128: return launch_lpc<32, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 256: return launch_lpc<64, 4, OUT, DRAW, DRAW>(a, slots, s);
+      default: break;
+    }
+  }
   if (nb <= 4) return launch_lpc<1, 4, OUT, DRAW>(a, slots, s);
   if (nb <= 8) return launch_lpc<2, 4, OUT, DRAW>(a, slots, s);
   if (nb <= 16) return launch_lpc<4, 4, OUT, DRAW>(a, slots, s);
