@@ -217,8 +217,10 @@ template <int LPC, int Q, int OUT, bool DRAW = false, bool FULL = false>
 hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
   int64_t groups = (a.n + kColsPerIter - 1) / kColsPerIter;
-  // enough blocks to fill the chip across all slots, each looping over column groups
-  int64_t want = (8192 + slots - 1) / slots;
+  // about 2048 blocks across all slots (8 per CU, two resident rounds at 4
+  // waves per SIMD), each looping over column groups, so that the per-block
+  // table fill is spread over more entries
+  int64_t want = (2048 + slots - 1) / slots;
   if (want < 1) want = 1;
   const int gx = (int)(groups < want ? groups : want);
   hipLaunchKernelGGL((k_perturb<LPC, Q, OUT, DRAW, FULL>), dim3(gx, slots), dim3(kThreads), 0, s, a);
