@@ -178,18 +178,21 @@ def _argmin_lowest(values, allowed=None):
 def screen_error_bound(d):
     """Largest possible |screened - exact| coherence for unit columns in C^d.
 
-    Entries rounded to bfloat16 carry relative error at most u = 2^-8, so each
-    real dot product of two unit 2d-vectors moves by at most 2u + u^2; summing
-    2d exact bf16 products in binary32 adds at most gamma_{2d} (1 + u)^2 with
-    gamma_n = n v / (1 - n v), v = 2^-24; Re and Im together give the factor
-    sqrt(2).  A few binary32 roundings in |G|^2 and the square root, and the
-    FP64 value's own rounding, are covered by the last two terms.
+    Rounding the real and imaginary parts of an entry to bfloat16 (relative
+    error at most u = 2^-8 each) moves the complex entry by at most u times
+    its modulus, so by the triangle and Cauchy-Schwarz inequalities the
+    complex inner product of two unit columns moves by at most 2u + u^2.
+    Summing 2d exact bf16 products in binary32 moves each of Re and Im by at
+    most gamma_{2d} (1 + u)^2 with gamma_n = n v / (1 - n v), v = 2^-24; the
+    two together give the factor sqrt(2).  A few binary32 roundings in |G|^2
+    and the square root, and the FP64 value's own rounding, are covered by
+    the last two terms.
     """
     u = 2.0 ** -8
     v = 2.0 ** -24
     n = 2 * d
     gamma = n * v / (1.0 - n * v)
-    return math.sqrt(2.0) * (2 * u + u * u + gamma * (1 + u) ** 2) + 8 * v + 1e-12
+    return (2 * u + u * u) + math.sqrt(2.0) * gamma * (1 + u) ** 2 + 8 * v + 1e-12
 
 
 def _is_done(p, mu, t):

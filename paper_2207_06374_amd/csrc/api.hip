@@ -248,15 +248,18 @@ double tau_of(const trstmi_params* p) {
 }
 
 // Certified bound on |screened - exact| coherence for unit columns in C^d:
-// bfloat16 inputs move each real dot product of two unit 2d-vectors by at
-// most 2u + u^2 (u = 2^-8); FP32 accumulation of 2d exact products adds
-// gamma_{2d} (1 + u)^2 (gamma_n = n v / (1 - n v), v = 2^-24); Re and Im give
-// sqrt(2); the last terms cover the FP32 epilogue and FP64 rounding.
+// rounding the real and imaginary parts of an entry to bfloat16 (relative
+// error <= u = 2^-8 each) moves the complex entry by at most u times its
+// modulus, so the complex inner product of two unit columns moves by at most
+// 2u + u^2 (triangle and Cauchy-Schwarz inequalities); FP32 accumulation of
+// 2d exact products moves Re and Im each by at most gamma_{2d} (1 + u)^2
+// (gamma_n = n v / (1 - n v), v = 2^-24), sqrt(2) for the two together; the
+// last terms cover the FP32 epilogue and FP64 rounding.
 double screen_eps(int64_t d) {
   const double u = std::ldexp(1.0, -8), v = std::ldexp(1.0, -24);
   const double nv = 2.0 * d * v;
   const double gamma = nv / (1.0 - nv);
-  return std::sqrt(2.0) * (2 * u + u * u + gamma * (1 + u) * (1 + u)) + 8 * v + 1e-12;
+  return (2 * u + u * u) + std::sqrt(2.0) * gamma * (1 + u) * (1 + u) + 8 * v + 1e-12;
 }
 
 PerturbArgs perturb_base(const trstmi_params* p) {

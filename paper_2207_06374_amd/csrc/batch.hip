@@ -54,13 +54,15 @@ struct alignas(16) BState {
 };
 
 __device__ __forceinline__ double eps32(int d) {
-  // |screened - exact| for unit columns: FP32 inputs (relative 2^-24) move each
-  // real dot product by at most 2u + u^2; FP32 accumulation of 2d products
-  // adds gamma_{2d}; Re and Im give sqrt 2; the tail covers the epilogue.
+  // |screened - exact| for unit columns: FP32 inputs (relative 2^-24 in each
+  // real part, so at most u times each complex entry's modulus) move the
+  // complex inner product by at most 2u + u^2; FP32 accumulation of 2d
+  // products moves Re and Im each by gamma_{2d} (1 + u)^2, sqrt 2 for the
+  // two; the tail covers the epilogue.
   const double u = 0x1p-24;
   const double nu = 2.0 * d * u;
   const double g = nu / (1.0 - nu);
-  return 1.4142135623730951 * (2 * u + u * u + g * (1 + u) * (1 + u)) + 16 * u + 1e-12;
+  return (2 * u + u * u) + 1.4142135623730951 * g * (1 + u) * (1 + u) + 16 * u + 1e-12;
 }
 
 // Candidate c of instance I at step t, column col, Philox block q (entries 2q, 2q+1).

@@ -539,38 +539,31 @@ int k_segments(int nt) {
   return total;
 }
 
-// Exact FP64 |<phi_j, phi_k>|^2 from the FP64 candidate (column stride ld).
-__device__ __forceinline__ uint64_t pair_f64(const double* c64, int ld, int d, int j, int k) {
+// Exact FP64 <phi_j, phi_k> partial sums for 16 lanes per pair: lane sub of
+// the group takes entries sub, sub + 16, ... (loads of a 64-entry chunk
+// issued together); the caller combines the sixteen with group_sum<16>
+// (commutative steps, so every lane of the group ends with the same bits,
+// whichever pair or item it is).
+__device__ __forceinline__ void pair_f64_part(const double* c64, int ld, int d, int j, int k, int sub, double& re,
+                                              double& im) {
   const double2* x = (const double2*)(c64 + (size_t)j * ld);
   const double2* y = (const double2*)(c64 + (size_t)k * ld);
-  double re = 0.0, im = 0.0;
-  for (int i = 0; i < d; ++i) {
-    const double2 p = x[i], q = y[i];
-    re += p.x * q.x + p.y * q.y;
-    im += p.x * q.y - p.y * q.x;
-  }
-  return (uint64_t)__double_as_longlong(re * re + im * im);
-}
-
-// The same value with the whole wave on one pair: lane i takes entries
-// i, i + 64, ... and a butterfly sum (commutative, so every lane ends with the
-// same bits) combines them.
-__device__ __forceinline__ uint64_t pair_f64_wave(const double* c64, int ld, int d, int j, int k) {
-  const int lane = threadIdx.x & 63;
-  const double2* x = (const double2*)(c64 + (size_t)j * ld);
-  const double2* y = (const double2*)(c64 + (size_t)k * ld);
-  double re = 0.0, im = 0.0;
-  for (int i = lane; i < d; i += 64) {
-    const double2 p = x[i], q = y[i];
-    re += p.x * q.x + p.y * q.y;
-    im += p.x * q.y - p.y * q.x;
-  }
+  re = 0.0;
+  im = 0.0;
+  for (int i0 = 0; i0 < d; i0 += 64) {
+    double2 p[4], q[4];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    re += __shfl_xor(re, off, 64);
-    im += __shfl_xor(im, off, 64);
+    for (int t = 0; t < 4; ++t) {
+      const int i = i0 + sub + 16 * t;
+      p[t] = i < d ? x[i] : make_double2(0.0, 0.0);
+      q[t] = i < d ? y[i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      re += p[t].x * q[t].x + p[t].y * q[t].y;
+      im += p[t].x * q[t].y - p[t].y * q[t].x;
+    }
   }
-  return (uint64_t)__double_as_longlong(re * re + im * im);
 }
 
 // Pair-level FP64 recheck.  For a rechecked candidate with screened maximum s
@@ -597,7 +590,8 @@ __global__ __launch_bounds__(64) void k_recheck_pairs(RecheckArgs a) {
     int bi, bj;
     tile_decode(item.y, a.nt, bi, bj);
     if (bi == bj && rq > cq) continue;  // wholly below the diagonal (uniform: no barrier skipped unevenly)
-    const int slot = item.x;
+    if (!((item.x >> (8 + rq)) & 1)) continue;  // row quarter below the threshold (uniform as well)
+    const int slot = item.x & 0xFF;
     const double thr = a.thr[slot];
     const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
     const uint16_t* base = a.screen + (size_t)a.rechecked[slot] * a.screen_stride;
@@ -650,17 +644,19 @@ __global__ __launch_bounds__(64) void k_recheck_pairs(RecheckArgs a) {
     __syncthreads();
     const int nh = nhits;
     uint64_t best = 0;
-    if (nh <= 16) {
-      // the usual case: a few pairs, each by the whole wave
-      for (int e = 0; e < nh; ++e) {
+    // 4 pairs at a time, 16 lanes per pair, so the loads of all of them are
+    // in flight together
+    for (int e0 = 0; e0 < nh; e0 += 4) {
+      const int e = e0 + (lane >> 4);
+      double re = 0.0, im = 0.0;
+      if (e < nh) {
         const int2 h = hits[e];
-        const uint64_t mb = pair_f64_wave(c64, a.ld64, a.d, h.x, h.y);
-        best = mb > best ? mb : best;
+        pair_f64_part(c64, a.ld64, a.d, h.x, h.y, lane & 15, re, im);
       }
-    } else {
-      for (int e = lane; e < nh; e += 64) {
-        const int2 h = hits[e];
-        const uint64_t mb = pair_f64(c64, a.ld64, a.d, h.x, h.y);
+      re = group_sum<16>(re);
+      im = group_sum<16>(im);
+      if (e < nh) {
+        const uint64_t mb = (uint64_t)__double_as_longlong(re * re + im * im);
         best = mb > best ? mb : best;
       }
     }

@@ -95,7 +95,7 @@ struct TopkArgs {
   // screen tiles that may hold a rechecked candidate's exact maximum out
   const uint32_t* tile_max;  // [C][screen tiles][4] float bits of max |G|^2 (per wave)
   int32_t screen_nt;         // screen tiles per side
-  int2* list;                // out: (slot, screen tile) items
+  int2* list;                // out: (slot | row-quarter mask << 8, screen tile) items
   int32_t* list_count;       // out
   int32_t list_cap;
 };
@@ -109,7 +109,7 @@ struct RecheckArgs {
   int64_t stride64;          // doubles per slot
   int32_t ld64;              // FP64 column stride (doubles)
   int32_t n, d, nt, k;       // nt: screen tiles per side; k: rechecked slots
-  const int2* list;          // (slot, screen tile)
+  const int2* list;          // (slot | row-quarter mask << 8, screen tile)
   const int32_t* count;
   int32_t list_cap;
   const int32_t* rechecked;  // slot -> candidate

@@ -9,12 +9,13 @@
 //
 // Work split: a column of d complex entries is ceil(d/2) Philox blocks (one
 // block = 4 words = 2 complex entries).  LPC lanes (a power of two <= 64)
-// share a column, each holding up to kMaxQ blocks in registers; the norm is
+// share a column, each holding kMaxQ = 4 blocks in registers; the norm is
 // reduced across the LPC lanes with DPP row permutes (xor-shuffles across
-// rows), so a column never leaves the wavefront.  BF16/FP32 screen copies put 4 blocks on a lane; FP64
-// outputs use one split per d, so a candidate's FP64 bits are the same in
-// every launch that writes it.  Loads and stores are 16-byte and consecutive
-// lanes touch consecutive entries of a column.
+// rows), so a column never leaves the wavefront.  Every output kind uses the
+// same split for a given d, so a candidate's FP64 bits are the same in every
+// launch that writes it and its screen copies are their roundings.  Loads
+// and stores are 16-byte and consecutive lanes touch consecutive entries of
+// a column.
 
 #include "device_common.h"
 #include "launch.h"
@@ -227,10 +228,12 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Screen copies (FP32 or BF16): 4 blocks per lane, so the column's inverse
-// norm is shared by more entries.
+// 4 blocks per lane, so the column's inverse norm is shared by more entries.
+// Every output kind of a candidate uses this same split, so a candidate's
+// FP64 bits are the same in every launch that writes it and its BF16 / FP32
+// screen copies are the roundings of those FP64 values.
 template <int OUT, bool DRAW>
-hipError_t launch_screen_copies(const PerturbArgs& a, int nb, int slots, hipStream_t s) {
+hipError_t launch_q4(const PerturbArgs& a, int nb, int slots, hipStream_t s) {
   if (DRAW && a.d % 2 == 0) {
     // full splits: d = 8, 16, 32, 64, 128, 256, 512
     switch (nb) {
@@ -258,26 +261,14 @@ hipError_t launch_screen_copies(const PerturbArgs& a, int nb, int slots, hipStre
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
   const int nb = (a.d + 1) / 2;
   const bool draw = a.base && a.have_z && !a.z_explicit;
-  if (a.out_kind == kOutF32) {
-    return draw ? launch_screen_copies<kOutF32, true>(a, nb, slots, s)
-                : launch_screen_copies<kOutF32, false>(a, nb, slots, s);
+  switch (a.out_kind) {
+    case kOutF64:
+      return draw ? launch_q4<kOutF64, true>(a, nb, slots, s) : launch_q4<kOutF64, false>(a, nb, slots, s);
+    case kOutF32:
+      return draw ? launch_q4<kOutF32, true>(a, nb, slots, s) : launch_q4<kOutF32, false>(a, nb, slots, s);
+    default:
+      return draw ? launch_q4<kOutBF16, true>(a, nb, slots, s) : launch_q4<kOutBF16, false>(a, nb, slots, s);
   }
-  if (a.out_kind == kOutBF16) {
-    return draw ? launch_screen_copies<kOutBF16, true>(a, nb, slots, s)
-                : launch_screen_copies<kOutBF16, false>(a, nb, slots, s);
-  }
-  // FP64 frames and candidates (every launch that writes one candidate in
-  // FP64 uses this same split, so its bits do not depend on the launch)
-  constexpr int F = kOutF64;
-  if (nb <= 1) return launch_lpc<1, 1, F>(a, slots, s);
-  if (nb <= 2) return launch_lpc<2, 1, F>(a, slots, s);
-  if (nb <= 4) return launch_lpc<4, 1, F>(a, slots, s);
-  if (nb <= 8) return launch_lpc<8, 1, F>(a, slots, s);
-  if (nb <= 16) return launch_lpc<16, 1, F>(a, slots, s);
-  if (nb <= 32) return launch_lpc<32, 1, F>(a, slots, s);
-  if (nb <= 64) return launch_lpc<64, 1, F>(a, slots, s);
-  if (nb <= 128) return launch_lpc<64, 2, F>(a, slots, s);
-  return launch_lpc<64, kMaxQ, F>(a, slots, s);
 }
 
 hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,

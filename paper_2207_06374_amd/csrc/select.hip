@@ -229,16 +229,24 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(TopkArgs a) {
     for (int u = 0; u < kU; ++u) {
       const int e = e0 + u * kTopkThreads + tid;
       bool keep = false;
-      int slot = 0, st = 0;
+      int slot = 0, st = 0, qmask = 0;
       if (e < a.k * sn) {
         slot = e / sn;
         st = e - slot * sn;
         if (sel_thr[slot] > -__builtin_inf()) {
-          uint32_t mb = tm[u].x > tm[u].y ? tm[u].x : tm[u].y;
-          mb = tm[u].z > mb ? tm[u].z : mb;
-          mb = tm[u].w > mb ? tm[u].w : mb;
-          const double m = sqrt((double)__uint_as_float(mb));
-          keep = !(m < sel_thr[slot]);
+          // entry q bounds the screened values of the tile's rows 32 q ..
+          // 32 q + 31 (the Gram kernels write one entry per 32-row quarter,
+          // or per 64-row half into both of its quarters, or one value into
+          // all four); bit q of the mask marks a quarter that can qualify
+          // (squares compared against thr^2 lowered by 1e-12 relative: at
+          // worst a quarter on the boundary is kept; a NaN entry is kept)
+          const double t = sel_thr[slot];
+          const double t2 = t > 0.0 ? t * t * (1.0 - 1e-12) : -__builtin_inf();
+          const uint32_t e4[4] = {tm[u].x, tm[u].y, tm[u].z, tm[u].w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (!((double)__uint_as_float(e4[q]) < t2)) qmask |= 1 << q;
+          keep = qmask != 0;
         }
       }
       const uint64_t ballot = __ballot(keep);
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(TopkArgs a) {
       base = __shfl(base, 0, 64);
       if (keep) {
         const int pos = base + __popcll(ballot & ((1ull << lane) - 1));
-        if (pos < a.list_cap) a.list[pos] = make_int2(slot, st);
+        if (pos < a.list_cap) a.list[pos] = make_int2(slot | (qmask << 8), st);
       }
     }
   }
