@@ -457,8 +457,11 @@ __device__ __forceinline__ uint32_t tile_max_k(const QRows<KS>& A, const uint16_
 }
 
 // Row segments of 256-row blocks: row block r (tile rows 2r, 2r + 1) against
-// runs of at most kSegK column tiles bj >= 2r.
-constexpr int kSegK = 4;
+// runs of column tiles bj >= 2r; the nt - 2r tiles of row block r are split
+// into ceil((nt - 2r) / kSegK) runs of equal length (within one tile), so
+// every block does about the same work and the A rows are loaded once per
+// run of up to kSegK tiles.
+constexpr int kSegK = 6;
 __device__ __forceinline__ void seg_decode_k(int s, int nt, int& r, int& bj0, int& bj1) {
   r = 0;
   int rem = s;
@@ -468,8 +471,10 @@ __device__ __forceinline__ void seg_decode_k(int s, int nt, int& r, int& bj0, in
     rem -= ns;
     ++r;
   }
-  bj0 = 2 * r + rem * kSegK;
-  bj1 = bj0 + kSegK < nt ? bj0 + kSegK : nt;
+  const int L = nt - 2 * r;
+  const int ns = (L + kSegK - 1) / kSegK;
+  bj0 = 2 * r + (rem * L) / ns;
+  bj1 = 2 * r + ((rem + 1) * L) / ns;
 }
 
 template <int KS>
