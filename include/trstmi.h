@@ -159,6 +159,26 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
                                double* mu_out, void* workspace, size_t workspace_bytes,
                                hipStream_t stream);
 
+/* Bytes of workspace trstmi_lse needs for an n x d frame. */
+size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d);
+
+/*
+ * Smooth maximum of section IV (the shifted log-sum-exp the paper's
+ * optimiser minimises; its Proposition bounds it by s <= F <= s + delta log n):
+ * the columns of `frame` (device, layout above, any nonzero scale) are
+ * normalised in FP64, x runs over the n = N(N-1)/2 values |G_jk|^2
+ * (squared = 1) or |G_jk| (squared = 0), j < k, s = max x, and
+ *   out[0] = s,  out[1] = F = s + delta log sum exp((x - s) / delta)
+ * (out: device, 2 doubles), all in FP64.  The sum is added in a fixed order,
+ * so repeated calls give the same bits.  A column whose norm is zero or not
+ * finite gives out = (+inf, +inf).  delta must be finite and > 0.
+ * Requires n >= 2, 1 <= d <= TRSTMI_MAX_D; workspace of
+ * trstmi_lse_workspace_bytes(n, d) bytes, else TRSTMI_E_WORKSPACE.
+ * Stream-ordered.
+ */
+trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta, int32_t squared,
+                         double* out, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /*
  * Random start (Alg. 2 step 1): state->frame <- N normalised CN(0, I_d)
  * columns drawn with tag 1 (candidate 0, step 0); *mu <- its coherence

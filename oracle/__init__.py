@@ -22,6 +22,8 @@ tuning for matrix incoherence", arXiv:2207.06374):
   perturbations.
 * ``rounding``   -- round-to-nearest-even to bfloat16 / float32, used to
   emulate the reduced-precision screening forms.
+* ``smoothmax``  -- the shifted log-sum-exp smooth maximum of §IV over the
+  upper-triangle Gram moduli (the objective the paper's optimiser uses).
 * ``trstmi``     -- Haar start, candidate generation, evaluation,
   select/accept and radius update, step and solve.
 
@@ -50,6 +52,12 @@ from .rng import (  # noqa: F401
     complex_gaussian_frame,
 )
 from .rounding import round_to_bf16, round_to_fp32  # noqa: F401
+from .smoothmax import (  # noqa: F401
+    upper_values,
+    smooth_max_of_values,
+    smooth_max,
+    smooth_max_bruteforce,
+)
 from .trstmi import (  # noqa: F401
     Params,
     State,

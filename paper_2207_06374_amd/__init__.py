@@ -106,6 +106,25 @@ def coherence(frame, n, d, mode=MODE_FP64, mu_out=None, workspace=None, stream=N
     return mu_out
 
 
+def lse_workspace_bytes(n, d):
+    return _abi.lib().trstmi_lse_workspace_bytes(int(n), int(d))
+
+
+def lse(frame, n, d, delta, squared=True, out=None, workspace=None, stream=None):
+    """Smooth maximum of a device frame: (s, F) with x = |G_jk|^2 (or |G_jk|),
+    j < k, s = max x and F = s + delta log sum exp((x - s) / delta), FP64.
+    Returns the device tensor (shape (2,), float64)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=frame.device)
+    need = lse_workspace_bytes(n, d)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=frame.device)
+    _abi.check(_abi.lib().trstmi_lse(int(n), int(d), _ptr(frame), float(delta), 1 if squared else 0, _ptr(out),
+                                     _ptr(workspace), workspace.numel(), _stream(stream)), "trstmi_lse")
+    return out
+
+
 def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, stream=None):
     """The normalised FP64 candidates c0..c0+count-1 of step t (flat tensor,
     candidate i at offset i*2*d*n)."""

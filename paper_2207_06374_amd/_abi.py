@@ -109,6 +109,8 @@ SIGNATURES = {
     "trstmi_workspace_bytes": (_sz, [_P(Params)]),
     "trstmi_coherence_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "trstmi_coherence": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "trstmi_lse_workspace_bytes": (_sz, [_i64, _i64]),
+    "trstmi_lse": (_i32, [_i64, _i64, _vp, ctypes.c_double, _i32, _vp, _vp, _sz, _vp]),
     "trstmi_init_haar": (_i32, [_P(Params), _P(State), _vp, _sz, _vp]),
     "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),

@@ -624,6 +624,47 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
   return TRSTMI_OK;
 }
 
+size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d) {
+  if (check_size(n, d)) return 0;
+  const int64_t nt = (n + kTileF64 - 1) / kTileF64;
+  return align256((size_t)n * ld_mode(d, TRSTMI_MODE_FP64) * 8) + 256 + align256((size_t)(nt * (nt + 1) / 2) * 8);
+}
+
+trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta, int32_t squared, double* out,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TRSTMI_E_INVALID_ARG, "delta must be finite and > 0");
+  if (squared != 0 && squared != 1) return fail(TRSTMI_E_INVALID_ARG, "squared must be 0 or 1");
+  if (!frame || !out) return fail(TRSTMI_E_INVALID_ARG, "frame and out must be device pointers");
+  if (((uintptr_t)frame & 15) || ((uintptr_t)out & 7)) return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_lse_workspace_bytes(n, d);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  char* ws = (char*)workspace;
+  const int32_t ld = ld_mode(d, TRSTMI_MODE_FP64);
+  const size_t frame_bytes = align256((size_t)n * ld * 8);
+  uint64_t* mx = (uint64_t*)(ws + frame_bytes);
+  double* partial = (double*)(ws + frame_bytes + 256);
+  const int64_t nt = (n + kTileF64 - 1) / kTileF64;
+
+  PerturbArgs pa{};
+  pa.base = frame;
+  pa.have_z = 0;
+  pa.n = n;
+  pa.d = (int32_t)d;
+  pa.out = ws;
+  pa.out_kind = kOutF64;
+  pa.out_ld = ld;
+  pa.out_slot_stride = n * ld;
+  pa.zero_max = mx;
+  TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
+  GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
+  TRY_HIP(TIMED("lse_max", stream, launch_gram_f64(g, 1, stream)), "gram_f64");
+  TRY_HIP(TIMED("lse_sumexp", stream, launch_lse_sumexp(g, mx, delta, squared, partial, stream)), "lse_sumexp");
+  TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, squared, out, stream), "lse_finish");
+  return TRSTMI_OK;
+}
+
 trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state, void* workspace,
                                size_t workspace_bytes, hipStream_t stream) {
   trstmi_status st = check_params(p);
@@ -940,6 +981,6 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
-int32_t trstmi_abi_version(void) { return 3; }
+int32_t trstmi_abi_version(void) { return 4; }
 
 }  // extern "C"

@@ -16,6 +16,14 @@
 // mark an invalid candidate) updates the candidate's maximum.  The Gram is
 // never stored.
 //
+// The same tiles also evaluate the smooth maximum of section IV,
+// F_{s,delta}(x) = s + delta log sum_i exp((x_i - s) / delta) over
+// x = |G_jk|^2 (or |G_jk|), j < k, with s = max x: a first launch finds s
+// (the maximum above), a second recomputes every tile with the same
+// arithmetic (so x <= s holds bit for bit) and sums exp((x - s) / delta) per
+// block into a slot of its own, and one block adds the slots in a fixed
+// order, so the result does not depend on scheduling.
+//
 // Tile: 64 x 64 complex outputs per 256-thread block, each wave a 32 x 32
 // quadrant (2 x 2 MFMA blocks, Re and Im accumulators).  K is staged through
 // LDS in chunks of 32 doubles, one double of padding per column so the 16
@@ -32,8 +40,17 @@ constexpr int T = kTileF64;
 constexpr int KC = 32;
 constexpr int LDA = KC + 1;
 
+// Parameters of the sum-exp epilogue (null: the maximum epilogue).
+struct SumExp {
+  const uint64_t* s_bits;  // max |G|^2 bits from the first launch
+  double inv_delta;
+  int32_t squared;         // x = |G|^2 (1) or |G| (0)
+  double* partial;         // [tile] block sums
+};
+
+template <bool SUMEXP>
 __device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int bi, int bj, double* As, double* Bs,
-                                              uint64_t* red) {
+                                              uint64_t* red, const SumExp& se) {
   const double* base = (const double*)a.cand + (size_t)slot * a.slot_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -98,6 +115,33 @@ __device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int b
     }
   }
 
+  if constexpr (SUMEXP) {
+    const double m_max = __longlong_as_double((int64_t)*se.s_bits);
+    const double s_x = se.squared ? m_max : sqrt(m_max);
+    double sum = 0.0;
+    if (!skip) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = bi * T + wr * 32 + r * 16 + 4 * v + (lane >> 4);
+            const int j = bj * T + wc * 32 + c * 16 + (lane & 15);
+            const double re = accR[r][c][v], im = accI[r][c][v];
+            const double m = re * re + im * im;
+            const double x = se.squared ? m : sqrt(m);
+            if (i < j && j < a.n) sum += exp((x - s_x) * se.inv_delta);
+          }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    double* reds = (double*)red;
+    if (lane == 0) reds[w] = sum;
+    __syncthreads();
+    if (tid == 0) se.partial[blockIdx.x] = (reds[0] + reds[1]) + (reds[2] + reds[3]);
+    return;
+  }
   uint64_t best = 0;
   if (!skip) {
 #pragma unroll
@@ -132,7 +176,43 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
   __shared__ uint64_t red[4];
   int bi, bj;
   tile_decode(blockIdx.x, a.nt, bi, bj);
-  gram_f64_tile(a, blockIdx.y, bi, bj, As, Bs, red);
+  gram_f64_tile<false>(a, blockIdx.y, bi, bj, As, Bs, red, SumExp{});
+}
+
+__global__ __launch_bounds__(256) void k_gram_f64_sumexp(GramArgs a, SumExp se) {
+  __shared__ double As[T * LDA];
+  __shared__ double Bs[T * LDA];
+  __shared__ uint64_t red[4];
+  int bi, bj;
+  tile_decode(blockIdx.x, a.nt, bi, bj);
+  gram_f64_tile<true>(a, 0, bi, bj, As, Bs, red, se);
+}
+
+// F = s + delta log(sum of the block sums), added in a fixed order: thread t
+// takes slots t, t + 256, ... in turn, then a fixed pairwise tree.
+__global__ __launch_bounds__(256) void k_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count,
+                                                    double delta, int32_t squared, double* out) {
+  __shared__ double acc[256];
+  double sum = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) sum += partial[i];
+  acc[threadIdx.x] = sum;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) acc[threadIdx.x] += acc[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t b = *s_bits;
+    if (b >= kInfBits64) {  // a zero or non-finite column
+      out[0] = __builtin_inf();
+      out[1] = __builtin_inf();
+      return;
+    }
+    const double m = __longlong_as_double((int64_t)b);
+    const double s = squared ? m : sqrt(m);
+    out[0] = s;
+    out[1] = s + delta * log(acc[0]);
+  }
 }
 
 }  // namespace
@@ -140,6 +220,20 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s) {
   const int tiles = a.nt * (a.nt + 1) / 2;
   hipLaunchKernelGGL(k_gram_f64, dim3(tiles, slots), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lse_sumexp(const GramArgs& a, const uint64_t* s_bits, double delta, int32_t squared,
+                             double* partial, hipStream_t s) {
+  const int tiles = a.nt * (a.nt + 1) / 2;
+  SumExp se{s_bits, 1.0 / delta, squared, partial};
+  hipLaunchKernelGGL(k_gram_f64_sumexp, dim3(tiles), dim3(256), 0, s, a, se);
+  return hipGetLastError();
+}
+
+hipError_t launch_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count, double delta,
+                             int32_t squared, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_lse_finish, dim3(1), dim3(256), 0, s, s_bits, partial, count, delta, squared, out);
   return hipGetLastError();
 }
 

@@ -161,6 +161,12 @@ int batch_lds_floats();
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
+// Smooth maximum (one frame, slot 0): block sums of exp((x - s) / delta) into
+// partial[tile], then F = s + delta log(sum) into out = (s, F).
+hipError_t launch_lse_sumexp(const GramArgs& a, const uint64_t* s_bits, double delta, int32_t squared,
+                             double* partial, hipStream_t s);
+hipError_t launch_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count, double delta,
+                             int32_t squared, double* out, hipStream_t s);
 hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);

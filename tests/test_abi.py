@@ -176,3 +176,21 @@ def test_timing_controls_without_device(L):
     assert ms.value == 0.0 and cnt.value == 0
     assert L.trstmi_timing_read(None, ctypes.byref(ms), ctypes.byref(cnt)) == abi.E_INVALID_ARG
     assert L.trstmi_abi_version() >= 3
+
+
+def test_lse_argument_checks(L):
+    """The smooth maximum rejects bad arguments before any launch."""
+    need = L.trstmi_lse_workspace_bytes(100, 8)
+    assert need > 100 * 16 * 8
+    assert L.trstmi_lse_workspace_bytes(1, 8) == 0 and L.trstmi_lse_workspace_bytes(100, 0) == 0
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    assert L.trstmi_lse(1, 8, p, 0.1, 1, p, ws, need, None) == abi.E_INVALID_ARG          # n < 2
+    assert L.trstmi_lse(100, 8, p, 0.0, 1, p, ws, need, None) == abi.E_INVALID_ARG        # delta <= 0
+    assert L.trstmi_lse(100, 8, p, float("inf"), 1, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse(100, 8, p, float("nan"), 1, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse(100, 8, p, 0.1, 2, p, ws, need, None) == abi.E_INVALID_ARG        # squared not 0/1
+    assert L.trstmi_lse(100, 8, None, 0.1, 1, p, ws, need, None) == abi.E_INVALID_ARG     # null frame
+    assert L.trstmi_lse(100, 8, ctypes.c_void_p(4104), 0.1, 1, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse(100, 8, p, 0.1, 1, p, ws, need - 1, None) == abi.E_WORKSPACE
+    assert L.trstmi_abi_version() >= 4
