@@ -157,6 +157,45 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
     }
 
 
+def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
+    """The smooth maximum of section IV on the throughput shape (one Haar
+    frame, N=4096, d=64): FP64 normalisation, the FP64 MFMA max pass, the
+    sum-exp pass over the same tiles and the fixed-order finish."""
+    s = lib.Solver(wl.n, wl.d, candidates=8, mode="fp64", seed=wl.seed, stream_id=wl.stream_id)
+    s.init_haar()
+    frame = s.state.frame
+    out = torch.empty(2, dtype=torch.float64, device=frame.device)
+    ws = torch.empty(lib.lse_workspace_bytes(wl.n, wl.d), dtype=torch.uint8, device=frame.device)
+    for _ in range(3):
+        lib.lse(frame, wl.n, wl.d, delta, True, out, ws)
+    torch.cuda.synchronize()
+    lib.timing_reset()
+    lib.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        lib.lse(frame, wl.n, wl.d, delta, True, out, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.timing_enable(False)
+    us = {}
+    for k in ("lse_max", "lse_sumexp"):
+        ms, cnt = lib.timing_read(k)
+        us[k] = 1e3 * ms / cnt
+    flops = flops_per_eval(wl.n, wl.d)  # per pass
+    s_val, f_val = out.cpu().numpy().tolist()
+    return {
+        "workload": f"F_(s,delta) of |G|^2 over j<k, N={wl.n}, d={wl.d}, delta={delta}, FP64 (Haar frame seed 0)",
+        "ms_per_eval": 1e3 * (t1 - t0) / evals,
+        "evals_per_s": evals / (t1 - t0),
+        "max_pass_us": us["lse_max"],
+        "sumexp_pass_us": us["lse_sumexp"],
+        "max_pass_frac_fp64_peak": flops / (us["lse_max"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+        "sumexp_pass_frac_fp64_peak": flops / (us["lse_sumexp"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+        "s": s_val,
+        "F": f_val,
+    }
+
+
 def run_serving(lib, count, max_steps, pool_gib):
     """The serving workload: Poisson arrivals (mean gap 5 ms), d in
     {8, 16, 32, 64, 128}, N uniform in [2d, 8d], each solved to 1.10 x Welch or
@@ -232,6 +271,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--smooth-max-evals", type=int, default=10,
+                    help="evaluations of the section IV smooth maximum at the throughput shape (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16, help="requests of the serving run (0: skip)")
     ap.add_argument("--serving-max-steps", type=int, default=5000)
     ap.add_argument("--serving-pool-gib", type=float, default=8.0)
@@ -265,6 +306,7 @@ def main():
         others[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
         others[m]["gram_avg_us"] = r["gram"]["avg_us"]
 
+    smooth = run_smooth_max(lib, torch, wl, args.smooth_max_evals) if args.smooth_max_evals > 0 else None
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
     serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib)
@@ -308,6 +350,7 @@ def main():
         "other_modes": others,
         "batched": batched,
         "serving": serving,
+        "smooth_max": smooth,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
