@@ -57,6 +57,7 @@ from .smoothmax import (  # noqa: F401
     smooth_max_of_values,
     smooth_max,
     smooth_max_bruteforce,
+    smooth_max_grad,
 )
 from .trstmi import (  # noqa: F401
     Params,

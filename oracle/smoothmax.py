@@ -80,3 +80,34 @@ def smooth_max_bruteforce(Phi, delta, squared=True):
             xs.append(m if squared else math.sqrt(m))
     s = max(xs)
     return s, s + delta * math.log(math.fsum(math.exp((v - s) / delta) for v in xs))
+
+
+def smooth_max_grad(Y, delta):
+    """Real gradient of F_{s,delta} over x = |G_jk|^2 (j < k) with respect to
+    the unconstrained frame Y (§IV: the columns of Y are normalised inside
+    the objective), returned as a complex d x N matrix g with
+    dF = sum Re(conj(g) * dY), i.e. g = 2 dF/d conj(Y).
+
+    The steps follow the chain of definitions:
+      w_jk = dF/dx_jk = exp((x_jk - s)/delta) / sum exp((x - s)/delta)
+             (the shift s cancels; w is symmetric, zero on the diagonal);
+      dx_jk/d conj(phi_k) = G_jk phi_j and dx_jk/d conj(phi_j) = conj(G_jk) phi_k,
+      so D = dF/d conj(Phi) = Phi (W o G);
+      phi_k = y_k / r_k gives dF/d conj(y_k) = (D_k - phi_k Re(phi_k^H D_k)) / r_k.
+    Returns None for a frame with a zero or non-finite column."""
+    Y = np.asarray(Y, dtype=np.complex128)
+    Phi, norms = normalize_columns(Y)
+    if not np.all(np.isfinite(norms) & (norms > 0.0)):
+        return None
+    G = gram(Phi)
+    N = G.shape[0]
+    X = G.real * G.real + G.imag * G.imag
+    iu = np.triu_indices(N, k=1)
+    s = float(np.max(X[iu]))
+    E = np.exp((X - s) / delta)
+    np.fill_diagonal(E, 0.0)
+    total = math.fsum(E[iu].tolist())
+    W = E / total                     # symmetric, both triangles carry w_jk
+    D = Phi @ (W * G)
+    c = np.sum((Phi.conj() * D).real, axis=0)
+    return 2.0 * (D - Phi * c[None, :]) / norms[None, :]

@@ -97,3 +97,36 @@ def test_invalid_column_and_arguments():
     assert oracle.smooth_max(F, 0.1) == (math.inf, math.inf)
     with pytest.raises(ValueError):
         oracle.smooth_max_of_values([0.1, 0.2], 0.0)
+
+
+@pytest.mark.parametrize("n,d,delta", [(8, 2, 0.1), (20, 3, 0.05), (40, 6, 0.01)])
+def test_gradient_matches_finite_differences(n, d, delta):
+    rng = np.random.default_rng(n + d)
+    Y = inputs.random_frame(n, d, seed=n) * (0.5 + rng.random(n))[None, :]
+    g = oracle.smooth_max_grad(Y, delta)
+    h = 1e-6
+    for _ in range(4):
+        E = rng.standard_normal(Y.shape) + 1j * rng.standard_normal(Y.shape)
+        fd = (oracle.smooth_max(Y + h * E, delta)[1] - oracle.smooth_max(Y - h * E, delta)[1]) / (2 * h)
+        an = float(np.sum((np.conj(g) * E).real))
+        assert abs(fd - an) <= 1e-6 * (1 + abs(an))
+
+
+def test_gradient_tangent_and_covariance():
+    rng = np.random.default_rng(3)
+    Y = inputs.random_frame(30, 4, seed=3)
+    g = oracle.smooth_max_grad(Y, 0.02)
+    Phi, norms = oracle.normalize_columns(Y)
+    # F does not change when a column is scaled: no radial component
+    assert np.max(np.abs(np.sum((Phi.conj() * g).real, axis=0))) <= 1e-13
+    # column scales c_k and phases: g_k -> g_k e^{i t_k} / c_k
+    c = 0.5 + rng.random(30)
+    ph = np.exp(2j * np.pi * rng.random(30))
+    g2 = oracle.smooth_max_grad(Y * (c * ph)[None, :], 0.02)
+    assert np.max(np.abs(g2 - g * (ph / c)[None, :])) <= 1e-12
+    # a unitary acting on the space: g -> Q g
+    Q, _ = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))
+    g3 = oracle.smooth_max_grad(Q @ Y, 0.02)
+    assert np.max(np.abs(g3 - Q @ g)) <= 1e-12
+    Y[:, 2] = 0
+    assert oracle.smooth_max_grad(Y, 0.02) is None
