@@ -179,6 +179,26 @@ size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d);
 trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta, int32_t squared,
                          double* out, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Bytes of workspace trstmi_lse_grad needs (0 if invalid or d > 64). */
+size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d);
+
+/*
+ * The smooth maximum of trstmi_lse over x = |G_jk|^2 and its gradient with
+ * respect to the unconstrained frame (section IV: the objective divides each
+ * column by its norm, so the frame itself is the free variable of the
+ * paper's trust-region minimisation): out (device, 2 doubles) = (s, F);
+ * grad (device, same layout and size as frame) = g with
+ *   dF = sum over entries of Re(conj(g) dframe),
+ * g_k = 2 (D_k - phi_k Re(phi_k^H D_k)) / |frame_k|, D = Phi (W o G),
+ * W_jk = exp((x_jk - s) / delta) / sum_{j<k} exp((x - s) / delta) (zero
+ * diagonal).  FP64, fixed summation order (repeatable bits).  A zero or
+ * non-finite column gives out = (+inf, +inf) and a NaN gradient.
+ * Requires n >= 2, 1 <= d <= 64 (TRSTMI_E_UNSUPPORTED above), delta finite
+ * and > 0; workspace of trstmi_lse_grad_workspace_bytes(n, d) bytes.
+ */
+trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double delta, double* out,
+                              double* grad, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /*
  * Random start (Alg. 2 step 1): state->frame <- N normalised CN(0, I_d)
  * columns drawn with tag 1 (candidate 0, step 0); *mu <- its coherence

@@ -104,6 +104,7 @@ def smooth_max_grad(Y, delta):
     X = G.real * G.real + G.imag * G.imag
     iu = np.triu_indices(N, k=1)
     s = float(np.max(X[iu]))
+    np.fill_diagonal(X, s)            # the diagonal is not a pair: zeroed below
     E = np.exp((X - s) / delta)
     np.fill_diagonal(E, 0.0)
     total = math.fsum(E[iu].tolist())

@@ -125,6 +125,27 @@ def lse(frame, n, d, delta, squared=True, out=None, workspace=None, stream=None)
     return out
 
 
+def lse_grad_workspace_bytes(n, d):
+    return _abi.lib().trstmi_lse_grad_workspace_bytes(int(n), int(d))
+
+
+def lse_grad(frame, n, d, delta, out=None, grad=None, workspace=None, stream=None):
+    """Smooth maximum over |G_jk|^2 and its gradient with respect to the
+    (unnormalised) device frame.  Returns (out, grad): out = (s, F) (shape
+    (2,), float64); grad has the frame's layout, dF = sum Re(conj(g) dframe)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=frame.device)
+    if grad is None:
+        grad = torch.empty_like(frame)
+    need = lse_grad_workspace_bytes(n, d)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=frame.device)
+    _abi.check(_abi.lib().trstmi_lse_grad(int(n), int(d), _ptr(frame), float(delta), _ptr(out), _ptr(grad),
+                                          _ptr(workspace), workspace.numel(), _stream(stream)), "trstmi_lse_grad")
+    return out, grad
+
+
 def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, stream=None):
     """The normalised FP64 candidates c0..c0+count-1 of step t (flat tensor,
     candidate i at offset i*2*d*n)."""

@@ -111,6 +111,8 @@ SIGNATURES = {
     "trstmi_coherence": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_lse_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_lse": (_i32, [_i64, _i64, _vp, ctypes.c_double, _i32, _vp, _vp, _sz, _vp]),
+    "trstmi_lse_grad_workspace_bytes": (_sz, [_i64, _i64]),
+    "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_init_haar": (_i32, [_P(Params), _P(State), _vp, _sz, _vp]),
     "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtrstmi.so")
 
-SOURCES = ["perturb.hip", "gram_f64.hip", "gram_f32.hip", "gram_bf16.hip", "select.hip", "batch.hip", "api.hip"]
+SOURCES = ["perturb.hip", "gram_f64.hip", "gram_f32.hip", "gram_bf16.hip", "select.hip", "batch.hip", "lse_grad.hip",
+           "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

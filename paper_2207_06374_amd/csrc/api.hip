@@ -661,7 +661,66 @@ trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta
   GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
   TRY_HIP(TIMED("lse_max", stream, launch_gram_f64(g, 1, stream)), "gram_f64");
   TRY_HIP(TIMED("lse_sumexp", stream, launch_lse_sumexp(g, mx, delta, squared, partial, stream)), "lse_sumexp");
-  TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, squared, out, stream), "lse_finish");
+  TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, squared, out, nullptr, stream), "lse_finish");
+  return TRSTMI_OK;
+}
+
+size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d) {
+  if (check_size(n, d) || d > 64) return 0;
+  const int64_t nkb = (n + kTileF64 - 1) / kTileF64;
+  const int64_t nch = lse_grad_chunks((int)nkb);
+  return trstmi_lse_workspace_bytes(n, d) + 256 + align256((size_t)nkb * nch * 2 * kTileF64 * 2 * d * 8);
+}
+
+trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double delta, double* out, double* grad,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (d > 64) return fail(TRSTMI_E_UNSUPPORTED, "the smooth-maximum gradient supports d <= 64");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TRSTMI_E_INVALID_ARG, "delta must be finite and > 0");
+  if (!frame || !out || !grad) return fail(TRSTMI_E_INVALID_ARG, "frame, out and grad must be device pointers");
+  if (((uintptr_t)frame & 15) || ((uintptr_t)out & 7) || ((uintptr_t)grad & 15))
+    return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_lse_grad_workspace_bytes(n, d);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  const size_t lse_bytes = trstmi_lse_workspace_bytes(n, d);
+  char* ws = (char*)workspace;
+  const int32_t ld = ld_mode(d, TRSTMI_MODE_FP64);
+  const size_t frame_bytes = align256((size_t)n * ld * 8);
+  uint64_t* mx = (uint64_t*)(ws + frame_bytes);
+  double* partial = (double*)(ws + frame_bytes + 256);
+  double* log_sum = (double*)(ws + lse_bytes);
+  double* gpart = (double*)(ws + lse_bytes + 256);
+  const int64_t nt = (n + kTileF64 - 1) / kTileF64;
+
+  PerturbArgs pa{};
+  pa.base = frame;
+  pa.have_z = 0;
+  pa.n = n;
+  pa.d = (int32_t)d;
+  pa.out = ws;
+  pa.out_kind = kOutF64;
+  pa.out_ld = ld;
+  pa.out_slot_stride = n * ld;
+  pa.zero_max = mx;
+  TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
+  GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
+  TRY_HIP(TIMED("lse_max", stream, launch_gram_f64(g, 1, stream)), "gram_f64");
+  TRY_HIP(TIMED("lse_sumexp", stream, launch_lse_sumexp(g, mx, delta, 1, partial, stream)), "lse_sumexp");
+  TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, 1, out, log_sum, stream), "lse_finish");
+  GradArgs ga{};
+  ga.frame = (const double*)ws;
+  ga.raw = frame;
+  ga.ld = ld;
+  ga.ldp = (int32_t)(((2 * d + 15) / 16) * 16 + 1);
+  ga.n = (int32_t)n;
+  ga.d = (int32_t)d;
+  ga.s_bits = mx;
+  ga.log_sum = log_sum;
+  ga.inv_delta = 1.0 / delta;
+  ga.partial = gpart;
+  ga.grad = grad;
+  TRY_HIP(TIMED("lse_grad", stream, launch_lse_grad(ga, stream)), "lse_grad");
   return TRSTMI_OK;
 }
 

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_gram_f64_sumexp(GramArgs a, SumExp se) 
 // F = s + delta log(sum of the block sums), added in a fixed order: thread t
 // takes slots t, t + 256, ... in turn, then a fixed pairwise tree.
 __global__ __launch_bounds__(256) void k_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count,
-                                                    double delta, int32_t squared, double* out) {
+                                                    double delta, int32_t squared, double* out, double* log_sum) {
   __shared__ double acc[256];
   double sum = 0.0;
   for (int64_t i = threadIdx.x; i < count; i += 256) sum += partial[i];
@@ -206,12 +206,15 @@ __global__ __launch_bounds__(256) void k_lse_finish(const uint64_t* s_bits, cons
     if (b >= kInfBits64) {  // a zero or non-finite column
       out[0] = __builtin_inf();
       out[1] = __builtin_inf();
+      if (log_sum) *log_sum = __builtin_inf();
       return;
     }
     const double m = __longlong_as_double((int64_t)b);
     const double s = squared ? m : sqrt(m);
+    const double ls = log(acc[0]);
     out[0] = s;
-    out[1] = s + delta * log(acc[0]);
+    out[1] = s + delta * ls;
+    if (log_sum) *log_sum = ls;
   }
 }
 
@@ -232,8 +235,8 @@ hipError_t launch_lse_sumexp(const GramArgs& a, const uint64_t* s_bits, double d
 }
 
 hipError_t launch_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count, double delta,
-                             int32_t squared, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_lse_finish, dim3(1), dim3(256), 0, s, s_bits, partial, count, delta, squared, out);
+                             int32_t squared, double* out, double* log_sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_lse_finish, dim3(1), dim3(256), 0, s, s_bits, partial, count, delta, squared, out, log_sum);
   return hipGetLastError();
 }
 

@@ -166,7 +166,24 @@ hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_lse_sumexp(const GramArgs& a, const uint64_t* s_bits, double delta, int32_t squared,
                              double* partial, hipStream_t s);
 hipError_t launch_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count, double delta,
-                             int32_t squared, double* out, hipStream_t s);
+                             int32_t squared, double* out, double* log_sum, hipStream_t s);
+
+// Gradient of the smooth maximum (x = |G|^2, d <= 64) with respect to the
+// unconstrained frame.
+struct GradArgs {
+  const double* frame;      // normalised frame (column stride ld)
+  const double* raw;        // the caller's frame (column stride 2d), for the column norms
+  int32_t ld;
+  int32_t ldp;              // LDS column stride: 2d rounded up to 16, plus one
+  int32_t n, d;
+  const uint64_t* s_bits;   // max |G|^2 bits
+  const double* log_sum;    // log of sum exp((x - s) / delta) over j < k
+  double inv_delta;
+  double* partial;          // [nkb][nch][2][64][2d]
+  double* grad;             // out: column stride 2d, (re, im) interleaved
+};
+int lse_grad_chunks(int nkb);
+hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s);
 hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);

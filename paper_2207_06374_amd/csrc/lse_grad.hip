@@ -1,0 +1,206 @@
+// Gradient of the smooth maximum of section IV with respect to the
+// unconstrained frame Y (the objective normalises Y's columns first):
+//   w_jk = exp((x_jk - s) / delta) / S   (x = |G|^2, S = sum over j < k),
+//   D = Phi (W o G)                        (W symmetric, zero diagonal),
+//   g_k = 2 (D_k - phi_k Re(phi_k^H D_k)) / ||y_k||,
+// so that dF = sum Re(conj(g) dY).
+//
+// k_lse_grad: a block owns 64 output columns k (tile kb) and a run of row
+// tiles jb.  Both 64-column tiles of the normalised frame sit in LDS with
+// the whole K = 2d (d <= 64).  Wave w computes G for all 64 rows j of tile
+// jb against its 16 columns k on v_mfma_f64_16x16x4f64, turns it into
+// B = W o G in registers, and feeds B straight into the second product
+// P = U_jb B (U: the real 2d-vectors of tile jb, rows m): the output layout
+// of a 16 x 16 block (register v of lane l: row 4 v + l / 16, column
+// l % 16) is the B-operand layout of the K step 4 v of the next product, so
+// no data moves between the two.  Re and Im of D come from the two real
+// products P1 = U Re(B), P2 = U Im(B) (D_re[i] = P1[2i] - P2[2i+1],
+// D_im[i] = P2[2i] + P1[2i+1]).  Each block writes its partial P1, P2 to a
+// slot of its own; k_lse_grad_finish adds the slots of a column in a fixed
+// order and applies the projection through the normalisation, so repeated
+// calls give the same bits.
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace trstmi {
+
+namespace {
+
+constexpr int T = 64;
+constexpr int kMaxLdp = 129;  // 2d rounded up to 16, plus one (d <= 64)
+
+__device__ __forceinline__ void stage_cols(const double* base, int ld, int n, int d, int c0, int ldp, double* Us) {
+  // columns c0 .. c0 + 63 of the normalised frame, entries 0 .. ldp - 2,
+  // zero past 2d and past column n
+  for (int idx = threadIdx.x; idx < T * (ldp - 1); idx += blockDim.x) {
+    const int col = idx / (ldp - 1), m = idx % (ldp - 1);
+    const int c = c0 + col;
+    Us[col * ldp + m] = (c < n && m < 2 * d) ? base[(size_t)c * ld + m] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
+  __shared__ double Uk[T * kMaxLdp];
+  __shared__ double Uj[T * kMaxLdp];
+  const int kb = blockIdx.x, ch = blockIdx.y;
+  const int nkb = gridDim.x, nch = gridDim.y;
+  const int jb0 = (int)(((int64_t)ch * nkb) / nch), jb1 = (int)(((int64_t)(ch + 1) * nkb) / nch);
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int ldp = a.ldp;
+  const int K4 = (2 * a.d + 3) & ~3;
+  const int MB = (2 * a.d + 15) / 16;
+  const uint64_t sb = *a.s_bits;
+  const bool valid = sb < kInfBits64;
+  const double s = __longlong_as_double((int64_t)sb);
+  const double logS = *a.log_sum;
+  const double inv_delta = a.inv_delta;
+
+  stage_cols(a.frame, a.ld, a.n, a.d, kb * T, ldp, Uk);
+
+  v4f64 P1[8], P2[8];
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    P1[mb] = v4f64{0.0, 0.0, 0.0, 0.0};
+    P2[mb] = v4f64{0.0, 0.0, 0.0, 0.0};
+  }
+  const int kl = lane >> 4;
+  const bool odd = kl & 1;
+  const int kcol = 16 * w + (lane & 15);  // this lane's column within tile kb
+  const int kglob = kb * T + kcol;
+
+  for (int jb = jb0; jb < jb1; ++jb) {
+    __syncthreads();  // Uj free (and Uk staged on the first pass)
+    stage_cols(a.frame, a.ld, a.n, a.d, jb * T, ldp, Uj);
+    __syncthreads();
+    v4f64 R[4], I[4];
+#pragma unroll
+    for (int jq = 0; jq < 4; ++jq) {
+      R[jq] = v4f64{0.0, 0.0, 0.0, 0.0};
+      I[jq] = v4f64{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int kk = 0; kk < K4 / 4; ++kk) {
+      const int k = 4 * kk + kl;
+      const double bu = Uk[kcol * ldp + k];
+      const double x = Uk[kcol * ldp + (k ^ 1)];
+      const double bv = odd ? -x : x;
+#pragma unroll
+      for (int jq = 0; jq < 4; ++jq) {
+        const double av = Uj[(16 * jq + (lane & 15)) * ldp + k];
+        R[jq] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bu, R[jq], 0, 0, 0);
+        I[jq] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, I[jq], 0, 0, 0);
+      }
+    }
+    // B = W o G in the output layout: register v of lane l is row
+    // j = 16 jq + 4 v + l / 16 of tile jb, column kcol
+#pragma unroll
+    for (int jq = 0; jq < 4; ++jq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jglob = jb * T + 16 * jq + 4 * v + kl;
+        const double re = R[jq][v], im = I[jq][v];
+        const double xv = re * re + im * im;
+        const bool use = valid && jglob != kglob && jglob < a.n && kglob < a.n;
+        const double wt = use ? exp((xv - s) * inv_delta - logS) : 0.0;
+        R[jq][v] = wt * re;
+        I[jq][v] = wt * im;
+      }
+    // P += U_jb B: K runs over the 64 rows j in steps of 4 (t = 4 jq + v)
+#pragma unroll
+    for (int jq = 0; jq < 4; ++jq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jq + 4 * v + kl;
+#pragma unroll
+        for (int mb = 0; mb < 8; ++mb) {
+          if (mb < MB) {
+            const double am = Uj[j * ldp + 16 * mb + (lane & 15)];
+            P1[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, R[jq][v], P1[mb], 0, 0, 0);
+            P2[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, I[jq][v], P2[mb], 0, 0, 0);
+          }
+        }
+      }
+  }
+  // partial slot (kb, ch): [2][64 columns][2d rows]
+  double* dst = a.partial + ((size_t)(kb * nch + ch) * 2) * T * (2 * a.d);
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    if (mb < MB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * mb + 4 * v + kl;
+        const int col = 16 * w + (lane & 15);
+        if (m < 2 * a.d) {
+          dst[(size_t)col * (2 * a.d) + m] = P1[mb][v];
+          dst[(size_t)T * (2 * a.d) + (size_t)col * (2 * a.d) + m] = P2[mb][v];
+        }
+      }
+    }
+  }
+}
+
+// One wave per column k: add the slots (kb, 0 .. nch - 1) in order, combine
+// into D_k, project and scale.  Lane i takes entries i, i + 64, ...
+__global__ __launch_bounds__(64) void k_lse_grad_finish(GradArgs a, int nch) {
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int d = a.d;
+  const int kb = k / T, kc = k % T;
+  const bool valid = *a.s_bits < kInfBits64;
+  double yy = 0.0, c = 0.0;
+  // first pass: the column's raw norm and c = Re(phi^H D)
+  for (int i = lane; i < d; i += 64) {
+    const double ya = a.raw[(size_t)k * 2 * d + 2 * i], yb = a.raw[(size_t)k * 2 * d + 2 * i + 1];
+    yy += ya * ya + yb * yb;
+  }
+  double dre[8], dim[8];  // d <= 64: at most one entry per lane, kept for both passes
+#pragma unroll
+  for (int q = 0; q < 8; ++q) dre[q] = dim[q] = 0.0;
+  for (int i = lane, q = 0; i < d; i += 64, ++q) {
+    double p1e = 0.0, p1o = 0.0, p2e = 0.0, p2o = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const double* src = a.partial + ((size_t)(kb * nch + ch) * 2) * T * (2 * d) + (size_t)kc * (2 * d);
+      p1e += src[2 * i];
+      p1o += src[2 * i + 1];
+      p2e += src[(size_t)T * (2 * d) + 2 * i];
+      p2o += src[(size_t)T * (2 * d) + 2 * i + 1];
+    }
+    dre[q] = p1e - p2o;
+    dim[q] = p2e + p1o;
+    const double pa = a.frame[(size_t)k * a.ld + 2 * i], pb = a.frame[(size_t)k * a.ld + 2 * i + 1];
+    c += pa * dre[q] + pb * dim[q];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    yy += __shfl_xor(yy, off, 64);
+    c += __shfl_xor(c, off, 64);
+  }
+  const double r = sqrt(yy);
+  const double scale = valid ? 2.0 / r : __builtin_nan("");
+  for (int i = lane, q = 0; i < d; i += 64, ++q) {
+    const double pa = a.frame[(size_t)k * a.ld + 2 * i], pb = a.frame[(size_t)k * a.ld + 2 * i + 1];
+    a.grad[(size_t)k * 2 * d + 2 * i] = scale * (dre[q] - c * pa);
+    a.grad[(size_t)k * 2 * d + 2 * i + 1] = scale * (dim[q] - c * pb);
+  }
+}
+
+}  // namespace
+
+int lse_grad_chunks(int nkb) {
+  // about 512 blocks: row tiles split into at most nkb runs
+  int nch = (512 + nkb - 1) / nkb;
+  return nch < 1 ? 1 : (nch > nkb ? nkb : nch);
+}
+
+hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s) {
+  const int nkb = (a.n + T - 1) / T;
+  const int nch = lse_grad_chunks(nkb);
+  hipLaunchKernelGGL(k_lse_grad, dim3(nkb, nch), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lse_grad_finish, dim3(a.n), dim3(64), 0, s, a, nch);
+  return hipGetLastError();
+}
+
+}  // namespace trstmi

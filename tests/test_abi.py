@@ -194,3 +194,16 @@ def test_lse_argument_checks(L):
     assert L.trstmi_lse(100, 8, ctypes.c_void_p(4104), 0.1, 1, p, ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_lse(100, 8, p, 0.1, 1, p, ws, need - 1, None) == abi.E_WORKSPACE
     assert L.trstmi_abi_version() >= 4
+
+
+def test_lse_grad_argument_checks(L):
+    need = L.trstmi_lse_grad_workspace_bytes(100, 8)
+    assert need > L.trstmi_lse_workspace_bytes(100, 8)
+    assert L.trstmi_lse_grad_workspace_bytes(100, 65) == 0
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    assert L.trstmi_lse_grad(100, 65, p, 0.1, p, p, ws, need, None) == abi.E_UNSUPPORTED
+    assert L.trstmi_lse_grad(100, 8, p, -1.0, p, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse_grad(100, 8, p, 0.1, p, None, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse_grad(100, 8, p, 0.1, p, ctypes.c_void_p(4104), ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse_grad(100, 8, p, 0.1, p, p, ws, need - 1, None) == abi.E_WORKSPACE

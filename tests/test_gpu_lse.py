@@ -81,3 +81,46 @@ def test_lse_full_size():
         s, f = _gpu(F, delta)
         assert abs(s - s_ref) <= 1e-14
         assert abs(f - f_ref) <= _tol(4096, delta)
+
+
+def _gpu_grad(F, delta):
+    d, n = F.shape
+    out, g = lib.lse_grad(lib.frame_to_device(F), n, d, delta)
+    return out.cpu().numpy().tolist(), lib.frame_from_device(g, n, d)
+
+
+GRAD_SHAPES = [(2, 1), (3, 2), (16, 4), (65, 3), (100, 7), (129, 5), (200, 16), (257, 33), (300, 64)]
+
+
+@pytest.mark.parametrize("n,d", GRAD_SHAPES)
+@pytest.mark.parametrize("delta", [0.1, 1e-2, 1e-3])
+def test_lse_grad_matches_oracle(n, d, delta):
+    rng = np.random.default_rng(n + d)
+    F = inputs.random_frame(n, d, seed=n * 7 + d) * (0.5 + rng.random(n))[None, :]   # unnormalised columns
+    (s, f), g = _gpu_grad(F, delta)
+    s_ref, f_ref = oracle.smooth_max(F, delta)
+    g_ref = oracle.smooth_max_grad(F, delta)
+    err = float(np.max(np.abs(g - g_ref)))
+    print(f"n={n} d={d} delta={delta} |g|max={float(np.max(np.abs(g_ref)))!r} err={err!r}", flush=True)
+    assert abs(s - s_ref) <= 1e-14 and abs(f - f_ref) <= _tol(n, delta)
+    assert err <= 2e-11 * max(1.0, float(np.max(np.abs(g_ref))))
+    # no radial component (F is invariant to column scale)
+    Phi, _ = oracle.normalize_columns(F)
+    assert float(np.max(np.abs(np.sum((Phi.conj() * g).real, axis=0)))) <= 1e-12
+
+
+def test_lse_grad_invalid_repeatable_and_full_size():
+    F = inputs.random_frame(70, 5, seed=1)
+    F[:, 3] = np.nan
+    (s, f), g = _gpu_grad(F, 0.1)
+    assert s == math.inf and f == math.inf and np.all(np.isnan(g))
+    F = inputs.random_frame(300, 32, seed=2)
+    dev = lib.frame_to_device(F)
+    _, g1 = lib.lse_grad(dev, 300, 32, 1e-2)
+    _, g2 = lib.lse_grad(dev, 300, 32, 1e-2)
+    assert np.array_equal(g1.cpu().numpy().view(np.uint64), g2.cpu().numpy().view(np.uint64))
+    p = oracle.Params(n=4096, d=64, seed=0)
+    F = oracle.haar_init(p).frame
+    (s, f), g = _gpu_grad(F, 1e-3)
+    g_ref = oracle.smooth_max_grad(F, 1e-3)
+    assert float(np.max(np.abs(g - g_ref))) <= 2e-11 * max(1.0, float(np.max(np.abs(g_ref))))
