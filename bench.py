@@ -160,7 +160,8 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
 def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     """The smooth maximum of section IV on the throughput shape (one Haar
     frame, N=4096, d=64): FP64 normalisation, the FP64 MFMA max pass, the
-    sum-exp pass over the same tiles and the fixed-order finish."""
+    sum-exp pass over the same tiles and the fixed-order finish; then the
+    value with its gradient with respect to the frame."""
     s = lib.Solver(wl.n, wl.d, candidates=8, mode="fp64", seed=wl.seed, stream_id=wl.stream_id)
     s.init_haar()
     frame = s.state.frame
@@ -183,6 +184,25 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
         us[k] = 1e3 * ms / cnt
     flops = flops_per_eval(wl.n, wl.d)  # per pass
     s_val, f_val = out.cpu().numpy().tolist()
+    # value and gradient with respect to the frame (the paper's optimiser's step)
+    grad = torch.empty_like(frame)
+    gws = torch.empty(lib.lse_grad_workspace_bytes(wl.n, wl.d), dtype=torch.uint8, device=frame.device)
+    for _ in range(2):
+        lib.lse_grad(frame, wl.n, wl.d, delta, out, grad, gws)
+    torch.cuda.synchronize()
+    lib.timing_reset()
+    lib.timing_enable(True)
+    t2 = time.perf_counter()
+    for _ in range(evals):
+        lib.lse_grad(frame, wl.n, wl.d, delta, out, grad, gws)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    lib.timing_enable(False)
+    ms, cnt = lib.timing_read("lse_grad")
+    grad_us = 1e3 * ms / cnt
+    n, d = wl.n, wl.d
+    grad_alg = 8 * d * n * (n - 1) // 2 + 8 * d * n * (n - 1)   # Gram once + D = Phi (W o G)
+    grad_issued = 16 * d * n * n                                  # the kernel forms G over the full square
     return {
         "workload": f"F_(s,delta) of |G|^2 over j<k, N={wl.n}, d={wl.d}, delta={delta}, FP64 (Haar frame seed 0)",
         "ms_per_eval": 1e3 * (t1 - t0) / evals,
@@ -193,6 +213,12 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
         "sumexp_pass_frac_fp64_peak": flops / (us["lse_sumexp"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
         "s": s_val,
         "F": f_val,
+        "grad_ms_per_eval": 1e3 * (t3 - t2) / evals,
+        "grad_pass_us": grad_us,
+        "grad_algorithmic_flop": grad_alg,
+        "grad_issued_flop": grad_issued,
+        "grad_pass_frac_fp64_peak": grad_alg / (grad_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+        "grad_pass_issued_frac_fp64_peak": grad_issued / (grad_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
     }
 
 
