@@ -712,7 +712,9 @@ trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double 
   ga.frame = (const double*)ws;
   ga.raw = frame;
   ga.ld = ld;
-  ga.ldp = (int32_t)(((2 * d + 15) / 16) * 16 + 1);
+  int32_t L = 16;  // LDS column: 2d rounded up to a power of two >= 16, plus one
+  while (L < 2 * d) L *= 2;
+  ga.ldp = L + 1;
   ga.n = (int32_t)n;
   ga.d = (int32_t)d;
   ga.s_bits = mx;

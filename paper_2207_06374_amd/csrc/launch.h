@@ -174,7 +174,7 @@ struct GradArgs {
   const double* frame;      // normalised frame (column stride ld)
   const double* raw;        // the caller's frame (column stride 2d), for the column norms
   int32_t ld;
-  int32_t ldp;              // LDS column stride: 2d rounded up to 16, plus one
+  int32_t ldp;              // LDS column stride: 2d rounded up to a power of two >= 16, plus one
   int32_t n, d;
   const uint64_t* s_bits;   // max |G|^2 bits
   const double* log_sum;    // log of sum exp((x - s) / delta) over j < k

@@ -18,7 +18,8 @@
 // D_im[i] = P2[2i] + P1[2i+1]).  Each block writes its partial P1, P2 to a
 // slot of its own; k_lse_grad_finish adds the slots of a column in a fixed
 // order and applies the projection through the normalisation, so repeated
-// calls give the same bits.
+// calls give the same bits.  The next row tile is loaded into registers
+// while the current one is multiplied (one wave per SIMD: 132 KB of LDS).
 
 #include "device_common.h"
 #include "launch.h"
@@ -37,6 +38,41 @@ __device__ __forceinline__ void stage_cols(const double* base, int ld, int n, in
     const int col = idx / (ldp - 1), m = idx % (ldp - 1);
     const int c = c0 + col;
     Us[col * ldp + m] = (c < n && m < 2 * d) ? base[(size_t)c * ld + m] : 0.0;
+  }
+}
+
+// The next row tile in registers while the current one is multiplied.  The
+// LDS column holds L = ldp - 1 doubles, a power of two (16 .. 128), so a
+// thread's 16-byte pieces sit at a fixed column stride: pair p = tid mod L/2
+// of columns tid / (L/2) + q (512 / L), q = 0 .. L/32 - 1.
+constexpr int kPre = T * (kMaxLdp - 1) / 2 / 256;  // double2 per thread, at most
+
+__device__ __forceinline__ void fetch_cols(const double* base, int ld, int n, int d, int c0, int ldp,
+                                           double2 pre[kPre]) {
+  const int L2 = (ldp - 1) / 2;
+  const int p = threadIdx.x % L2;
+  const int col0 = threadIdx.x / L2, cstep = 256 / L2;
+  const int nq = T / cstep;
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int c = c0 + col0 + q * cstep;
+    pre[q] = (q < nq && c < n && 2 * p < 2 * d) ? *(const double2*)(base + (size_t)c * ld + 2 * p)
+                                               : make_double2(0.0, 0.0);
+  }
+}
+
+__device__ __forceinline__ void put_cols(const double2 pre[kPre], int ldp, double* Us) {
+  const int L2 = (ldp - 1) / 2;
+  const int p = threadIdx.x % L2;
+  const int col0 = threadIdx.x / L2, cstep = 256 / L2;
+  const int nq = T / cstep;
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    if (q < nq) {
+      double* dst = Us + (col0 + q * cstep) * ldp + 2 * p;
+      dst[0] = pre[q].x;
+      dst[1] = pre[q].y;
+    }
   }
 }
 
@@ -70,10 +106,13 @@ __global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
   const int kcol = 16 * w + (lane & 15);  // this lane's column within tile kb
   const int kglob = kb * T + kcol;
 
+  double2 pre[kPre];
+  fetch_cols(a.frame, a.ld, a.n, a.d, jb0 * T, ldp, pre);
   for (int jb = jb0; jb < jb1; ++jb) {
     __syncthreads();  // Uj free (and Uk staged on the first pass)
-    stage_cols(a.frame, a.ld, a.n, a.d, jb * T, ldp, Uj);
+    put_cols(pre, ldp, Uj);
     __syncthreads();
+    if (jb + 1 < jb1) fetch_cols(a.frame, a.ld, a.n, a.d, (jb + 1) * T, ldp, pre);
     v4f64 R[4], I[4];
 #pragma unroll
     for (int jq = 0; jq < 4; ++jq) {
