@@ -24,6 +24,9 @@ tuning for matrix incoherence", arXiv:2207.06374):
   emulate the reduced-precision screening forms.
 * ``smoothmax``  -- the shifted log-sum-exp smooth maximum of §IV over the
   upper-triangle Gram moduli (the objective the paper's optimiser uses).
+* ``trust_region`` -- the trust-region step of the paper's optimiser:
+  Steihaug CG (Alg. 1, read with the textbook's completion) on the smooth
+  maximum, and the outer ratio test and radius update.
 * ``trstmi``     -- Haar start, candidate generation, evaluation,
   select/accept and radius update, step and solve.
 
@@ -58,6 +61,13 @@ from .smoothmax import (  # noqa: F401
     smooth_max,
     smooth_max_bruteforce,
     smooth_max_grad,
+)
+from .trust_region import (  # noqa: F401
+    TRParams,
+    TRReport,
+    cg_steihaug,
+    tr_step,
+    rdot,
 )
 from .trstmi import (  # noqa: F401
     Params,
