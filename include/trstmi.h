@@ -199,6 +199,56 @@ size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d);
 trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double delta, double* out,
                               double* grad, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Exit of Steihaug CG (trstmi_tr_report.cg_exit). */
+enum {
+  TRSTMI_CG_SMALL_RESIDUAL = 0,      /* |r| < cg_tol: interior step */
+  TRSTMI_CG_NEGATIVE_CURVATURE = 1,  /* d.Bd <= 0: to the boundary point with the lower model value */
+  TRSTMI_CG_BOUNDARY = 2,            /* the next iterate would leave the region: stop on the boundary */
+  TRSTMI_CG_MAX_ITER = 3,            /* cg_max_iter iterations */
+  TRSTMI_CG_ZERO_GRADIENT = 4        /* |g| < cg_tol: no step */
+};
+
+typedef struct {
+  double delta;       /* smoothing of the maximum, > 0 */
+  double radius;      /* trust radius of this step, > 0 */
+  double radius_max;  /* cap of the radius rule, >= radius */
+  double eta;         /* the step is taken when rho > eta, 0 <= eta < 1/4 */
+  double cg_tol;      /* residual norm that ends CG, > 0 */
+  int32_t cg_max_iter;/* >= 1 */
+  double fd_step;     /* central-difference step of Hessian-vector products, > 0 */
+} trstmi_tr_params;
+
+typedef struct {
+  double f_old, f_new;  /* F at the frame and at frame + step (f_new = f_old if no step was tried) */
+  double rho;           /* actual / predicted decrease */
+  double step_norm;
+  double new_radius;    /* radius for the next step */
+  int32_t cg_iters, cg_exit, accepted;
+} trstmi_tr_report;
+
+/* Bytes of workspace trstmi_tr_step needs (0 if invalid or d > 64). */
+size_t trstmi_tr_workspace_bytes(int64_t n, int64_t d);
+
+/*
+ * One trust-region step of the paper's optimiser (section IV) on the smooth
+ * maximum over |G|^2 of the unconstrained frame (device, in/out): Alg. 1,
+ * Steihaug's truncated CG for min g.p + p.B p / 2 over |p| <= radius, read
+ * with the textbook's completion of the printed listing (boundary test on
+ * the new iterate, residual test on the new residual, the beta / direction
+ * update; negative curvature goes to the boundary point with the lower
+ * model value); B p by central differences of trstmi_lse_grad along p/|p|.
+ * Then rho = (F(frame) - F(frame + p)) / (m(0) - m(p)); rho < 1/4 divides
+ * the radius by 4, rho > 3/4 with |p| = radius doubles it (up to
+ * radius_max), and frame <- frame + p when rho > eta.  *rep (host) gets
+ * the outcome.  All vector work runs on the GPU (fixed-order dot products:
+ * repeatable bits); the call synchronises the stream a few times per CG
+ * iteration to read scalars.  Requires n >= 2, 1 <= d <= 64; a frame with
+ * a zero or non-finite column returns TRSTMI_E_INVALID_ARG (frame unchanged).
+ */
+trstmi_status trstmi_tr_step(int64_t n, int64_t d, double* frame, const trstmi_tr_params* params,
+                             trstmi_tr_report* rep, void* workspace, size_t workspace_bytes,
+                             hipStream_t stream);
+
 /*
  * Random start (Alg. 2 step 1): state->frame <- N normalised CN(0, I_d)
  * columns drawn with tag 1 (candidate 0, step 0); *mu <- its coherence

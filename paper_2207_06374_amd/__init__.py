@@ -146,6 +146,26 @@ def lse_grad(frame, n, d, delta, out=None, grad=None, workspace=None, stream=Non
     return out, grad
 
 
+def tr_workspace_bytes(n, d):
+    return _abi.lib().trstmi_tr_workspace_bytes(int(n), int(d))
+
+
+def tr_step(frame, n, d, delta, radius, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg_max_iter=20, fd_step=1e-6,
+            workspace=None, stream=None):
+    """One trust-region step (Steihaug CG + ratio test) on the smooth maximum
+    of the device frame, updated in place when the step is taken.  Returns the
+    report as a dict."""
+    torch = _torch()
+    p = _abi.TRParams(float(delta), float(radius), float(radius_max), float(eta), float(cg_tol), int(cg_max_iter),
+                      float(fd_step))
+    rep = _abi.TRReport()
+    if workspace is None:
+        workspace = torch.empty(max(tr_workspace_bytes(n, d), 1), dtype=torch.uint8, device=frame.device)
+    _abi.check(_abi.lib().trstmi_tr_step(int(n), int(d), _ptr(frame), ctypes.byref(p), ctypes.byref(rep),
+                                         _ptr(workspace), workspace.numel(), _stream(stream)), "trstmi_tr_step")
+    return {k: getattr(rep, k) for k, _ in _abi.TRReport._fields_}
+
+
 def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, stream=None):
     """The normalised FP64 candidates c0..c0+count-1 of step t (flat tensor,
     candidate i at offset i*2*d*n)."""

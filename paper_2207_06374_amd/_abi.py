@@ -103,6 +103,18 @@ _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
 _sz = ctypes.c_size_t
 
+class TRParams(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("radius", ctypes.c_double), ("radius_max", ctypes.c_double),
+                ("eta", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
+                ("fd_step", ctypes.c_double)]
+
+
+class TRReport(ctypes.Structure):
+    _fields_ = [("f_old", ctypes.c_double), ("f_new", ctypes.c_double), ("rho", ctypes.c_double),
+                ("step_norm", ctypes.c_double), ("new_radius", ctypes.c_double), ("cg_iters", ctypes.c_int32),
+                ("cg_exit", ctypes.c_int32), ("accepted", ctypes.c_int32)]
+
+
 # name: (restype, argtypes)
 SIGNATURES = {
     "trstmi_default_params": (None, [_P(Params), _i64, _i64]),
@@ -113,6 +125,8 @@ SIGNATURES = {
     "trstmi_lse": (_i32, [_i64, _i64, _vp, ctypes.c_double, _i32, _vp, _vp, _sz, _vp]),
     "trstmi_lse_grad_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    "trstmi_tr_workspace_bytes": (_sz, [_i64, _i64]),
+    "trstmi_tr_step": (_i32, [_i64, _i64, _vp, _P(TRParams), _P(TRReport), _vp, _sz, _vp]),
     "trstmi_init_haar": (_i32, [_P(Params), _P(State), _vp, _sz, _vp]),
     "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),

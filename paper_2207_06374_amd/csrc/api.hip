@@ -726,6 +726,33 @@ trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double 
   return TRSTMI_OK;
 }
 
+size_t trstmi_tr_workspace_bytes(int64_t n, int64_t d) {
+  const size_t g = trstmi_lse_grad_workspace_bytes(n, d);
+  return g ? align256(g) + tr_vectors_bytes(n, d) : 0;
+}
+
+trstmi_status trstmi_tr_step(int64_t n, int64_t d, double* frame, const trstmi_tr_params* tp, trstmi_tr_report* rep,
+                             void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (d > 64) return fail(TRSTMI_E_UNSUPPORTED, "the trust-region step supports d <= 64");
+  if (!tp || !rep) return fail(TRSTMI_E_INVALID_ARG, "params and report must be host pointers");
+  auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
+  if (!pos(tp->delta) || !pos(tp->radius) || !pos(tp->cg_tol) || !pos(tp->fd_step) ||
+      !(tp->radius_max >= tp->radius) || !std::isfinite(tp->radius_max) || !(tp->eta >= 0.0 && tp->eta < 0.25) ||
+      tp->cg_max_iter < 1)
+    return fail(TRSTMI_E_INVALID_ARG, "invalid trust-region parameters");
+  if (!frame) return fail(TRSTMI_E_INVALID_ARG, "frame must be a device pointer");
+  if ((uintptr_t)frame & 15) return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_tr_workspace_bytes(n, d);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  const size_t lws = align256(trstmi_lse_grad_workspace_bytes(n, d));
+  st = tr_step_impl(n, d, frame, tp, rep, (char*)workspace, lws, stream);
+  if (st == TRSTMI_E_HIP) return fail(TRSTMI_E_HIP, "trust-region step: a HIP call failed");
+  if (st == TRSTMI_E_INVALID_ARG) return fail(TRSTMI_E_INVALID_ARG, "the frame has a zero or non-finite column");
+  return st;
+}
+
 trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state, void* workspace,
                                size_t workspace_bytes, hipStream_t stream) {
   trstmi_status st = check_params(p);

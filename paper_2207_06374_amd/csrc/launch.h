@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "trstmi.h"
+
 namespace trstmi {
 
 enum OutKind { kOutF64 = 0, kOutF32 = 1, kOutBF16 = 2 };
@@ -184,6 +186,12 @@ struct GradArgs {
 };
 int lse_grad_chunks(int nkb);
 hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s);
+
+// Trust-region step (trust_region.hip): the vectors' workspace bytes, and the
+// step itself given a trstmi_lse_grad workspace of lws_bytes at ws.
+size_t tr_vectors_bytes(int64_t n, int64_t d);
+trstmi_status tr_step_impl(int64_t n, int64_t d, double* frame, const trstmi_tr_params* tp, trstmi_tr_report* rep,
+                           char* ws, size_t lws_bytes, hipStream_t stream);
 hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);

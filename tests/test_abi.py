@@ -207,3 +207,20 @@ def test_lse_grad_argument_checks(L):
     assert L.trstmi_lse_grad(100, 8, p, 0.1, p, None, ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_lse_grad(100, 8, p, 0.1, p, ctypes.c_void_p(4104), ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_lse_grad(100, 8, p, 0.1, p, p, ws, need - 1, None) == abi.E_WORKSPACE
+
+
+def test_tr_step_argument_checks(L):
+    need = L.trstmi_tr_workspace_bytes(100, 8)
+    assert need > L.trstmi_lse_grad_workspace_bytes(100, 8)
+    assert L.trstmi_tr_workspace_bytes(100, 65) == 0
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    good = abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 20, 1e-6)
+    rep = abi.TRReport()
+    assert L.trstmi_tr_step(100, 65, p, ctypes.byref(good), ctypes.byref(rep), ws, need, None) == abi.E_UNSUPPORTED
+    for bad in (abi.TRParams(0.0, 0.1, 1.0, 0.1, 1e-8, 20, 1e-6), abi.TRParams(0.05, -1.0, 1.0, 0.1, 1e-8, 20, 1e-6),
+                abi.TRParams(0.05, 0.1, 0.05, 0.1, 1e-8, 20, 1e-6), abi.TRParams(0.05, 0.1, 1.0, 0.3, 1e-8, 20, 1e-6),
+                abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 0, 1e-6), abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 20, 0.0)):
+        assert L.trstmi_tr_step(100, 8, p, ctypes.byref(bad), ctypes.byref(rep), ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_tr_step(100, 8, p, None, ctypes.byref(rep), ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_tr_step(100, 8, p, ctypes.byref(good), ctypes.byref(rep), ws, need - 1, None) == abi.E_WORKSPACE

@@ -1,0 +1,101 @@
+"""GPU parity: trstmi_tr_step (Steihaug CG of Alg. 1 + ratio test) against the oracle's step."""
+
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2207_06374_amd")
+
+
+def _compare(Y, params, tol=1e-6):
+    d, n = Y.shape
+    dev = lib.frame_to_device(Y)
+    rep = lib.tr_step(dev, n, d, params.delta, params.radius, params.radius_max, params.eta, params.cg_tol,
+                      params.cg_max_iter, params.fd_step)
+    Y_ref, r = oracle.tr_step(Y, params)
+    Y_got = lib.frame_from_device(dev, n, d)
+    print(f"n={n} d={d} radius={params.radius} gpu={rep} ref={r}", flush=True)
+    assert rep["cg_exit"] == r.cg_exit and rep["cg_iters"] == r.cg_iters
+    assert bool(rep["accepted"]) == r.accepted
+    # The finite-difference Hessian amplifies the GPU / oracle gradient
+    # difference (about 1e-15) by 1 / fd_step, so the steps agree to about
+    # 1e-10 relative; F(frame + p) then differs by |grad F| times that, and
+    # rho by that over the predicted decrease.
+    assert abs(rep["f_old"] - r.f_old) <= 1e-13
+    df = abs(rep["f_new"] - r.f_new)
+    assert df <= 1e-12 + tol * r.step_norm
+    assert abs(rep["step_norm"] - r.step_norm) <= tol * r.step_norm + 1e-15
+    dec = abs(r.f_old - r.f_new)
+    assert abs(rep["rho"] - r.rho) <= tol * (1 + abs(r.rho)) + (2 * df * abs(r.rho) / dec if dec > 0 else 0.0)
+    assert rep["new_radius"] == r.new_radius
+    assert np.max(np.abs(Y_got - Y_ref)) <= tol * max(r.step_norm, 1e-12)
+    return Y_ref, r
+
+
+@pytest.mark.parametrize("n,d,delta", [(40, 4, 0.05), (65, 3, 0.02), (300, 16, 0.01)])
+def test_tr_steps_match_oracle(n, d, delta):
+    Y = inputs.random_frame(n, d, seed=n + d)
+    params = oracle.TRParams(delta=delta, radius=0.1, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg_max_iter=20,
+                             fd_step=1e-6)
+    for _ in range(4):
+        Y, r = _compare(Y, params)
+        params.radius = r.new_radius
+
+
+def test_tr_large_delta_and_radius():
+    # a smoother maximum and the largest radius
+    Y = inputs.random_frame(30, 5, seed=9)
+    params = oracle.TRParams(delta=0.2, radius=1.0, radius_max=1.0, eta=0.1, cg_tol=1e-3, cg_max_iter=6,
+                             fd_step=1e-6)
+    _compare(Y, params, tol=1e-5)
+
+
+def test_tr_full_size_one_step():
+    p = oracle.Params(n=4096, d=64, seed=0)
+    Y = oracle.haar_init(p).frame
+    params = oracle.TRParams(delta=1e-3, radius=0.05, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg_max_iter=2,
+                             fd_step=1e-6)
+    _compare(Y, params)
+
+
+def test_tr_invalid_column_raises():
+    Y = inputs.random_frame(20, 3, seed=1)
+    Y[:, 4] = 0
+    dev = lib.frame_to_device(Y)
+    with pytest.raises(RuntimeError) as e:
+        lib.tr_step(dev, 20, 3, 0.05, 0.1)
+    assert e.value.status == 1 and "non-finite" in str(e.value)
+
+
+def _oracle_state(n, d, delta, seed, steps, cg_tol, cg_max_iter):
+    """The frame and radius after `steps` oracle steps from a random start."""
+    Y = inputs.random_frame(n, d, seed=seed)
+    p = oracle.TRParams(delta=delta, radius=0.1, radius_max=1.0, eta=0.1, cg_tol=cg_tol, cg_max_iter=cg_max_iter,
+                        fd_step=1e-6)
+    for _ in range(steps):
+        Y, r = oracle.tr_step(Y, p)
+        p.radius = r.new_radius
+    return Y, p
+
+
+@pytest.mark.parametrize("n,d,delta,seed,steps,cg_max_iter,want", [
+    (4, 2, 0.05, 0, 25, 10, oracle.trust_region.EXIT_SMALL_RESIDUAL),
+    (4, 2, 0.05, 0, 26, 10, oracle.trust_region.EXIT_ZERO_GRADIENT),
+    # the interior state above with the cap below the 5 iterations CG needs there (a capped state deep in a
+    # 10-iteration run is so ill-conditioned that 1e-15 changes in the gradient move the step by 1e-6)
+    (4, 2, 0.05, 0, 25, 3, oracle.trust_region.EXIT_MAX_ITER),
+    (4, 2, 0.05, 0, 0, 10, oracle.trust_region.EXIT_NEGATIVE_CURVATURE),
+])
+def test_tr_every_cg_exit(n, d, delta, seed, steps, cg_max_iter, want):
+    Y, p = _oracle_state(n, d, delta, seed, steps, 1e-6, 10)
+    p.cg_max_iter = cg_max_iter
+    _, r = oracle.tr_step(Y, p)
+    assert r.cg_exit == want
+    _compare(Y, p, tol=1e-5)
