@@ -200,6 +200,20 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     lib.timing_enable(False)
     ms, cnt = lib.timing_read("lse_grad")
     grad_us = 1e3 * ms / cnt
+    # trust-region steps (Steihaug CG with finite-difference Hessian products)
+    # from the same frame; each CG iteration costs two value-and-gradient calls
+    Y = frame.clone()
+    tws = torch.empty(lib.tr_workspace_bytes(wl.n, wl.d), dtype=torch.uint8, device=frame.device)
+    radius, tr_reps = 0.05, []
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(3):
+        rep = lib.tr_step(Y, wl.n, wl.d, delta, radius, cg_max_iter=5, workspace=tws)
+        tr_reps.append(rep)
+        radius = rep["new_radius"]
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    grad_calls = sum(1 + 2 * r["cg_iters"] for r in tr_reps)
     n, d = wl.n, wl.d
     grad_alg = 8 * d * n * (n - 1) // 2 + 8 * d * n * (n - 1)   # Gram once + D = Phi (W o G)
     grad_issued = 16 * d * n * n                                  # the kernel forms G over the full square
@@ -219,6 +233,12 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
         "grad_issued_flop": grad_issued,
         "grad_pass_frac_fp64_peak": grad_alg / (grad_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
         "grad_pass_issued_frac_fp64_peak": grad_issued / (grad_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+        "tr_steps": len(tr_reps),
+        "tr_ms_per_step": 1e3 * (t5 - t4) / len(tr_reps),
+        "tr_ms_per_gradient_call": 1e3 * (t5 - t4) / grad_calls,
+        "tr_cg_iters": [r["cg_iters"] for r in tr_reps],
+        "tr_cg_exit": [r["cg_exit"] for r in tr_reps],
+        "tr_F": [tr_reps[0]["f_old"]] + [r["f_new"] if r["accepted"] else r["f_old"] for r in tr_reps],
     }
 
 
