@@ -68,6 +68,8 @@ from .trust_region import (  # noqa: F401
     cg_steihaug,
     tr_step,
     rdot,
+    OptParams,
+    optimize,
 )
 from .trstmi import (  # noqa: F401
     Params,

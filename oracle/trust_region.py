@@ -146,3 +146,44 @@ def tr_step(Y, p: TRParams):
         radius = min(2 * p.radius, p.radius_max)
     accepted = rho > p.eta
     return (Y + step if accepted else Y.copy()), TRReport(f0, f1, rho, snorm, radius, iters, code, accepted)
+
+
+@dataclass
+class OptParams:
+    restarts: int = 8                     # L random starts (the paper uses L = 2 d^2)
+    deltas: tuple = (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4)   # decreasing smoothing (continuation)
+    steps_per_delta: int = 40
+    radius0: float = 0.1                  # radius at the start of every delta
+    radius_min: float = 1e-10             # a delta ends when the radius falls below this
+    radius_max: float = 1.0
+    eta: float = 0.1
+    cg_tol: float = 1e-10
+    cg_max_iter: int = 0                  # 0: 2 d N (the dimension of the real search space)
+    fd_step: float = 1e-6
+    seed: int = 0
+
+
+def optimize(n, d, op: OptParams):
+    """The paper's outer procedure (Alg. 2): for each of L random starts
+    (the Haar start of stream l), minimise F_{s,delta_k} with trust-region
+    steps for a decreasing sequence of delta_k, feeding each minimiser to the
+    next; keep the frame with the smallest coherence.  Returns
+    (best mu, best restart index, best frame)."""
+    from .trstmi import Params, haar_init
+    from .coherence import coherence
+
+    best = (math.inf, -1, None)
+    for l in range(op.restarts):
+        Y = haar_init(Params(n=n, d=d, seed=op.seed, stream_id=l)).frame
+        for dl in op.deltas:
+            p = TRParams(delta=dl, radius=op.radius0, radius_max=op.radius_max, eta=op.eta, cg_tol=op.cg_tol,
+                         cg_max_iter=op.cg_max_iter or 2 * d * n, fd_step=op.fd_step)
+            for _ in range(op.steps_per_delta):
+                Y, r = tr_step(Y, p)
+                p.radius = r.new_radius
+                if p.radius < op.radius_min or r.cg_exit == EXIT_ZERO_GRADIENT:
+                    break
+        mu = coherence(Y)
+        if mu < best[0]:
+            best = (mu, l, Y)
+    return best

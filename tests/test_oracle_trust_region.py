@@ -105,3 +105,24 @@ def test_tr_step_decreases_and_follows_the_radius_rules():
         else:
             assert r.new_radius == p.radius
         Y, p.radius = Y2, r.new_radius
+
+
+def _table2():
+    rows = {}
+    import os
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table2_trstmi_mu.txt")):
+        if line.strip() and not line.startswith("#"):
+            d, n, mu = line.split()
+            rows[int(d)] = (int(n), float(mu))
+    return rows
+
+
+@pytest.mark.parametrize("d,restarts", [(2, 8), (3, 6)])
+def test_optimize_reaches_table2(d, restarts):
+    """Alg. 2 (continuation over delta, random restarts, trust-region steps)
+    reaches the printed Table II coherence at N = d^2, which is also the
+    Welch bound there, so the value is optimal."""
+    n, printed = _table2()[d]
+    mu, l, Y = oracle.optimize(n, d, oracle.OptParams(restarts=restarts))
+    assert oracle.welch_bound(n, d) - 1e-12 <= mu <= printed
+    assert abs(mu - oracle.coherence(Y)) == 0.0
