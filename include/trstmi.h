@@ -249,6 +249,40 @@ trstmi_status trstmi_tr_step(int64_t n, int64_t d, double* frame, const trstmi_t
                              trstmi_tr_report* rep, void* workspace, size_t workspace_bytes,
                              hipStream_t stream);
 
+typedef struct {
+  uint64_t seed;           /* random starts: stream l of this seed, l = 0 .. restarts - 1 */
+  int32_t restarts;        /* L >= 1 (the paper uses L = 2 d^2) */
+  int32_t n_deltas;        /* >= 1 */
+  const double* deltas;    /* host array of n_deltas decreasing smoothing values, each > 0 */
+  int32_t steps_per_delta; /* trust-region steps per delta, >= 1 */
+  double radius0;          /* radius at the start of every delta, > 0 */
+  double radius_min;       /* a delta ends when the radius falls below this, >= 0 */
+  double radius_max;       /* >= radius0 */
+  double eta;              /* 0 <= eta < 1/4 */
+  double cg_tol;           /* > 0 */
+  int32_t cg_max_iter;     /* >= 1, or 0 for 2 d N */
+  double fd_step;          /* > 0 */
+} trstmi_opt_params;
+
+/* Bytes of workspace trstmi_optimize needs (0 if invalid or d > 64). */
+size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d);
+
+/*
+ * The paper's outer procedure (Alg. 2): for each of L random starts (the
+ * Haar start of trstmi_init_haar with stream_id l), minimise the smooth
+ * maximum F_{s,delta_k} over |G|^2 with trust-region steps (trstmi_tr_step)
+ * for the decreasing deltas in turn, each continuing from the previous
+ * minimiser (a delta ends after steps_per_delta steps, when the radius
+ * falls below radius_min, or when the gradient vanishes); then the exact
+ * FP64 coherence of the result.  best_frame (device, caller's layout)
+ * receives the frame with the smallest coherence, *best_mu and
+ * *best_restart (host) its coherence and start index.  Synchronises the
+ * stream.  Requires n >= 2, 1 <= d <= 64.
+ */
+trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* params, double* best_frame,
+                              double* best_mu, int32_t* best_restart, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream);
+
 /*
  * Random start (Alg. 2 step 1): state->frame <- N normalised CN(0, I_d)
  * columns drawn with tag 1 (candidate 0, step 0); *mu <- its coherence

@@ -166,6 +166,29 @@ def tr_step(frame, n, d, delta, radius, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg
     return {k: getattr(rep, k) for k, _ in _abi.TRReport._fields_}
 
 
+def optimize(n, d, restarts=None, deltas=(1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4), steps_per_delta=40, seed=0,
+             radius0=0.1, radius_min=1e-10, radius_max=1.0, eta=0.1, cg_tol=1e-10, cg_max_iter=0, fd_step=1e-6,
+             device="cuda", workspace=None, stream=None):
+    """The outer procedure of Alg. 2 (delta continuation and random restarts
+    around trust-region steps).  Returns (best frame as a device tensor,
+    best coherence, best restart index).  restarts defaults to 2 d^2."""
+    torch = _torch()
+    L = int(restarts) if restarts is not None else 2 * int(d) * int(d)
+    dl = (ctypes.c_double * len(deltas))(*[float(x) for x in deltas])
+    p = _abi.OptParams(int(seed), L, len(deltas), dl, int(steps_per_delta), float(radius0), float(radius_min),
+                       float(radius_max), float(eta), float(cg_tol), int(cg_max_iter), float(fd_step))
+    out = torch.empty(2 * int(d) * int(n), dtype=torch.float64, device=device)
+    if workspace is None:
+        need = _abi.lib().trstmi_optimize_workspace_bytes(int(n), int(d))
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    mu = ctypes.c_double()
+    best = ctypes.c_int32()
+    _abi.check(_abi.lib().trstmi_optimize(int(n), int(d), ctypes.byref(p), _ptr(out), ctypes.byref(mu),
+                                          ctypes.byref(best), _ptr(workspace), workspace.numel(), _stream(stream)),
+               "trstmi_optimize")
+    return out, mu.value, best.value
+
+
 def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, stream=None):
     """The normalised FP64 candidates c0..c0+count-1 of step t (flat tensor,
     candidate i at offset i*2*d*n)."""

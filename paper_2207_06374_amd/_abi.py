@@ -109,6 +109,14 @@ class TRParams(ctypes.Structure):
                 ("fd_step", ctypes.c_double)]
 
 
+class OptParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("restarts", ctypes.c_int32), ("n_deltas", ctypes.c_int32),
+                ("deltas", ctypes.POINTER(ctypes.c_double)), ("steps_per_delta", ctypes.c_int32),
+                ("radius0", ctypes.c_double), ("radius_min", ctypes.c_double), ("radius_max", ctypes.c_double),
+                ("eta", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
+                ("fd_step", ctypes.c_double)]
+
+
 class TRReport(ctypes.Structure):
     _fields_ = [("f_old", ctypes.c_double), ("f_new", ctypes.c_double), ("rho", ctypes.c_double),
                 ("step_norm", ctypes.c_double), ("new_radius", ctypes.c_double), ("cg_iters", ctypes.c_int32),
@@ -127,6 +135,8 @@ SIGNATURES = {
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_tr_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_tr_step": (_i32, [_i64, _i64, _vp, _P(TRParams), _P(TRReport), _vp, _sz, _vp]),
+    "trstmi_optimize_workspace_bytes": (_sz, [_i64, _i64]),
+    "trstmi_optimize": (_i32, [_i64, _i64, _P(OptParams), _vp, _P(ctypes.c_double), _P(_i32), _vp, _sz, _vp]),
     "trstmi_init_haar": (_i32, [_P(Params), _P(State), _vp, _sz, _vp]),
     "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),

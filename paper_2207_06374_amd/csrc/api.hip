@@ -753,6 +753,85 @@ trstmi_status trstmi_tr_step(int64_t n, int64_t d, double* frame, const trstmi_t
   return st;
 }
 
+size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d) {
+  const size_t t = trstmi_tr_workspace_bytes(n, d);
+  if (!t) return 0;
+  return align256(t) + align256((size_t)2 * d * n * 8) + align256(trstmi_coherence_workspace_bytes(n, d, 0)) + 256;
+}
+
+trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op, double* best_frame, double* best_mu,
+                              int32_t* best_restart, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (d > 64) return fail(TRSTMI_E_UNSUPPORTED, "the optimiser supports d <= 64");
+  if (!op || !best_mu || !best_restart) return fail(TRSTMI_E_INVALID_ARG, "params, best_mu and best_restart are host pointers");
+  auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
+  bool ok = op->restarts >= 1 && op->n_deltas >= 1 && op->deltas && op->steps_per_delta >= 1 && pos(op->radius0) &&
+            op->radius_min >= 0.0 && op->radius_max >= op->radius0 && std::isfinite(op->radius_max) &&
+            op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) && op->cg_max_iter >= 0 && pos(op->fd_step);
+  for (int32_t k = 0; ok && k < op->n_deltas; ++k) ok = pos(op->deltas[k]);
+  if (!ok) return fail(TRSTMI_E_INVALID_ARG, "invalid optimiser parameters");
+  if (!best_frame || ((uintptr_t)best_frame & 15)) return fail(TRSTMI_E_INVALID_ARG, "best_frame: null or misaligned");
+  const size_t need = trstmi_optimize_workspace_bytes(n, d);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  char* ws = (char*)workspace;
+  const size_t tws = align256(trstmi_tr_workspace_bytes(n, d));
+  const size_t lws = align256(trstmi_lse_grad_workspace_bytes(n, d));
+  double* W = (double*)(ws + tws);
+  char* cws = ws + tws + align256((size_t)2 * d * n * 8);
+  const size_t cws_bytes = trstmi_coherence_workspace_bytes(n, d, 0);
+  double* mu_dev = (double*)(cws + align256(cws_bytes));
+
+  *best_mu = __builtin_inf();
+  *best_restart = -1;
+  for (int32_t l = 0; l < op->restarts; ++l) {
+    PerturbArgs pa{};
+    pa.n = n;
+    pa.d = (int32_t)d;
+    pa.seed = (uint32_t)op->seed;
+    pa.stream_id = (uint32_t)l;
+    pa.have_z = 1;
+    pa.base = nullptr;
+    pa.tag = 1;
+    pa.t_const = 0;
+    pa.c0 = 0;
+    pa.out = W;
+    pa.out_kind = kOutF64;
+    pa.out_ld = (int32_t)(2 * d);
+    pa.out_slot_stride = 2 * d * n;
+    TRY_HIP(launch_perturb(pa, 1, stream), "optimise: random start");
+    for (int32_t k = 0; k < op->n_deltas; ++k) {
+      trstmi_tr_params tp{};
+      tp.delta = op->deltas[k];
+      tp.radius = op->radius0;
+      tp.radius_max = op->radius_max;
+      tp.eta = op->eta;
+      tp.cg_tol = op->cg_tol;
+      tp.cg_max_iter = op->cg_max_iter ? op->cg_max_iter : (int32_t)(2 * d * n);
+      tp.fd_step = op->fd_step;
+      for (int32_t s = 0; s < op->steps_per_delta; ++s) {
+        trstmi_tr_report rep{};
+        st = tr_step_impl(n, d, W, &tp, &rep, ws, lws, stream);
+        if (st == TRSTMI_E_HIP) return fail(TRSTMI_E_HIP, "optimise: a HIP call failed");
+        if (st != TRSTMI_OK) return fail(st, "optimise: trust-region step failed");
+        tp.radius = rep.new_radius;
+        if (tp.radius < op->radius_min || rep.cg_exit == TRSTMI_CG_ZERO_GRADIENT) break;
+      }
+    }
+    if ((st = trstmi_coherence(n, d, TRSTMI_MODE_FP64, W, mu_dev, cws, cws_bytes, stream))) return st;
+    double mu = 0.0;
+    TRY_HIP(hipMemcpyAsync(&mu, mu_dev, sizeof(double), hipMemcpyDeviceToHost, stream), "optimise: read mu");
+    TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+    if (mu < *best_mu) {
+      *best_mu = mu;
+      *best_restart = l;
+      TRY_HIP(hipMemcpyAsync(best_frame, W, (size_t)2 * d * n * 8, hipMemcpyDeviceToDevice, stream), "optimise: copy");
+    }
+  }
+  TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+  return TRSTMI_OK;
+}
+
 trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state, void* workspace,
                                size_t workspace_bytes, hipStream_t stream) {
   trstmi_status st = check_params(p);

@@ -224,3 +224,28 @@ def test_tr_step_argument_checks(L):
         assert L.trstmi_tr_step(100, 8, p, ctypes.byref(bad), ctypes.byref(rep), ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_tr_step(100, 8, p, None, ctypes.byref(rep), ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_tr_step(100, 8, p, ctypes.byref(good), ctypes.byref(rep), ws, need - 1, None) == abi.E_WORKSPACE
+
+
+def test_optimize_argument_checks(L):
+    need = L.trstmi_optimize_workspace_bytes(9, 3)
+    assert need > L.trstmi_tr_workspace_bytes(9, 3)
+    assert L.trstmi_optimize_workspace_bytes(9, 65) == 0
+    dl = (ctypes.c_double * 2)(0.1, 0.01)
+    mu = ctypes.c_double()
+    best = ctypes.c_int32()
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    good = abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6)
+    assert L.trstmi_optimize(9, 65, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
+                             None) == abi.E_UNSUPPORTED
+    bad_dl = (ctypes.c_double * 2)(0.1, -1.0)
+    for bad in (abi.OptParams(0, 0, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6),
+                abi.OptParams(0, 2, 2, bad_dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6),
+                abi.OptParams(0, 2, 2, dl, 0, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6),
+                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 0.01, 0.1, 1e-10, 0, 1e-6)):
+        assert L.trstmi_optimize(9, 3, ctypes.byref(bad), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
+                                 None) == abi.E_INVALID_ARG
+    assert L.trstmi_optimize(9, 3, ctypes.byref(good), p, None, ctypes.byref(best), ws, need,
+                             None) == abi.E_INVALID_ARG
+    assert L.trstmi_optimize(9, 3, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws, need - 1,
+                             None) == abi.E_WORKSPACE

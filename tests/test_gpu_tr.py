@@ -99,3 +99,25 @@ def test_tr_every_cg_exit(n, d, delta, seed, steps, cg_max_iter, want):
     _, r = oracle.tr_step(Y, p)
     assert r.cg_exit == want
     _compare(Y, p, tol=1e-5)
+
+
+def _table2():
+    import os
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table2_trstmi_mu.txt")):
+        if line.strip() and not line.startswith("#"):
+            d, n, mu = line.split()
+            rows[int(d)] = (int(n), float(mu))
+    return rows
+
+
+@pytest.mark.parametrize("d,restarts", [(2, 8), (3, 18)])
+def test_optimize_reaches_table2(d, restarts):
+    """Alg. 2 on the GPU reaches the printed Table II coherence at N = d^2
+    (the Welch bound there, so optimal)."""
+    n, printed = _table2()[d]
+    frame, mu, l = lib.optimize(n, d, restarts=restarts)
+    print(f"d={d} n={n} mu={mu!r} restart={l} printed={printed}", flush=True)
+    assert oracle.welch_bound(n, d) - 1e-12 <= mu <= printed
+    F = lib.frame_from_device(frame, n, d)
+    assert abs(oracle.coherence(F) - mu) <= 1e-12
