@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -242,6 +243,29 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     }
 
 
+def run_table2(lib, dims):
+    """The paper's optimiser (Alg. 2: delta continuation, L = 2 d^2 random
+    restarts, trust-region steps) at N = d^2: the coherence reached and the
+    wall time, beside the values Table II prints (upper bounds, rounded up
+    at the fourth decimal)."""
+    import os
+    printed = {}
+    for line in open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                  "table2_trstmi_mu.txt")):
+        if line.strip() and not line.startswith("#"):
+            d, n, mu = line.split()
+            printed[int(d)] = float(mu)
+    rows = []
+    for d in dims:
+        n = d * d
+        t0 = time.perf_counter()
+        _, mu, best = lib.optimize(n, d)
+        rows.append({"d": d, "n": n, "restarts": 2 * d * d, "mu": mu, "printed_mu": printed.get(d),
+                     "welch": math.sqrt((n - d) / (d * (n - 1))), "seconds": time.perf_counter() - t0})
+        log(f"table II d={d}: mu={mu:.10f} in {rows[-1]['seconds']:.1f} s")
+    return rows
+
+
 def run_serving(lib, count, max_steps, pool_gib):
     """The serving workload: Poisson arrivals (mean gap 5 ms), d in
     {8, 16, 32, 64, 128}, N uniform in [2d, 8d], each solved to 1.10 x Welch or
@@ -317,6 +341,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--table2-dims", default="2,3,4",
+                    help="dimensions d for the optimiser at N = d^2 (Table II comparison; empty: skip)")
     ap.add_argument("--smooth-max-evals", type=int, default=10,
                     help="evaluations of the section IV smooth maximum at the throughput shape (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16, help="requests of the serving run (0: skip)")
@@ -353,6 +379,7 @@ def main():
         others[m]["gram_avg_us"] = r["gram"]["avg_us"]
 
     smooth = run_smooth_max(lib, torch, wl, args.smooth_max_evals) if args.smooth_max_evals > 0 else None
+    table2 = run_table2(lib, [int(x) for x in args.table2_dims.split(",") if x]) if args.table2_dims else None
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
     serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib)
@@ -397,6 +424,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "smooth_max": smooth,
+        "optimiser_table2": table2,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
