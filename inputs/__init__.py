@@ -14,6 +14,8 @@ paper runs on random unit vectors only and uses no dataset):
   workload; bfloat16 screen with the top 8 re-evaluated in FP64);
 * ``batched_instances``  512 independent (d, N) with d uniform in {3..16} and
   N uniform in [d+1, d^2], 64 candidates each;
+* ``miso_channels``      CN(0, I_d) channel vectors for the codebook
+  evaluation of §III;
 * ``serving_requests``   Poisson arrivals (mean gap 5 ms), d in
   {8, 16, 32, 64, 128}, N uniform in [2d, 8d].
 """
@@ -85,3 +87,10 @@ def serving_requests(count, seed=1, mean_gap_s=0.005, dims=(8, 16, 32, 64, 128))
         n = int(rng.integers(2 * d, 8 * d + 1))
         out.append({"id": i, "arrival": t, "d": d, "n": n, "seed": i})
     return out
+
+
+def miso_channels(m, d, seed):
+    """``m`` channel vectors of the MISO model (§III): a (d, m) complex128
+    array whose entries are i.i.d. CN(0, 1) (real and imaginary parts
+    N(0, 1/2))."""
+    return random_frame(m, d, seed, scale_spread=False)

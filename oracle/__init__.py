@@ -14,6 +14,8 @@ tuning for matrix incoherence", arXiv:2207.06374):
   orthoplex / Levenshtein bounds (§V, Proposition on orthoplex and
   Levenshtein bounds), column normalisation (§IV, remark on dividing each
   column by its norm).
+* ``miso``       -- the beamforming-codebook quantiser of §III (argmax of
+  |<phi_i, h>|^2 over the codewords) and its Monte-Carlo distortion.
 * ``philox``     -- Philox4x32-10 counter-based generator, from its published
   definition (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
   as 1, 2, 3", SC'11).  The paper does not fix a generator; see ``rng``.
@@ -46,6 +48,7 @@ from .coherence import (  # noqa: F401
     levenshtein_bound,
     lower_bound,
 )
+from .miso import quantize, distortion  # noqa: F401
 from .philox import philox4x32_10  # noqa: F401
 from .rng import (  # noqa: F401
     TAG_PERTURB,
