@@ -33,21 +33,31 @@ def quantize(codebook, H):
     gain[m]  = that maximum (the SNR in units of E_s / sigma),
     dist[m]  = d_c^2(h_m / |h_m|, phi_index) = 1 - gain[m] / |h_m|^2.
     A codeword of zero or non-finite norm makes the codebook invalid: every
-    index is -1 and every gain and distance NaN.
+    index is -1 and every gain and distance NaN.  A channel whose squared
+    norm is not finite (a non-finite entry, or overflow) gets index -1 and
+    NaN gain and distance; a zero channel has gain 0 at index 0 and a NaN
+    distance (its line is undefined).  The paper draws channels from a
+    Gaussian and fixes none of these cases.
     """
     H = np.asarray(H, dtype=np.complex128)
     M = H.shape[1]
     Phi, norms = normalize_columns(codebook)
     if not np.all(np.isfinite(norms) & (norms > 0.0)):
         return np.full(M, -1, dtype=np.int32), np.full(M, np.nan), np.full(M, np.nan)
-    G = Phi.conj().T @ H                      # G[i, m] = <phi_i, h_m>
-    P = G.real * G.real + G.imag * G.imag     # |<phi_i, h_m>|^2
-    index = np.argmax(P, axis=0)              # numpy returns the first maximum
+    with np.errstate(over="ignore", invalid="ignore"):
+        G = Phi.conj().T @ H                      # G[i, m] = <phi_i, h_m>
+        P = G.real * G.real + G.imag * G.imag     # |<phi_i, h_m>|^2
+        h2 = np.sum(H.real * H.real + H.imag * H.imag, axis=0)
+    bad = ~np.isfinite(h2)
+    P[:, bad] = 0.0
+    index = np.argmax(P, axis=0).astype(np.int32)   # numpy returns the first maximum
     gain = P[index, np.arange(M)]
-    h2 = np.sum(H.real * H.real + H.imag * H.imag, axis=0)
     with np.errstate(invalid="ignore", divide="ignore"):
         dist = 1.0 - gain / h2
-    return index.astype(np.int32), gain, dist
+    index[bad] = -1
+    gain[bad] = np.nan
+    dist[bad] = np.nan
+    return index, gain, dist
 
 
 def distortion(codebook, H):

@@ -157,7 +157,18 @@ def test_invalid_codeword_and_zero_channel():
     H = inputs.miso_channels(3, 3, seed=1)
     H[:, 1] = 0
     index, gain, dist = oracle.quantize(C, H)
-    assert gain[1] == 0 and np.isnan(dist[1]) and np.isfinite(dist[[0, 2]]).all()
+    assert index[1] == 0 and gain[1] == 0 and np.isnan(dist[1]) and np.isfinite(dist[[0, 2]]).all()
+    ref_i, ref_g, ref_d = index.copy(), gain.copy(), dist.copy()
+    H[1, 0] = np.inf
+    H[0, 2] = np.nan
+    H[:, 1] = 1e200                      # finite entries whose squared norm overflows
+    index, gain, dist = oracle.quantize(C, H)
+    assert np.all(index == -1) and np.all(np.isnan(gain)) and np.all(np.isnan(dist))
+    H = inputs.miso_channels(3, 3, seed=1)
+    H[2, 1] = -np.inf
+    index, gain, dist = oracle.quantize(C, H)
+    assert index[1] == -1 and np.isnan(gain[1]) and np.isnan(dist[1])
+    assert np.array_equal(index[[0, 2]], ref_i[[0, 2]]) and np.array_equal(gain[[0, 2]], ref_g[[0, 2]])
 
 
 def test_distortion_falls_with_better_packings():
