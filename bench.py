@@ -243,6 +243,45 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     }
 
 
+def run_miso(lib, torch, n, d, m, evals):
+    """The beamforming-codebook evaluation of section III: m CN(0, I_d)
+    channels quantised with an n-word codebook (normalise the codebook, FP64
+    MFMA products with a fused argmax, fixed-order means of the squared
+    chordal distance and the gain)."""
+    import inputs
+    C = lib.frame_to_device(inputs.random_frame(n, d, seed=1, scale_spread=False))
+    H = lib.frame_to_device(inputs.miso_channels(m, d, seed=2))
+    index = torch.empty(m, dtype=torch.int32, device=C.device)
+    gain = torch.empty(m, dtype=torch.float64, device=C.device)
+    dist = torch.empty(m, dtype=torch.float64, device=C.device)
+    summary = torch.empty(2, dtype=torch.float64, device=C.device)
+    ws = torch.empty(lib.miso_workspace_bytes(n, d, m), dtype=torch.uint8, device=C.device)
+
+    def call():
+        lib.miso_quantize_into(C, n, d, H, m, index, gain, dist, summary, ws)
+
+    for _ in range(2):
+        call()
+    torch.cuda.synchronize()
+    lib.timing_reset()
+    lib.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        call()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.timing_enable(False)
+    ms, cnt = lib.timing_read("miso")
+    us = 1e3 * ms / cnt
+    flops = 8 * d * n * m                    # Re and Im of every <phi_i, h_j>: 2 x 2d multiply-adds
+    D, g = summary.cpu().numpy().tolist()
+    return {"workload": f"{m} CN(0, I_{d}) channels, codebook of {n} unit vectors in C^{d}, FP64",
+            "ms_per_eval": 1e3 * (t1 - t0) / evals, "channels_per_s": m * evals / (t1 - t0),
+            "kernel_us": us, "tflops": flops / (us * 1e-6) / 1e12,
+            "frac_fp64_peak": flops / (us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+            "distortion": D, "mean_gain": g}
+
+
 def run_table2(lib, dims):
     """The paper's optimiser (Alg. 2: delta continuation, L = 2 d^2 random
     restarts, trust-region steps) at N = d^2: the coherence reached and the
@@ -341,6 +380,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--miso-evals", type=int, default=10,
+                    help="codebook quantiser calls to time (4096 codewords, d = 64, 65536 channels; 0: skip)")
     ap.add_argument("--table2-dims", default="2,3,4",
                     help="dimensions d for the optimiser at N = d^2 (Table II comparison; empty: skip)")
     ap.add_argument("--smooth-max-evals", type=int, default=10,
@@ -379,6 +420,7 @@ def main():
         others[m]["gram_avg_us"] = r["gram"]["avg_us"]
 
     smooth = run_smooth_max(lib, torch, wl, args.smooth_max_evals) if args.smooth_max_evals > 0 else None
+    miso = run_miso(lib, torch, 4096, 64, 65536, args.miso_evals) if args.miso_evals > 0 else None
     table2 = run_table2(lib, [int(x) for x in args.table2_dims.split(",") if x]) if args.table2_dims else None
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
@@ -425,6 +467,7 @@ def main():
         "serving": serving,
         "smooth_max": smooth,
         "optimiser_table2": table2,
+        "miso_codebook": miso,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

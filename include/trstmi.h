@@ -283,6 +283,34 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* par
                               double* best_mu, int32_t* best_restart, void* workspace,
                               size_t workspace_bytes, hipStream_t stream);
 
+/* Bytes of workspace trstmi_miso_quantize needs (0 if a size is invalid). */
+size_t trstmi_miso_workspace_bytes(int64_t n, int64_t d, int64_t m);
+
+/*
+ * Beamforming-codebook quantiser of section III (the MISO application): the
+ * codebook is n codewords phi_i (columns, normalised here as section III
+ * takes unit codewords), the channels are m vectors h_j in C^d; both in the
+ * frame layout (device, column j at offset 2*d*j as interleaved re, im).
+ * For every channel, written where the pointer is not NULL (device):
+ *   index[j] = argmax_i |<phi_i, h_j>|^2 (the first of equal maxima),
+ *   gain[j]  = that maximum (the received SNR in units of E_s / sigma),
+ *   dist[j]  = 1 - gain[j] / |h_j|^2 (squared chordal distance from the line
+ *              of h_j to its codeword, section II),
+ * and summary[0..1] = the means of dist and gain over the m channels (a
+ * Monte-Carlo estimate of the codebook's distortion and mean SNR gain when
+ * the channels are CN(0, I_d) draws), added in a fixed order (NaN if m = 0).
+ * <phi, h> = sum conj(phi_k) h_k, computed in FP64.  A codeword of zero or
+ * non-finite norm gives index -1 and NaN gain and dist for every channel; a
+ * channel whose squared norm is not finite gives -1 and NaN for that
+ * channel; a zero channel has gain 0 at index 0 and a NaN dist.
+ * Stream-ordered.  1 <= n <= 262144, 1 <= d <= 512, 0 <= m < 2^31;
+ * codebook and channels 16-byte aligned; the workspace (device, 256-byte
+ * aligned) holds the normalised codebook and the block sums.
+ */
+trstmi_status trstmi_miso_quantize(const double* codebook, int64_t n, int64_t d, const double* channels, int64_t m,
+                                   int32_t* index, double* gain, double* dist, double* summary, void* workspace,
+                                   size_t workspace_bytes, hipStream_t stream);
+
 /*
  * Random start (Alg. 2 step 1): state->frame <- N normalised CN(0, I_d)
  * columns drawn with tag 1 (candidate 0, step 0); *mu <- its coherence

@@ -189,6 +189,39 @@ def optimize(n, d, restarts=None, deltas=(1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e
     return out, mu.value, best.value
 
 
+def miso_workspace_bytes(n, d, m):
+    return _abi.lib().trstmi_miso_workspace_bytes(int(n), int(d), int(m))
+
+
+def miso_quantize_into(codebook, n, d, channels, m, index, gain, dist, summary, workspace, stream=None):
+    """trstmi_miso_quantize into caller buffers (any output may be None)."""
+    _abi.check(_abi.lib().trstmi_miso_quantize(_ptr(codebook), int(n), int(d), _ptr(channels), int(m), _ptr(index),
+                                               _ptr(gain), _ptr(dist), _ptr(summary), _ptr(workspace),
+                                               0 if workspace is None else workspace.numel(), _stream(stream)),
+               "trstmi_miso_quantize")
+
+
+def miso_quantize(codebook, n, d, channels, m, per_channel=True, workspace=None, stream=None):
+    """Quantise m channels (device, frame layout) with an n-word codebook
+    (section III).  Returns (index int32, gain, dist) device tensors of
+    length m (None unless per_channel) and a 2-element device tensor
+    (mean dist, mean gain)."""
+    torch = _torch()
+    dev = codebook.device
+    index = gain = dist = None
+    if per_channel:
+        index = torch.empty(max(int(m), 1), dtype=torch.int32, device=dev)
+        gain = torch.empty(max(int(m), 1), dtype=torch.float64, device=dev)
+        dist = torch.empty(max(int(m), 1), dtype=torch.float64, device=dev)
+    summary = torch.empty(2, dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(max(miso_workspace_bytes(n, d, m), 1), dtype=torch.uint8, device=dev)
+    miso_quantize_into(codebook, n, d, channels, m, index, gain, dist, summary, workspace, stream)
+    if per_channel:
+        index, gain, dist = index[:m], gain[:m], dist[:m]
+    return index, gain, dist, summary
+
+
 def candidates(params, frame, radius, t, c0, count, explicit_z=None, out=None, stream=None):
     """The normalised FP64 candidates c0..c0+count-1 of step t (flat tensor,
     candidate i at offset i*2*d*n)."""

@@ -137,6 +137,8 @@ SIGNATURES = {
     "trstmi_tr_step": (_i32, [_i64, _i64, _vp, _P(TRParams), _P(TRReport), _vp, _sz, _vp]),
     "trstmi_optimize_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_optimize": (_i32, [_i64, _i64, _P(OptParams), _vp, _P(ctypes.c_double), _P(_i32), _vp, _sz, _vp]),
+    "trstmi_miso_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "trstmi_miso_quantize": (_i32, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_init_haar": (_i32, [_P(Params), _P(State), _vp, _sz, _vp]),
     "trstmi_candidates": (_i32, [_P(Params), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "trstmi_step": (_i32, [_P(Params), _P(State), _vp, _sz, _vp, _P(Report), _vp]),

@@ -129,6 +129,7 @@ trstmi_status drain_timing() {
 }
 
 constexpr int64_t kMaxN = 1 << 18;
+constexpr int64_t kMaxChannels = 2147483647;  // channels per quantiser call (int32 indices)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -665,6 +666,52 @@ trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta
   return TRSTMI_OK;
 }
 
+size_t trstmi_miso_workspace_bytes(int64_t n, int64_t d, int64_t m) {
+  if (n < 1 || n > kMaxN || d < 1 || d > TRSTMI_MAX_D || m < 0 || m > kMaxChannels) return 0;
+  return align256((size_t)n * ld_of(d) * 8) + align256((size_t)(miso_blocks(m) > 0 ? miso_blocks(m) : 1) * 16);
+}
+
+trstmi_status trstmi_miso_quantize(const double* codebook, int64_t n, int64_t d, const double* channels, int64_t m,
+                                   int32_t* index, double* gain, double* dist, double* summary, void* workspace,
+                                   size_t workspace_bytes, hipStream_t stream) {
+  if (n < 1 || n > kMaxN) return fail(TRSTMI_E_INVALID_ARG, "n must be in [1, 262144]");
+  if (d < 1 || d > TRSTMI_MAX_D) return fail(TRSTMI_E_INVALID_ARG, "d must be in [1, 512]");
+  if (m < 0 || m > kMaxChannels) return fail(TRSTMI_E_INVALID_ARG, "m must be in [0, 2^31 - 1]");
+  if (!codebook) return fail(TRSTMI_E_INVALID_ARG, "codebook must be a device pointer");
+  if (m > 0 && !channels) return fail(TRSTMI_E_INVALID_ARG, "channels must be a device pointer");
+  if (((uintptr_t)codebook & 15) || ((uintptr_t)channels & 15) || ((uintptr_t)index & 3) ||
+      ((uintptr_t)gain & 7) || ((uintptr_t)dist & 7) || ((uintptr_t)summary & 7))
+    return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_miso_workspace_bytes(n, d, m);
+  trstmi_status st = check_ws(workspace, workspace_bytes, need);
+  if (st) return st;
+  char* ws = (char*)workspace;
+  const int32_t ld = ld_of(d);
+  PerturbArgs pa{};
+  pa.base = codebook;
+  pa.have_z = 0;
+  pa.n = n;
+  pa.d = (int32_t)d;
+  pa.out = ws;
+  pa.out_kind = kOutF64;
+  pa.out_ld = ld;
+  pa.out_slot_stride = n * ld;
+  TRY_HIP(launch_perturb(pa, 1, stream), "normalise codebook");
+  MisoArgs a{};
+  a.codebook = (const double*)ws;
+  a.ldk = ld;
+  a.n = (int32_t)n;
+  a.d = (int32_t)d;
+  a.channels = channels;
+  a.m = m;
+  a.index = index;
+  a.gain = gain;
+  a.dist = dist;
+  a.partial = (double*)(ws + align256((size_t)n * ld * 8));
+  TRY_HIP(TIMED("miso", stream, launch_miso(a, summary, stream)), "miso_quantize");
+  return TRSTMI_OK;
+}
+
 size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d) {
   if (check_size(n, d) || d > 64) return 0;
   const int64_t nkb = (n + kTileF64 - 1) / kTileF64;
@@ -1148,6 +1195,6 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
-int32_t trstmi_abi_version(void) { return 4; }
+int32_t trstmi_abi_version(void) { return 5; }
 
 }  // extern "C"

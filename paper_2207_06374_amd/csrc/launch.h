@@ -187,6 +187,22 @@ struct GradArgs {
 int lse_grad_chunks(int nkb);
 hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s);
 
+// Beamforming-codebook quantiser (miso.hip).
+struct MisoArgs {
+  const double* codebook;   // normalised codewords (column stride ldk, zero padded)
+  int32_t ldk;
+  int32_t n, d;
+  const double* channels;   // the caller's channels (column stride 2d)
+  int64_t m;
+  int32_t* index;           // [m] argmax codeword, -1 if undefined (null: not written)
+  double* gain;             // [m] max |<phi_i, h>|^2 (null: not written)
+  double* dist;             // [m] 1 - gain / |h|^2 (null: not written)
+  double* partial;          // [blocks][2] block sums of dist and gain (null: not kept)
+};
+int64_t miso_blocks(int64_t m);
+// The quantiser, then (if summary is not null) summary = (mean dist, mean gain).
+hipError_t launch_miso(const MisoArgs& a, double* summary, hipStream_t s);
+
 // Trust-region step (trust_region.hip): the vectors' workspace bytes, and the
 // step itself given a trstmi_lse_grad workspace of lws_bytes at ws.
 size_t tr_vectors_bytes(int64_t n, int64_t d);

@@ -1,0 +1,240 @@
+// Beamforming-codebook quantiser of section III on v_mfma_f64_16x16x4_f64.
+//
+// For channels h_m (columns of H, d x M) and unit codewords phi_i (the
+// normalised codebook, d x N): index_m = argmax_i |<phi_i, h_m>|^2 (the first
+// of equal maxima), gain_m = that maximum, dist_m = 1 - gain_m / |h_m|^2 (the
+// squared chordal distance from the line of h_m to its codeword).
+//
+// With phi = a + i b stored as u = (a_0, b_0, a_1, b_1, ...) and, for a
+// channel, v = (b_0, -a_0, ...): Re <phi, h> = u_phi . u_h and
+// Im <phi, h> = u_phi . v_h, so one tile of Phi^* H is two real products
+// with K = 2d sharing the codeword operand.  A block owns 64 channels and
+// walks every 64-codeword tile in the same order as all other blocks (so a
+// codeword tile is read from L2 by the whole grid at about the same time);
+// each wave computes a 32 x 32 quadrant (codewords x channels) and keeps,
+// per lane and channel column, the running maximum and its index.  Within a
+// lane the codeword index only grows, so a strict comparison keeps the
+// first of equal maxima; the final reduction across lanes and waves breaks
+// ties by the lower index.  |h|^2 is summed from the channel chunks while
+// the first codeword tile is computed.  Per-block sums of dist and gain go
+// to fixed slots and one block adds them in a fixed order, so the means do
+// not depend on scheduling.
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace trstmi {
+
+namespace {
+
+constexpr int T = 64;        // codewords and channels per block tile
+constexpr int KC = 32;       // K chunk staged through LDS
+constexpr int LDA = KC + 1;  // padded LDS column
+
+__global__ __launch_bounds__(256) void k_miso_quantize(MisoArgs a) {
+  __shared__ double As[T * LDA];
+  __shared__ double Bs[T * LDA];
+  __shared__ double h2s[T];
+  __shared__ double redg[8][T];
+  __shared__ int32_t redi[8][T];
+  __shared__ int32_t redn[8][T];
+  __shared__ double sums[2][4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int K = 2 * a.d;
+  const int64_t j0 = (int64_t)blockIdx.x * T;
+  const int ntile = (a.n + T - 1) / T;
+
+  double best[2] = {-1.0, -1.0};
+  int32_t bidx[2] = {0, 0};
+  bool nan[2] = {false, false};
+  double h2 = 0.0;
+
+  for (int bi = 0; bi < ntile; ++bi) {
+    v4f64 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        accR[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
+        accI[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
+      }
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < (T * KC / 2) / 256; ++it) {
+        const int idx = it * 256 + tid;
+        const int col = idx / (KC / 2);
+        const int m = idx % (KC / 2);
+        const int k = k0 + 2 * m;
+        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+        const int ci = bi * T + col;
+        const int64_t cj = j0 + col;
+        if (k < K) {
+          if (ci < a.n) va = *(const double2*)(a.codebook + (size_t)ci * a.ldk + k);
+          if (cj < a.m) vb = *(const double2*)(a.channels + (size_t)cj * K + k);
+        }
+        As[col * LDA + 2 * m] = va.x;
+        As[col * LDA + 2 * m + 1] = va.y;
+        Bs[col * LDA + 2 * m] = vb.x;
+        Bs[col * LDA + 2 * m + 1] = vb.y;
+      }
+      __syncthreads();
+      const int kn = K - k0 < KC ? K - k0 : KC;
+      if (bi == 0 && tid < T) {
+        for (int k = 0; k < kn; ++k) {
+          const double x = Bs[tid * LDA + k];
+          h2 = fma(x, x, h2);
+        }
+      }
+      const int ksteps = (kn + 3) / 4;
+      const int kl = lane >> 4;
+      const bool odd = kl & 1;
+      for (int kk = 0; kk < ksteps; ++kk) {
+        const int k = kk * 4 + kl;
+        double av[2], bu[2], bv[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) av[r] = As[(wr * 32 + r * 16 + (lane & 15)) * LDA + k];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int cc = (wc * 32 + c * 16 + (lane & 15)) * LDA;
+          bu[c] = Bs[cc + k];
+          const double x = Bs[cc + (k ^ 1)];
+          bv[c] = odd ? -x : x;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bu[c], accR[r][c], 0, 0, 0);
+            accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], accI[r][c], 0, 0, 0);
+          }
+      }
+    }
+    // output register v of lane l: codeword row 4 v + l / 16, channel column l % 16
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = bi * T + wr * 32 + r * 16 + 4 * v + (lane >> 4);
+        if (i < a.n) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const double re = accR[r][c][v], im = accI[r][c][v];
+            const double g = re * re + im * im;
+            if (g > best[c]) {
+              best[c] = g;
+              bidx[c] = i;
+            }
+            nan[c] |= (g != g);
+          }
+        }
+      }
+  }
+
+  // candidates per channel column: 4 lane groups x 2 waves (wr)
+  const int slot = wr * 4 + (lane >> 4);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int col = wc * 32 + c * 16 + (lane & 15);
+    redg[slot][col] = best[c];
+    redi[slot][col] = bidx[c];
+    redn[slot][col] = nan[c] ? 1 : 0;
+  }
+  if (tid < T) h2s[tid] = h2;
+  __syncthreads();
+  double dist = 0.0, gain = 0.0;
+  if (tid < T) {
+    double g = redg[0][tid];
+    int32_t gi = redi[0][tid];
+    int32_t bad = redn[0][tid];
+    for (int q = 1; q < 8; ++q) {
+      const double x = redg[q][tid];
+      const int32_t xi = redi[q][tid];
+      if (x > g || (x == g && xi < gi)) {
+        g = x;
+        gi = xi;
+      }
+      bad |= redn[q][tid];
+    }
+    const int64_t j = j0 + tid;
+    const double hh = h2s[tid];
+    const bool finite_h = hh - hh == 0.0;
+    if (bad || !finite_h) {
+      gi = -1;
+      g = __longlong_as_double(0x7FF8000000000000LL);
+      dist = g;
+    } else {
+      dist = 1.0 - g / hh;
+    }
+    gain = g;
+    if (j < a.m) {
+      if (a.index) a.index[j] = gi;
+      if (a.gain) a.gain[j] = g;
+      if (a.dist) a.dist[j] = dist;
+    } else {
+      dist = 0.0;
+      gain = 0.0;
+    }
+  }
+  if (a.partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      dist += __shfl_xor(dist, off, 64);
+      gain += __shfl_xor(gain, off, 64);
+    }
+    if (tid == 0) {
+      a.partial[2 * blockIdx.x] = dist;
+      a.partial[2 * blockIdx.x + 1] = gain;
+    }
+  }
+}
+
+// summary = (sum of dist, sum of gain) / m over the block slots, added in a
+// fixed order: thread t takes slots t, t + 256, ... in turn, then a fixed
+// pairwise tree.
+__global__ __launch_bounds__(256) void k_miso_finish(const double* partial, int64_t count, int64_t m,
+                                                     double* summary) {
+  __shared__ double acc[2][256];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) {
+    s0 += partial[2 * i];
+    s1 += partial[2 * i + 1];
+  }
+  acc[0][threadIdx.x] = s0;
+  acc[1][threadIdx.x] = s1;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      acc[0][threadIdx.x] += acc[0][threadIdx.x + h];
+      acc[1][threadIdx.x] += acc[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nan = __longlong_as_double(0x7FF8000000000000LL);
+    summary[0] = m > 0 ? acc[0][0] / (double)m : nan;
+    summary[1] = m > 0 ? acc[1][0] / (double)m : nan;
+  }
+}
+
+}  // namespace
+
+int64_t miso_blocks(int64_t m) { return (m + T - 1) / T; }
+
+hipError_t launch_miso(const MisoArgs& a, double* summary, hipStream_t s) {
+  const int64_t blocks = miso_blocks(a.m);
+  if (blocks > 0) hipLaunchKernelGGL(k_miso_quantize, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (summary) {
+    hipLaunchKernelGGL(k_miso_finish, dim3(1), dim3(256), 0, s, a.partial, blocks, a.m, summary);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace trstmi

@@ -249,3 +249,33 @@ def test_optimize_argument_checks(L):
                              None) == abi.E_INVALID_ARG
     assert L.trstmi_optimize(9, 3, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws, need - 1,
                              None) == abi.E_WORKSPACE
+
+
+def test_miso_argument_checks(L):
+    """The codebook quantiser rejects bad arguments before any launch."""
+    need = L.trstmi_miso_workspace_bytes(100, 8, 1000)
+    assert need >= 100 * 16 * 8 + 16 * 16
+    assert L.trstmi_miso_workspace_bytes(0, 8, 10) == 0 and L.trstmi_miso_workspace_bytes(10, 0, 10) == 0
+    assert L.trstmi_miso_workspace_bytes(10, 8, -1) == 0 and L.trstmi_miso_workspace_bytes(10, 513, 10) == 0
+    assert L.trstmi_miso_workspace_bytes(1, 1, 0) > 0
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    args = lambda **k: dict(dict(cb=p, n=100, d=8, ch=p, m=1000, idx=p, g=p, dist=p, s=p, ws=ws, wsb=need), **k)
+
+    def call(**k):
+        a = args(**k)
+        return L.trstmi_miso_quantize(a["cb"], a["n"], a["d"], a["ch"], a["m"], a["idx"], a["g"], a["dist"], a["s"],
+                                      a["ws"], a["wsb"], None)
+
+    assert call(n=0) == abi.E_INVALID_ARG
+    assert call(n=(1 << 18) + 1) == abi.E_INVALID_ARG
+    assert call(d=0) == abi.E_INVALID_ARG and call(d=513) == abi.E_INVALID_ARG
+    assert call(m=-1) == abi.E_INVALID_ARG and call(m=1 << 31) == abi.E_INVALID_ARG
+    assert call(cb=None) == abi.E_INVALID_ARG
+    assert call(ch=None) == abi.E_INVALID_ARG
+    assert call(ch=ctypes.c_void_p(4104)) == abi.E_INVALID_ARG
+    assert call(idx=ctypes.c_void_p(4098)) == abi.E_INVALID_ARG
+    assert call(s=ctypes.c_void_p(4100)) == abi.E_INVALID_ARG
+    assert call(wsb=need - 1) == abi.E_WORKSPACE
+    assert call(ws=None) == abi.E_WORKSPACE
+    assert L.trstmi_abi_version() >= 5

@@ -1,0 +1,154 @@
+"""GPU parity: the §III codebook quantiser (trstmi_miso_quantize) against the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2207_06374_amd")
+
+# FP64 products of K = 2d <= 1024 terms and a normalisation: |error| of a gain
+# is a few K u |h|^2 (u = 2^-53), far below this.
+TOL = 1e-12
+
+
+def _run(C, H, per_channel=True):
+    d, n = C.shape
+    m = H.shape[1]
+    ch = lib.frame_to_device(H) if m else torch.zeros(2, dtype=torch.float64, device="cuda")
+    index, gain, dist, summary = lib.miso_quantize(lib.frame_to_device(C), n, d, ch, m, per_channel=per_channel)
+    torch.cuda.synchronize()
+    out = [None if t is None else t.cpu().numpy() for t in (index, gain, dist)]
+    return out[0], out[1], out[2], summary.cpu().numpy()
+
+
+def _check_channels(C, H, idx, gain, dist, cols=None):
+    """Per channel: the same index unless the oracle's two best gains are
+    within TOL |h|^2 (then the GPU's choice must be one of those), gain and
+    dist within TOL."""
+    cols = np.arange(H.shape[1]) if cols is None else cols
+    ri, rg, rd = oracle.quantize(C, H[:, cols])
+    Phi, _ = oracle.normalize_columns(C)
+    h2 = np.sum(np.abs(H[:, cols]) ** 2, axis=0)
+    P = np.abs(Phi.conj().T @ H[:, cols]) ** 2
+    for q, j in enumerate(cols):
+        if idx[j] != ri[q]:
+            top = np.sort(P[:, q])[-2:]
+            assert top[1] - top[0] <= TOL * h2[q], (j, idx[j], ri[q])
+            assert abs(P[idx[j], q] - rg[q]) <= TOL * h2[q]
+        assert abs(gain[j] - rg[q]) <= TOL * h2[q], (j, gain[j], rg[q])
+        assert abs(dist[j] - rd[q]) <= TOL, (j, dist[j], rd[q])
+
+
+SHAPES = [(1, 4, 100), (2, 1, 65), (16, 4, 1000), (64, 8, 777), (100, 7, 130), (200, 33, 300), (65, 16, 64),
+          (300, 128, 70), (17, 512, 65), (1000, 3, 2049), (4096, 64, 200)]
+
+
+@pytest.mark.parametrize("n,d,m", SHAPES)
+def test_miso_matches_oracle(n, d, m):
+    C = inputs.random_frame(n, d, seed=n + 3 * d)
+    H = inputs.miso_channels(m, d, seed=m + d)
+    print(f"n={n} d={d} m={m}", flush=True)
+    idx, gain, dist, summary = _run(C, H)
+    _check_channels(C, H, idx, gain, dist)
+    D, g = oracle.distortion(C, H)
+    assert abs(summary[0] - D) <= TOL and abs(summary[1] - g) <= TOL * d
+    # the summary is the mean of the per-channel values
+    assert abs(summary[0] - np.mean(dist)) <= 1e-13 and abs(summary[1] - np.mean(gain)) <= 1e-13 * d
+
+
+def test_miso_full_size_sampled():
+    """The benchmark's shape: 4096 codewords in C^64, 65536 channels; 512
+    sampled channels against the oracle one by one, the summary against the
+    per-channel values."""
+    n, d, m = 4096, 64, 65536
+    C = inputs.random_frame(n, d, seed=1)
+    H = inputs.miso_channels(m, d, seed=2)
+    idx, gain, dist, summary = _run(C, H)
+    cols = np.sort(np.random.default_rng(0).choice(m, 512, replace=False))
+    cols[-1] = m - 1
+    _check_channels(C, H, idx, gain, dist, cols)
+    assert abs(summary[0] - np.mean(dist)) <= 1e-13 and abs(summary[1] - np.mean(gain)) <= 1e-12
+    assert 0.0 < summary[0] < 1.0 - 1.0 / d
+
+
+def test_miso_summary_only():
+    C = inputs.random_frame(300, 16, seed=4)
+    H = inputs.miso_channels(5000, 16, seed=5)
+    _, _, _, s_full = _run(C, H)
+    _, _, _, s_only = _run(C, H, per_channel=False)
+    assert s_full[0] == s_only[0] and s_full[1] == s_only[1]
+    D, g = oracle.distortion(C, H)
+    assert abs(s_only[0] - D) <= TOL and abs(s_only[1] - g) <= TOL * 16
+
+
+def test_miso_ties_take_the_lowest_index():
+    """Exact duplicates of a codeword (in other tiles and lanes) never win
+    over the first copy; channels on a codeword's line quantise to it with
+    distance 0."""
+    n, d = 200, 6
+    C = inputs.random_frame(n, d, seed=8)
+    for k in (40, 77, 150, 199):
+        C[:, k] = C[:, 5]
+    H = np.concatenate([C[:, [5, 9, 150]] * np.array([2.0, 1j, -0.5])[None, :],
+                        inputs.miso_channels(300, d, seed=9)], axis=1)
+    idx, gain, dist, _ = _run(C, H)
+    assert idx[0] == 5 and idx[2] == 5 and idx[1] == 9
+    assert np.all(np.abs(dist[:3]) <= 1e-14)
+    assert not np.any(np.isin(idx, [40, 77, 150, 199]))
+    _check_channels(C, H, idx, gain, dist)
+
+
+def test_miso_invalid_inputs():
+    n, d = 50, 5
+    C = inputs.random_frame(n, d, seed=10)
+    H = inputs.miso_channels(100, d, seed=11)
+    H[:, 3] = 0
+    H[2, 7] = np.inf
+    H[0, 8] = np.nan
+    H[:, 9] = 1e200
+    idx, gain, dist, summary = _run(C, H)
+    ri, rg, rd = oracle.quantize(C, H)
+    assert np.array_equal(idx, ri)
+    assert idx[3] == 0 and gain[3] == 0 and np.isnan(dist[3])
+    for j in (7, 8, 9):
+        assert idx[j] == -1 and np.isnan(gain[j]) and np.isnan(dist[j])
+    ok = np.setdiff1d(np.arange(100), [3, 7, 8, 9])
+    assert np.all(np.abs(gain[ok] - rg[ok]) <= TOL * d) and np.all(np.abs(dist[ok] - rd[ok]) <= TOL)
+    assert np.isnan(summary).all()
+    C[:, 17] = 0
+    idx, gain, dist, summary = _run(C, inputs.miso_channels(70, d, seed=12))
+    assert np.all(idx == -1) and np.isnan(gain).all() and np.isnan(dist).all() and np.isnan(summary).all()
+
+
+def test_miso_no_channels():
+    C = inputs.random_frame(10, 3, seed=1)
+    _, _, _, summary = _run(C, np.zeros((3, 0), dtype=complex), per_channel=False)
+    assert np.isnan(summary).all()
+
+
+def test_miso_closed_form_orthonormal_basis():
+    """An orthonormal basis: mean gain H_d and distortion 1 - H_d / d
+    (order statistics of d i.i.d. Exp(1)), within five standard errors."""
+    d, m = 8, 1 << 18
+    Hd = sum(1.0 / k for k in range(1, d + 1))
+    idx, gain, dist, summary = _run(np.eye(d, dtype=complex), inputs.miso_channels(m, d, seed=13))
+    assert abs(summary[0] - (1 - Hd / d)) <= 5 * np.std(dist) / math.sqrt(m)
+    assert abs(summary[1] - Hd) <= 5 * np.std(gain) / math.sqrt(m)
+
+
+def test_miso_argument_errors():
+    C = lib.frame_to_device(inputs.random_frame(10, 3, seed=1))
+    H = lib.frame_to_device(inputs.miso_channels(10, 3, seed=1))
+    with pytest.raises(lib.TrstmiError):
+        lib.miso_quantize(C, 0, 3, H, 10)
+    with pytest.raises(lib.TrstmiError):
+        lib.miso_quantize(C, 10, 0, H, 10)
+    with pytest.raises(lib.TrstmiError):
+        lib.miso_quantize(C, 10, 3, H, -1)
