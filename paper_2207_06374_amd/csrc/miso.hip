@@ -31,14 +31,54 @@ constexpr int T = 64;        // codewords and channels per block tile
 constexpr int KC = 32;       // K chunk staged through LDS
 constexpr int LDA = KC + 1;  // padded LDS column
 
+// One K chunk of the codeword tile bi and of the block's channels, held in
+// registers between its global load and its store to LDS.
+struct Chunk {
+  double2 a[(T * KC / 2) / 256];
+  double2 b[(T * KC / 2) / 256];
+};
+
+__device__ __forceinline__ void load_chunk(const MisoArgs& a, int bi, int k0, int64_t j0, int K, Chunk& c) {
+#pragma unroll
+  for (int it = 0; it < (T * KC / 2) / 256; ++it) {
+    const int idx = it * 256 + threadIdx.x;
+    const int col = idx / (KC / 2);
+    const int k = k0 + 2 * (idx % (KC / 2));
+    const int ci = bi * T + col;
+    const int64_t cj = j0 + col;
+    c.a[it] = make_double2(0.0, 0.0);
+    c.b[it] = make_double2(0.0, 0.0);
+    if (k < K) {
+      if (ci < a.n) c.a[it] = *(const double2*)(a.codebook + (size_t)ci * a.ldk + k);
+      if (cj < a.m) c.b[it] = *(const double2*)(a.channels + (size_t)cj * K + k);
+    }
+  }
+}
+
+__device__ __forceinline__ void store_chunk(const Chunk& c, double* As, double* Bs) {
+#pragma unroll
+  for (int it = 0; it < (T * KC / 2) / 256; ++it) {
+    const int idx = it * 256 + threadIdx.x;
+    const int col = idx / (KC / 2);
+    const int m = idx % (KC / 2);
+    As[col * LDA + 2 * m] = c.a[it].x;
+    As[col * LDA + 2 * m + 1] = c.a[it].y;
+    Bs[col * LDA + 2 * m] = c.b[it].x;
+    Bs[col * LDA + 2 * m + 1] = c.b[it].y;
+  }
+}
+
+// The chunks (codeword tile bi, K offset k0) are taken in one flat sequence;
+// the next chunk's global loads are issued before the current chunk's
+// products, into registers, and stored to the other LDS buffer afterwards,
+// so one barrier per chunk separates the two buffers' uses.
 __global__ __launch_bounds__(256) void k_miso_quantize(MisoArgs a) {
-  __shared__ double As[T * LDA];
-  __shared__ double Bs[T * LDA];
+  __shared__ double As[2][T * LDA];
+  __shared__ double Bs[2][T * LDA];
   __shared__ double h2s[T];
   __shared__ double redg[8][T];
   __shared__ int32_t redi[8][T];
   __shared__ int32_t redn[8][T];
-  __shared__ double sums[2][4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -47,92 +87,104 @@ __global__ __launch_bounds__(256) void k_miso_quantize(MisoArgs a) {
   const int K = 2 * a.d;
   const int64_t j0 = (int64_t)blockIdx.x * T;
   const int ntile = (a.n + T - 1) / T;
+  const int nk = (K + KC - 1) / KC;
+  const int nq = ntile * nk;
 
   double best[2] = {-1.0, -1.0};
   int32_t bidx[2] = {0, 0};
   bool nan[2] = {false, false};
   double h2 = 0.0;
 
-  for (int bi = 0; bi < ntile; ++bi) {
-    v4f64 accR[2][2], accI[2][2];
+  v4f64 accR[2][2], accI[2][2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        accR[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
-        accI[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
-      }
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < (T * KC / 2) / 256; ++it) {
-        const int idx = it * 256 + tid;
-        const int col = idx / (KC / 2);
-        const int m = idx % (KC / 2);
-        const int k = k0 + 2 * m;
-        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-        const int ci = bi * T + col;
-        const int64_t cj = j0 + col;
-        if (k < K) {
-          if (ci < a.n) va = *(const double2*)(a.codebook + (size_t)ci * a.ldk + k);
-          if (cj < a.m) vb = *(const double2*)(a.channels + (size_t)cj * K + k);
-        }
-        As[col * LDA + 2 * m] = va.x;
-        As[col * LDA + 2 * m + 1] = va.y;
-        Bs[col * LDA + 2 * m] = vb.x;
-        Bs[col * LDA + 2 * m + 1] = vb.y;
-      }
-      __syncthreads();
-      const int kn = K - k0 < KC ? K - k0 : KC;
-      if (bi == 0 && tid < T) {
-        for (int k = 0; k < kn; ++k) {
-          const double x = Bs[tid * LDA + k];
-          h2 = fma(x, x, h2);
-        }
-      }
-      const int ksteps = (kn + 3) / 4;
-      const int kl = lane >> 4;
-      const bool odd = kl & 1;
-      for (int kk = 0; kk < ksteps; ++kk) {
-        const int k = kk * 4 + kl;
-        double av[2], bu[2], bv[2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) av[r] = As[(wr * 32 + r * 16 + (lane & 15)) * LDA + k];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int cc = (wc * 32 + c * 16 + (lane & 15)) * LDA;
-          bu[c] = Bs[cc + k];
-          const double x = Bs[cc + (k ^ 1)];
-          bv[c] = odd ? -x : x;
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bu[c], accR[r][c], 0, 0, 0);
-            accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], accI[r][c], 0, 0, 0);
-          }
+    for (int c = 0; c < 2; ++c) {
+      accR[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
+      accI[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
+    }
+
+  Chunk nxt;
+  load_chunk(a, 0, 0, j0, K, nxt);
+  store_chunk(nxt, As[0], Bs[0]);
+  __syncthreads();
+
+  int bi = 0, kc = 0;
+  for (int q = 0; q < nq; ++q) {
+    const int buf = q & 1;
+    const bool more = q + 1 < nq;
+    if (more) {
+      const int nbi = kc + 1 < nk ? bi : bi + 1;
+      const int nkc = kc + 1 < nk ? kc + 1 : 0;
+      load_chunk(a, nbi, nkc * KC, j0, K, nxt);
+    }
+    const double* Ab = As[buf];
+    const double* Bb = Bs[buf];
+    const int k0 = kc * KC;
+    const int kn = K - k0 < KC ? K - k0 : KC;
+    if (bi == 0 && tid < T) {
+      for (int k = 0; k < kn; ++k) {
+        const double x = Bb[tid * LDA + k];
+        h2 = fma(x, x, h2);
       }
     }
-    // output register v of lane l: codeword row 4 v + l / 16, channel column l % 16
+    const int ksteps = (kn + 3) / 4;
+    const int kl = lane >> 4;
+    const bool odd = kl & 1;
+    for (int kk = 0; kk < ksteps; ++kk) {
+      const int k = kk * 4 + kl;
+      double av[2], bu[2], bv[2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+      for (int r = 0; r < 2; ++r) av[r] = Ab[(wr * 32 + r * 16 + (lane & 15)) * LDA + k];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = bi * T + wr * 32 + r * 16 + 4 * v + (lane >> 4);
-        if (i < a.n) {
+      for (int c = 0; c < 2; ++c) {
+        const int cc = (wc * 32 + c * 16 + (lane & 15)) * LDA;
+        bu[c] = Bb[cc + k];
+        const double x = Bb[cc + (k ^ 1)];
+        bv[c] = odd ? -x : x;
+      }
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const double re = accR[r][c][v], im = accI[r][c][v];
-            const double g = re * re + im * im;
-            if (g > best[c]) {
-              best[c] = g;
-              bidx[c] = i;
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bu[c], accR[r][c], 0, 0, 0);
+          accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], accI[r][c], 0, 0, 0);
+        }
+    }
+    if (kc + 1 == nk) {
+      // output register v of lane l: codeword row 4 v + l / 16, channel column l % 16
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = bi * T + wr * 32 + r * 16 + 4 * v + (lane >> 4);
+          if (i < a.n) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const double re = accR[r][c][v], im = accI[r][c][v];
+              const double g = re * re + im * im;
+              if (g > best[c]) {
+                best[c] = g;
+                bidx[c] = i;
+              }
+              nan[c] |= (g != g);
             }
-            nan[c] |= (g != g);
           }
         }
-      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          accR[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
+          accI[r][c] = v4f64{0.0, 0.0, 0.0, 0.0};
+        }
+      kc = 0;
+      ++bi;
+    } else {
+      ++kc;
+    }
+    if (more) store_chunk(nxt, As[buf ^ 1], Bs[buf ^ 1]);
+    __syncthreads();
   }
 
   // candidates per channel column: 4 lane groups x 2 waves (wr)
