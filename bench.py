@@ -382,7 +382,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
     ap.add_argument("--miso-evals", type=int, default=10,
                     help="codebook quantiser calls to time (4096 codewords, d = 64, 65536 channels; 0: skip)")
-    ap.add_argument("--table2-dims", default="2,3,4",
+    ap.add_argument("--table2-dims", default="2,3,4,5,6",
                     help="dimensions d for the optimiser at N = d^2 (Table II comparison; empty: skip)")
     ap.add_argument("--smooth-max-evals", type=int, default=10,
                     help="evaluations of the section IV smooth maximum at the throughput shape (0: skip)")

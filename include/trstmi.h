@@ -262,10 +262,12 @@ typedef struct {
   double cg_tol;           /* > 0 */
   int32_t cg_max_iter;     /* >= 1, or 0 for 2 d N */
   double fd_step;          /* > 0 */
+  int32_t concurrency;     /* starts run at once (one host thread and stream each), 1 .. 64 */
 } trstmi_opt_params;
 
-/* Bytes of workspace trstmi_optimize needs (0 if invalid or d > 64). */
-size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d);
+/* Bytes of workspace trstmi_optimize needs with `concurrency` starts in
+ * flight (0 if invalid or d > 64). */
+size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d, int32_t concurrency);
 
 /*
  * The paper's outer procedure (Alg. 2): for each of L random starts (the
@@ -276,8 +278,13 @@ size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d);
  * falls below radius_min, or when the gradient vanishes); then the exact
  * FP64 coherence of the result.  best_frame (device, caller's layout)
  * receives the frame with the smallest coherence, *best_mu and
- * *best_restart (host) its coherence and start index.  Synchronises the
- * stream.  Requires n >= 2, 1 <= d <= 64.
+ * *best_restart (host) its coherence and start index (the lowest index
+ * among equal coherences).  With concurrency P > 1 the starts are dealt to
+ * P host threads, each with a stream of its own (created and destroyed by
+ * the call, after the caller's stream has drained; start l goes to thread
+ * l mod P); every start computes exactly what it computes alone, so the
+ * result does not depend on P.  Synchronises the stream.  Requires n >= 2,
+ * 1 <= d <= 64, and a workspace of trstmi_optimize_workspace_bytes(n, d, P).
  */
 trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* params, double* best_frame,
                               double* best_mu, int32_t* best_restart, void* workspace,

@@ -114,7 +114,7 @@ class OptParams(ctypes.Structure):
                 ("deltas", ctypes.POINTER(ctypes.c_double)), ("steps_per_delta", ctypes.c_int32),
                 ("radius0", ctypes.c_double), ("radius_min", ctypes.c_double), ("radius_max", ctypes.c_double),
                 ("eta", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
-                ("fd_step", ctypes.c_double)]
+                ("fd_step", ctypes.c_double), ("concurrency", ctypes.c_int32)]
 
 
 class TRReport(ctypes.Structure):
@@ -135,7 +135,7 @@ SIGNATURES = {
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_tr_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_tr_step": (_i32, [_i64, _i64, _vp, _P(TRParams), _P(TRReport), _vp, _sz, _vp]),
-    "trstmi_optimize_workspace_bytes": (_sz, [_i64, _i64]),
+    "trstmi_optimize_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "trstmi_optimize": (_i32, [_i64, _i64, _P(OptParams), _vp, _P(ctypes.c_double), _P(_i32), _vp, _sz, _vp]),
     "trstmi_miso_workspace_bytes": (_sz, [_i64, _i64, _i64]),
     "trstmi_miso_quantize": (_i32, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -800,11 +801,97 @@ trstmi_status trstmi_tr_step(int64_t n, int64_t d, double* frame, const trstmi_t
   return st;
 }
 
-size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d) {
+static size_t optimize_slot_bytes(int64_t n, int64_t d) {
   const size_t t = trstmi_tr_workspace_bytes(n, d);
   if (!t) return 0;
-  return align256(t) + align256((size_t)2 * d * n * 8) + align256(trstmi_coherence_workspace_bytes(n, d, 0)) + 256;
+  const size_t frame = align256((size_t)2 * d * n * 8);
+  return align256(t) + frame + align256(trstmi_coherence_workspace_bytes(n, d, 0)) + 256 + frame;
 }
+
+size_t trstmi_optimize_workspace_bytes(int64_t n, int64_t d, int32_t concurrency) {
+  if (concurrency < 1 || concurrency > 64) return 0;
+  return (size_t)concurrency * optimize_slot_bytes(n, d);
+}
+
+namespace {
+
+// One worker's share of the starts: l = first, first + stride, ...; keeps
+// the best (mu, l) of its share and that frame in its slot.
+struct OptWorker {
+  int64_t n, d;
+  const trstmi_opt_params* op;
+  char* slot;
+  hipStream_t stream;
+  int32_t first, stride;
+  double best_mu = __builtin_inf();
+  int32_t best_l = -1;
+  trstmi_status st = TRSTMI_OK;
+  std::string err;
+
+  double* best_frame() const {
+    const size_t frame = align256((size_t)2 * d * n * 8);
+    return (double*)(slot + optimize_slot_bytes(n, d) - frame);
+  }
+
+  trstmi_status run() {
+    const size_t tws = align256(trstmi_tr_workspace_bytes(n, d));
+    const size_t lws = align256(trstmi_lse_grad_workspace_bytes(n, d));
+    double* W = (double*)(slot + tws);
+    char* cws = slot + tws + align256((size_t)2 * d * n * 8);
+    const size_t cws_bytes = trstmi_coherence_workspace_bytes(n, d, 0);
+    double* mu_dev = (double*)(cws + align256(cws_bytes));
+    trstmi_status rs;
+    for (int32_t l = first; l < op->restarts; l += stride) {
+      PerturbArgs pa{};
+      pa.n = n;
+      pa.d = (int32_t)d;
+      pa.seed = (uint32_t)op->seed;
+      pa.stream_id = (uint32_t)l;
+      pa.have_z = 1;
+      pa.base = nullptr;
+      pa.tag = 1;
+      pa.t_const = 0;
+      pa.c0 = 0;
+      pa.out = W;
+      pa.out_kind = kOutF64;
+      pa.out_ld = (int32_t)(2 * d);
+      pa.out_slot_stride = 2 * d * n;
+      TRY_HIP(launch_perturb(pa, 1, stream), "optimise: random start");
+      for (int32_t k = 0; k < op->n_deltas; ++k) {
+        trstmi_tr_params tp{};
+        tp.delta = op->deltas[k];
+        tp.radius = op->radius0;
+        tp.radius_max = op->radius_max;
+        tp.eta = op->eta;
+        tp.cg_tol = op->cg_tol;
+        tp.cg_max_iter = op->cg_max_iter ? op->cg_max_iter : (int32_t)(2 * d * n);
+        tp.fd_step = op->fd_step;
+        for (int32_t s = 0; s < op->steps_per_delta; ++s) {
+          trstmi_tr_report rep{};
+          rs = tr_step_impl(n, d, W, &tp, &rep, slot, lws, stream);
+          if (rs == TRSTMI_E_HIP) return fail(TRSTMI_E_HIP, "optimise: a HIP call failed");
+          if (rs != TRSTMI_OK) return fail(rs, "optimise: trust-region step failed");
+          tp.radius = rep.new_radius;
+          if (tp.radius < op->radius_min || rep.cg_exit == TRSTMI_CG_ZERO_GRADIENT) break;
+        }
+      }
+      if ((rs = trstmi_coherence(n, d, TRSTMI_MODE_FP64, W, mu_dev, cws, cws_bytes, stream))) return rs;
+      double mu = 0.0;
+      TRY_HIP(hipMemcpyAsync(&mu, mu_dev, sizeof(double), hipMemcpyDeviceToHost, stream), "optimise: read mu");
+      TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+      if (mu < best_mu) {
+        best_mu = mu;
+        best_l = l;
+        TRY_HIP(hipMemcpyAsync(best_frame(), W, (size_t)2 * d * n * 8, hipMemcpyDeviceToDevice, stream),
+                "optimise: copy");
+      }
+    }
+    TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+    return TRSTMI_OK;
+  }
+};
+
+}  // namespace
 
 trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op, double* best_frame, double* best_mu,
                               int32_t* best_restart, void* workspace, size_t workspace_bytes, hipStream_t stream) {
@@ -815,65 +902,68 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op,
   auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
   bool ok = op->restarts >= 1 && op->n_deltas >= 1 && op->deltas && op->steps_per_delta >= 1 && pos(op->radius0) &&
             op->radius_min >= 0.0 && op->radius_max >= op->radius0 && std::isfinite(op->radius_max) &&
-            op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) && op->cg_max_iter >= 0 && pos(op->fd_step);
+            op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) && op->cg_max_iter >= 0 && pos(op->fd_step) &&
+            op->concurrency >= 1 && op->concurrency <= 64;
   for (int32_t k = 0; ok && k < op->n_deltas; ++k) ok = pos(op->deltas[k]);
   if (!ok) return fail(TRSTMI_E_INVALID_ARG, "invalid optimiser parameters");
   if (!best_frame || ((uintptr_t)best_frame & 15)) return fail(TRSTMI_E_INVALID_ARG, "best_frame: null or misaligned");
-  const size_t need = trstmi_optimize_workspace_bytes(n, d);
+  const size_t need = trstmi_optimize_workspace_bytes(n, d, op->concurrency);
   if ((st = check_ws(workspace, workspace_bytes, need))) return st;
-  char* ws = (char*)workspace;
-  const size_t tws = align256(trstmi_tr_workspace_bytes(n, d));
-  const size_t lws = align256(trstmi_lse_grad_workspace_bytes(n, d));
-  double* W = (double*)(ws + tws);
-  char* cws = ws + tws + align256((size_t)2 * d * n * 8);
-  const size_t cws_bytes = trstmi_coherence_workspace_bytes(n, d, 0);
-  double* mu_dev = (double*)(cws + align256(cws_bytes));
+  const int32_t P = std::min(op->concurrency, op->restarts);
+  const size_t slot_bytes = optimize_slot_bytes(n, d);
 
-  *best_mu = __builtin_inf();
-  *best_restart = -1;
-  for (int32_t l = 0; l < op->restarts; ++l) {
-    PerturbArgs pa{};
-    pa.n = n;
-    pa.d = (int32_t)d;
-    pa.seed = (uint32_t)op->seed;
-    pa.stream_id = (uint32_t)l;
-    pa.have_z = 1;
-    pa.base = nullptr;
-    pa.tag = 1;
-    pa.t_const = 0;
-    pa.c0 = 0;
-    pa.out = W;
-    pa.out_kind = kOutF64;
-    pa.out_ld = (int32_t)(2 * d);
-    pa.out_slot_stride = 2 * d * n;
-    TRY_HIP(launch_perturb(pa, 1, stream), "optimise: random start");
-    for (int32_t k = 0; k < op->n_deltas; ++k) {
-      trstmi_tr_params tp{};
-      tp.delta = op->deltas[k];
-      tp.radius = op->radius0;
-      tp.radius_max = op->radius_max;
-      tp.eta = op->eta;
-      tp.cg_tol = op->cg_tol;
-      tp.cg_max_iter = op->cg_max_iter ? op->cg_max_iter : (int32_t)(2 * d * n);
-      tp.fd_step = op->fd_step;
-      for (int32_t s = 0; s < op->steps_per_delta; ++s) {
-        trstmi_tr_report rep{};
-        st = tr_step_impl(n, d, W, &tp, &rep, ws, lws, stream);
-        if (st == TRSTMI_E_HIP) return fail(TRSTMI_E_HIP, "optimise: a HIP call failed");
-        if (st != TRSTMI_OK) return fail(st, "optimise: trust-region step failed");
-        tp.radius = rep.new_radius;
-        if (tp.radius < op->radius_min || rep.cg_exit == TRSTMI_CG_ZERO_GRADIENT) break;
+  std::vector<OptWorker> work(P);
+  for (int32_t t = 0; t < P; ++t) {
+    work[t].n = n;
+    work[t].d = d;
+    work[t].op = op;
+    work[t].slot = (char*)workspace + (size_t)t * slot_bytes;
+    work[t].stream = stream;
+    work[t].first = t;
+    work[t].stride = P;
+  }
+  if (P == 1) {
+    work[0].st = work[0].run();
+  } else {
+    int dev = 0;
+    TRY_HIP(hipGetDevice(&dev), "optimise: device");
+    TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+    for (int32_t t = 0; t < P; ++t) {
+      hipError_t e = hipStreamCreateWithFlags(&work[t].stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        for (int32_t u = 0; u < t; ++u) (void)hipStreamDestroy(work[u].stream);
+        return hip_fail(e, "optimise: stream");
       }
     }
-    if ((st = trstmi_coherence(n, d, TRSTMI_MODE_FP64, W, mu_dev, cws, cws_bytes, stream))) return st;
-    double mu = 0.0;
-    TRY_HIP(hipMemcpyAsync(&mu, mu_dev, sizeof(double), hipMemcpyDeviceToHost, stream), "optimise: read mu");
-    TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
-    if (mu < *best_mu) {
-      *best_mu = mu;
-      *best_restart = l;
-      TRY_HIP(hipMemcpyAsync(best_frame, W, (size_t)2 * d * n * 8, hipMemcpyDeviceToDevice, stream), "optimise: copy");
-    }
+    std::vector<std::thread> threads;
+    for (int32_t t = 0; t < P; ++t)
+      threads.emplace_back([&work, t, dev]() {
+        OptWorker& w = work[t];
+        hipError_t e = hipSetDevice(dev);
+        w.st = e == hipSuccess ? w.run() : hip_fail(e, "optimise: device");
+        if (w.st != TRSTMI_OK) w.err = g_last_error;
+      });
+    for (auto& th : threads) th.join();
+    for (int32_t t = 0; t < P; ++t) (void)hipStreamDestroy(work[t].stream);
+    for (int32_t t = 0; t < P; ++t)
+      if (work[t].st != TRSTMI_OK) return fail(work[t].st, work[t].err);
+  }
+  if (work[0].st != TRSTMI_OK) return work[0].st;
+  int32_t w_best = -1;
+  for (int32_t t = 0; t < P; ++t) {
+    const OptWorker& w = work[t];
+    if (w.best_l < 0) continue;
+    if (w_best < 0 || w.best_mu < work[w_best].best_mu ||
+        (w.best_mu == work[w_best].best_mu && w.best_l < work[w_best].best_l))
+      w_best = t;
+  }
+  *best_mu = __builtin_inf();
+  *best_restart = -1;
+  if (w_best >= 0) {
+    *best_mu = work[w_best].best_mu;
+    *best_restart = work[w_best].best_l;
+    TRY_HIP(hipMemcpyAsync(best_frame, work[w_best].best_frame(), (size_t)2 * d * n * 8, hipMemcpyDeviceToDevice,
+                           stream), "optimise: copy");
   }
   TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
   return TRSTMI_OK;
@@ -1195,6 +1285,6 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
-int32_t trstmi_abi_version(void) { return 5; }
+int32_t trstmi_abi_version(void) { return 6; }
 
 }  // extern "C"

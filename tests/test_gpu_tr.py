@@ -143,3 +143,17 @@ def test_optimize_matches_oracle_short_run(n, d, seed):
     ph = np.sum(np.conj(Fr) * Fn, axis=0)
     ph /= np.abs(ph)
     assert np.max(np.abs(Fn - Fr * ph)) <= 1e-6
+
+
+def test_optimize_concurrency_does_not_change_the_result():
+    """Starts dealt to several host threads and streams compute exactly what
+    they compute one after another: same coherence bits, same start, same
+    frame."""
+    n, d = 16, 4
+    kw = dict(restarts=6, deltas=(1e-1, 1e-2), steps_per_delta=10, seed=3)
+    f1, mu1, l1 = lib.optimize(n, d, concurrency=1, **kw)
+    f4, mu4, l4 = lib.optimize(n, d, concurrency=4, **kw)
+    f6, mu6, l6 = lib.optimize(n, d, concurrency=6, **kw)
+    print(f"mu={mu1!r} {mu4!r} {mu6!r} restart={l1} {l4} {l6}", flush=True)
+    assert mu1 == mu4 == mu6 and l1 == l4 == l6
+    assert torch.equal(f1, f4) and torch.equal(f1, f6)
