@@ -160,9 +160,9 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
 
 def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     """The smooth maximum of section IV on the throughput shape (one Haar
-    frame, N=4096, d=64): FP64 normalisation, the FP64 MFMA max pass, the
-    sum-exp pass over the same tiles and the fixed-order finish; then the
-    value with its gradient with respect to the frame."""
+    frame, N=4096, d=64): FP64 normalisation, one FP64 MFMA pass over the
+    upper-triangle tiles (block maxima and rescaled sums) and the fixed-order
+    finish; then the value with its gradient with respect to the frame."""
     s = lib.Solver(wl.n, wl.d, candidates=8, mode="fp64", seed=wl.seed, stream_id=wl.stream_id)
     s.init_haar()
     frame = s.state.frame
@@ -180,10 +180,10 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     t1 = time.perf_counter()
     lib.timing_enable(False)
     us = {}
-    for k in ("lse_max", "lse_sumexp"):
+    for k in ("lse_pass",):
         ms, cnt = lib.timing_read(k)
         us[k] = 1e3 * ms / cnt
-    flops = flops_per_eval(wl.n, wl.d)  # per pass
+    flops = flops_per_eval(wl.n, wl.d)  # the one pass over the upper-triangle tiles
     s_val, f_val = out.cpu().numpy().tolist()
     # value and gradient with respect to the frame (the paper's optimiser's step)
     grad = torch.empty_like(frame)
@@ -222,10 +222,8 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
         "workload": f"F_(s,delta) of |G|^2 over j<k, N={wl.n}, d={wl.d}, delta={delta}, FP64 (Haar frame seed 0)",
         "ms_per_eval": 1e3 * (t1 - t0) / evals,
         "evals_per_s": evals / (t1 - t0),
-        "max_pass_us": us["lse_max"],
-        "sumexp_pass_us": us["lse_sumexp"],
-        "max_pass_frac_fp64_peak": flops / (us["lse_max"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
-        "sumexp_pass_frac_fp64_peak": flops / (us["lse_sumexp"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+        "pass_us": us["lse_pass"],
+        "pass_frac_fp64_peak": flops / (us["lse_pass"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
         "s": s_val,
         "F": f_val,
         "grad_ms_per_eval": 1e3 * (t3 - t2) / evals,

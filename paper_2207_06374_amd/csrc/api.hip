@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -629,7 +630,7 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
 size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d) {
   if (check_size(n, d)) return 0;
   const int64_t nt = (n + kTileF64 - 1) / kTileF64;
-  return align256((size_t)n * ld_mode(d, TRSTMI_MODE_FP64) * 8) + 256 + align256((size_t)(nt * (nt + 1) / 2) * 8);
+  return align256((size_t)n * ld_mode(d, TRSTMI_MODE_FP64) * 8) + 256 + align256((size_t)(nt * (nt + 1) / 2) * 16);
 }
 
 trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta, int32_t squared, double* out,
@@ -661,8 +662,7 @@ trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta
   pa.zero_max = mx;
   TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
   GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
-  TRY_HIP(TIMED("lse_max", stream, launch_gram_f64(g, 1, stream)), "gram_f64");
-  TRY_HIP(TIMED("lse_sumexp", stream, launch_lse_sumexp(g, mx, delta, squared, partial, stream)), "lse_sumexp");
+  TRY_HIP(TIMED("lse_pass", stream, launch_lse_pass(g, delta, squared, partial, stream)), "lse_pass");
   TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, squared, out, nullptr, stream), "lse_finish");
   return TRSTMI_OK;
 }
@@ -753,8 +753,7 @@ trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double 
   pa.zero_max = mx;
   TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
   GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
-  TRY_HIP(TIMED("lse_max", stream, launch_gram_f64(g, 1, stream)), "gram_f64");
-  TRY_HIP(TIMED("lse_sumexp", stream, launch_lse_sumexp(g, mx, delta, 1, partial, stream)), "lse_sumexp");
+  TRY_HIP(TIMED("lse_pass", stream, launch_lse_pass(g, delta, 1, partial, stream)), "lse_pass");
   TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, 1, out, log_sum, stream), "lse_finish");
   GradArgs ga{};
   ga.frame = (const double*)ws;
@@ -823,6 +822,7 @@ struct OptWorker {
   char* slot;
   hipStream_t stream;
   int32_t first, stride;
+  std::atomic<bool>* abort;  // set when any worker fails: the others stop at their next start
   double best_mu = __builtin_inf();
   int32_t best_l = -1;
   trstmi_status st = TRSTMI_OK;
@@ -842,6 +842,7 @@ struct OptWorker {
     double* mu_dev = (double*)(cws + align256(cws_bytes));
     trstmi_status rs;
     for (int32_t l = first; l < op->restarts; l += stride) {
+      if (abort->load(std::memory_order_relaxed)) break;
       PerturbArgs pa{};
       pa.n = n;
       pa.d = (int32_t)d;
@@ -912,8 +913,10 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op,
   const int32_t P = std::min(op->concurrency, op->restarts);
   const size_t slot_bytes = optimize_slot_bytes(n, d);
 
+  std::atomic<bool> abort{false};
   std::vector<OptWorker> work(P);
   for (int32_t t = 0; t < P; ++t) {
+    work[t].abort = &abort;
     work[t].n = n;
     work[t].d = d;
     work[t].op = op;
@@ -941,7 +944,10 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op,
         OptWorker& w = work[t];
         hipError_t e = hipSetDevice(dev);
         w.st = e == hipSuccess ? w.run() : hip_fail(e, "optimise: device");
-        if (w.st != TRSTMI_OK) w.err = g_last_error;
+        if (w.st != TRSTMI_OK) {
+          w.err = g_last_error;
+          w.abort->store(true, std::memory_order_relaxed);
+        }
       });
     for (auto& th : threads) th.join();
     for (int32_t t = 0; t < P; ++t) (void)hipStreamDestroy(work[t].stream);

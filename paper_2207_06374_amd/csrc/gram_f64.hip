@@ -18,11 +18,12 @@
 //
 // The same tiles also evaluate the smooth maximum of section IV,
 // F_{s,delta}(x) = s + delta log sum_i exp((x_i - s) / delta) over
-// x = |G_jk|^2 (or |G_jk|), j < k, with s = max x: a first launch finds s
-// (the maximum above), a second recomputes every tile with the same
-// arithmetic (so x <= s holds bit for bit) and sums exp((x - s) / delta) per
-// block into a slot of its own, and one block adds the slots in a fixed
-// order, so the result does not depend on scheduling.
+// x = |G_jk|^2 (or |G_jk|), j < k, with s = max x, in one pass: each block
+// finds its own maximum x_b (and raises the global maximum with the atomic
+// above), sums exp((x - x_b) / delta) over its pairs into a slot of its own
+// together with x_b, and one block rescales the slots to the global s,
+// S = sum_b S_b exp((x_b - s) / delta), adding them in a fixed order, so the
+// result does not depend on scheduling.  Every exponent is <= 0.
 //
 // Tile: 64 x 64 complex outputs per 256-thread block, each wave a 32 x 32
 // quadrant (2 x 2 MFMA blocks, Re and Im accumulators).  K is staged through
@@ -42,10 +43,9 @@ constexpr int LDA = KC + 1;
 
 // Parameters of the sum-exp epilogue (null: the maximum epilogue).
 struct SumExp {
-  const uint64_t* s_bits;  // max |G|^2 bits from the first launch
   double inv_delta;
   int32_t squared;         // x = |G|^2 (1) or |G| (0)
-  double* partial;         // [tile] block sums
+  double* partial;         // [tile][2]: block sum S_b, block maximum x_b
 };
 
 template <bool SUMEXP>
@@ -116,10 +116,32 @@ __device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int b
   }
 
   if constexpr (SUMEXP) {
-    const double m_max = __longlong_as_double((int64_t)*se.s_bits);
-    const double s_x = se.squared ? m_max : sqrt(m_max);
-    double sum = 0.0;
+    // the block's maximum of |G|^2 (bit patterns: NaN above +inf), then its sum
+    uint64_t bm = 0;
     if (!skip) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = bi * T + wr * 32 + r * 16 + 4 * v + (lane >> 4);
+            const int j = bj * T + wc * 32 + c * 16 + (lane & 15);
+            const double re = accR[r][c][v], im = accI[r][c][v];
+            const uint64_t mb = (uint64_t)__double_as_longlong(re * re + im * im);
+            if (i < j && j < a.n && mb > bm) bm = mb;
+          }
+    }
+    bm = wave_max_u64(bm);
+    if (lane == 0) red[w] = bm;
+    __syncthreads();
+    bm = red[0];
+    for (int q = 1; q < 4; ++q) bm = red[q] > bm ? red[q] : bm;
+    const bool finite = bm < kInfBits64;
+    const double m_b = finite ? __longlong_as_double((int64_t)bm) : 0.0;
+    const double x_b = se.squared ? m_b : sqrt(m_b);
+    double sum = 0.0;
+    if (!skip && finite) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -131,15 +153,20 @@ __device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int b
             const double re = accR[r][c][v], im = accI[r][c][v];
             const double m = re * re + im * im;
             const double x = se.squared ? m : sqrt(m);
-            if (i < j && j < a.n) sum += exp((x - s_x) * se.inv_delta);
+            if (i < j && j < a.n) sum += exp((x - x_b) * se.inv_delta);
           }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    __syncthreads();  // every wave has read red[]
     double* reds = (double*)red;
     if (lane == 0) reds[w] = sum;
     __syncthreads();
-    if (tid == 0) se.partial[blockIdx.x] = (reds[0] + reds[1]) + (reds[2] + reds[3]);
+    if (tid == 0) {
+      se.partial[2 * blockIdx.x] = (reds[0] + reds[1]) + (reds[2] + reds[3]);
+      se.partial[2 * blockIdx.x + 1] = x_b;
+      atomicMax((unsigned long long*)&a.cand_max[slot], (unsigned long long)bm);
+    }
     return;
   }
   uint64_t best = 0;
@@ -179,7 +206,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
   gram_f64_tile<false>(a, blockIdx.y, bi, bj, As, Bs, red, SumExp{});
 }
 
-__global__ __launch_bounds__(256) void k_gram_f64_sumexp(GramArgs a, SumExp se) {
+__global__ __launch_bounds__(256) void k_gram_f64_lse(GramArgs a, SumExp se) {
   __shared__ double As[T * LDA];
   __shared__ double Bs[T * LDA];
   __shared__ uint64_t red[4];
@@ -188,13 +215,20 @@ __global__ __launch_bounds__(256) void k_gram_f64_sumexp(GramArgs a, SumExp se) 
   gram_f64_tile<true>(a, 0, bi, bj, As, Bs, red, se);
 }
 
-// F = s + delta log(sum of the block sums), added in a fixed order: thread t
-// takes slots t, t + 256, ... in turn, then a fixed pairwise tree.
+// F = s + delta log S with S = sum_b S_b exp((x_b - s) / delta), added in a
+// fixed order: thread t takes slots t, t + 256, ... in turn, then a fixed
+// pairwise tree.
 __global__ __launch_bounds__(256) void k_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count,
                                                     double delta, int32_t squared, double* out, double* log_sum) {
   __shared__ double acc[256];
+  const uint64_t b = *s_bits;
+  const bool finite = b < kInfBits64;
+  const double m = finite ? __longlong_as_double((int64_t)b) : 0.0;
+  const double s = squared ? m : sqrt(m);
+  const double inv_delta = 1.0 / delta;
   double sum = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += 256) sum += partial[i];
+  if (finite)
+    for (int64_t i = threadIdx.x; i < count; i += 256) sum += partial[2 * i] * exp((partial[2 * i + 1] - s) * inv_delta);
   acc[threadIdx.x] = sum;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -202,15 +236,12 @@ __global__ __launch_bounds__(256) void k_lse_finish(const uint64_t* s_bits, cons
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const uint64_t b = *s_bits;
-    if (b >= kInfBits64) {  // a zero or non-finite column
+    if (!finite) {  // a zero or non-finite column
       out[0] = __builtin_inf();
       out[1] = __builtin_inf();
       if (log_sum) *log_sum = __builtin_inf();
       return;
     }
-    const double m = __longlong_as_double((int64_t)b);
-    const double s = squared ? m : sqrt(m);
     const double ls = log(acc[0]);
     out[0] = s;
     out[1] = s + delta * ls;
@@ -226,11 +257,10 @@ hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_lse_sumexp(const GramArgs& a, const uint64_t* s_bits, double delta, int32_t squared,
-                             double* partial, hipStream_t s) {
+hipError_t launch_lse_pass(const GramArgs& a, double delta, int32_t squared, double* partial, hipStream_t s) {
   const int tiles = a.nt * (a.nt + 1) / 2;
-  SumExp se{s_bits, 1.0 / delta, squared, partial};
-  hipLaunchKernelGGL(k_gram_f64_sumexp, dim3(tiles), dim3(256), 0, s, a, se);
+  SumExp se{1.0 / delta, squared, partial};
+  hipLaunchKernelGGL(k_gram_f64_lse, dim3(tiles), dim3(256), 0, s, a, se);
   return hipGetLastError();
 }
 

@@ -163,10 +163,11 @@ int batch_lds_floats();
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
-// Smooth maximum (one frame, slot 0): block sums of exp((x - s) / delta) into
-// partial[tile], then F = s + delta log(sum) into out = (s, F).
-hipError_t launch_lse_sumexp(const GramArgs& a, const uint64_t* s_bits, double delta, int32_t squared,
-                             double* partial, hipStream_t s);
+// Smooth maximum (one frame, slot 0), one pass over the tiles: per block
+// (S_b, x_b) into partial[tile][2] and the maximum |G|^2 bits into
+// a.cand_max[0] (zeroed beforehand); then F = s + delta log S into
+// out = (s, F).
+hipError_t launch_lse_pass(const GramArgs& a, double delta, int32_t squared, double* partial, hipStream_t s);
 hipError_t launch_lse_finish(const uint64_t* s_bits, const double* partial, int64_t count, double delta,
                              int32_t squared, double* out, double* log_sum, hipStream_t s);
 

@@ -111,7 +111,7 @@ def _table2():
     return rows
 
 
-@pytest.mark.parametrize("d,restarts", [(2, 8), (3, 18), (4, 32), (5, 50)])
+@pytest.mark.parametrize("d,restarts", [(2, 8), (3, 18), (4, 32), (5, 50), (6, 72)])
 def test_optimize_reaches_table2(d, restarts):
     """Alg. 2 on the GPU reaches the printed Table II coherence at N = d^2
     (the Welch bound there, so optimal)."""
