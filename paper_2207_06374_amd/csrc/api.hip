@@ -717,7 +717,7 @@ size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d) {
   if (check_size(n, d) || d > 64) return 0;
   const int64_t nkb = (n + kTileF64 - 1) / kTileF64;
   const int64_t nch = lse_grad_chunks((int)nkb);
-  return trstmi_lse_workspace_bytes(n, d) + 256 + align256((size_t)nkb * nch * 2 * kTileF64 * 2 * d * 8);
+  return trstmi_lse_workspace_bytes(n, d) + 256 + align256((size_t)nkb * nch * 2 * 2 * kTileF64 * 2 * d * 8);
 }
 
 trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double delta, double* out, double* grad,

@@ -182,7 +182,7 @@ struct GradArgs {
   const uint64_t* s_bits;   // max |G|^2 bits
   const double* log_sum;    // log of sum exp((x - s) / delta) over j < k
   double inv_delta;
-  double* partial;          // [nkb][nch][2][64][2d]
+  double* partial;          // [nkb][nch][2 row halves][2][64][2d]
   double* grad;             // out: column stride 2d, (re, im) interleaved
 };
 int lse_grad_chunks(int nkb);

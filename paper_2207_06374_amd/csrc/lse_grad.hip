@@ -7,19 +7,22 @@
 //
 // k_lse_grad: a block owns 64 output columns k (tile kb) and a run of row
 // tiles jb.  Both 64-column tiles of the normalised frame sit in LDS with
-// the whole K = 2d (d <= 64).  Wave w computes G for all 64 rows j of tile
-// jb against its 16 columns k on v_mfma_f64_16x16x4f64, turns it into
-// B = W o G in registers, and feeds B straight into the second product
-// P = U_jb B (U: the real 2d-vectors of tile jb, rows m): the output layout
+// the whole K = 2d (d <= 64).  Eight waves share them: wave w takes the 16
+// columns k of group w mod 4 and the 32 rows j of half w / 4 of tile jb
+// (two waves per SIMD, so one wave's exponentials and barriers overlap the
+// other's matrix products).  A wave computes G for its rows and columns on
+// v_mfma_f64_16x16x4f64, turns it into B = W o G in registers, and feeds B
+// straight into the second product P = U_jb B over its rows (U: the real
+// 2d-vectors of tile jb, rows m): the output layout
 // of a 16 x 16 block (register v of lane l: row 4 v + l / 16, column
 // l % 16) is the B-operand layout of the K step 4 v of the next product, so
 // no data moves between the two.  Re and Im of D come from the two real
 // products P1 = U Re(B), P2 = U Im(B) (D_re[i] = P1[2i] - P2[2i+1],
-// D_im[i] = P2[2i] + P1[2i+1]).  Each block writes its partial P1, P2 to a
-// slot of its own; k_lse_grad_finish adds the slots of a column in a fixed
-// order and applies the projection through the normalisation, so repeated
-// calls give the same bits.  The next row tile is loaded into registers
-// while the current one is multiplied (one wave per SIMD: 132 KB of LDS).
+// D_im[i] = P2[2i] + P1[2i+1]).  Each wave writes its partial P1, P2 (its
+// columns over its row half) to a slot of its own; k_lse_grad_finish adds
+// the slots of a column in a fixed order and applies the projection through
+// the normalisation, so repeated calls give the same bits.  The next row
+// tile is loaded into registers while the current one is multiplied.
 
 #include "device_common.h"
 #include "launch.h"
@@ -30,6 +33,7 @@ namespace {
 
 constexpr int T = 64;
 constexpr int kMaxLdp = 129;  // 2d rounded up to 16, plus one (d <= 64)
+constexpr int kThreadsG = 512;
 
 __device__ __forceinline__ void stage_cols(const double* base, int ld, int n, int d, int c0, int ldp, double* Us) {
   // columns c0 .. c0 + 63 of the normalised frame, entries 0 .. ldp - 2,
@@ -44,14 +48,14 @@ __device__ __forceinline__ void stage_cols(const double* base, int ld, int n, in
 // The next row tile in registers while the current one is multiplied.  The
 // LDS column holds L = ldp - 1 doubles, a power of two (16 .. 128), so a
 // thread's 16-byte pieces sit at a fixed column stride: pair p = tid mod L/2
-// of columns tid / (L/2) + q (512 / L), q = 0 .. L/32 - 1.
-constexpr int kPre = T * (kMaxLdp - 1) / 2 / 256;  // double2 per thread, at most
+// of columns tid / (L/2) + q (1024 / L), q = 0 .. L/64 - 1 (at least one).
+constexpr int kPre = T * (kMaxLdp - 1) / 2 / kThreadsG;  // double2 per thread, at most
 
 __device__ __forceinline__ void fetch_cols(const double* base, int ld, int n, int d, int c0, int ldp,
                                            double2 pre[kPre]) {
   const int L2 = (ldp - 1) / 2;
   const int p = threadIdx.x % L2;
-  const int col0 = threadIdx.x / L2, cstep = 256 / L2;
+  const int col0 = threadIdx.x / L2, cstep = kThreadsG / L2;
   const int nq = T / cstep;
 #pragma unroll
   for (int q = 0; q < kPre; ++q) {
@@ -64,11 +68,11 @@ __device__ __forceinline__ void fetch_cols(const double* base, int ld, int n, in
 __device__ __forceinline__ void put_cols(const double2 pre[kPre], int ldp, double* Us) {
   const int L2 = (ldp - 1) / 2;
   const int p = threadIdx.x % L2;
-  const int col0 = threadIdx.x / L2, cstep = 256 / L2;
+  const int col0 = threadIdx.x / L2, cstep = kThreadsG / L2;
   const int nq = T / cstep;
 #pragma unroll
   for (int q = 0; q < kPre; ++q) {
-    if (q < nq) {
+    if (q < nq && col0 + q * cstep < T) {
       double* dst = Us + (col0 + q * cstep) * ldp + 2 * p;
       dst[0] = pre[q].x;
       dst[1] = pre[q].y;
@@ -76,7 +80,7 @@ __device__ __forceinline__ void put_cols(const double2 pre[kPre], int ldp, doubl
   }
 }
 
-__global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
+__global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
   __shared__ double Uk[T * kMaxLdp];
   __shared__ double Uj[T * kMaxLdp];
   const int kb = blockIdx.x, ch = blockIdx.y;
@@ -84,6 +88,8 @@ __global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
   const int jb0 = (int)(((int64_t)ch * nkb) / nch), jb1 = (int)(((int64_t)(ch + 1) * nkb) / nch);
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
+  const int cg = w & 3;   // column group: columns 16 cg .. 16 cg + 15 of tile kb
+  const int rh = w >> 2;  // row half: rows 32 rh .. 32 rh + 31 of tile jb
   const int ldp = a.ldp;
   const int K4 = (2 * a.d + 3) & ~3;
   const int MB = (2 * a.d + 15) / 16;
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
   }
   const int kl = lane >> 4;
   const bool odd = kl & 1;
-  const int kcol = 16 * w + (lane & 15);  // this lane's column within tile kb
+  const int kcol = 16 * cg + (lane & 15);  // this lane's column within tile kb
   const int kglob = kb * T + kcol;
 
   double2 pre[kPre];
@@ -113,11 +119,11 @@ __global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
     put_cols(pre, ldp, Uj);
     __syncthreads();
     if (jb + 1 < jb1) fetch_cols(a.frame, a.ld, a.n, a.d, (jb + 1) * T, ldp, pre);
-    v4f64 R[4], I[4];
+    v4f64 R[2], I[2];
 #pragma unroll
-    for (int jq = 0; jq < 4; ++jq) {
-      R[jq] = v4f64{0.0, 0.0, 0.0, 0.0};
-      I[jq] = v4f64{0.0, 0.0, 0.0, 0.0};
+    for (int jl = 0; jl < 2; ++jl) {
+      R[jl] = v4f64{0.0, 0.0, 0.0, 0.0};
+      I[jl] = v4f64{0.0, 0.0, 0.0, 0.0};
     }
     for (int kk = 0; kk < K4 / 4; ++kk) {
       const int k = 4 * kk + kl;
@@ -125,61 +131,60 @@ __global__ __launch_bounds__(256, 1) void k_lse_grad(GradArgs a) {
       const double x = Uk[kcol * ldp + (k ^ 1)];
       const double bv = odd ? -x : x;
 #pragma unroll
-      for (int jq = 0; jq < 4; ++jq) {
-        const double av = Uj[(16 * jq + (lane & 15)) * ldp + k];
-        R[jq] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bu, R[jq], 0, 0, 0);
-        I[jq] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, I[jq], 0, 0, 0);
+      for (int jl = 0; jl < 2; ++jl) {
+        const double av = Uj[(32 * rh + 16 * jl + (lane & 15)) * ldp + k];
+        R[jl] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bu, R[jl], 0, 0, 0);
+        I[jl] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, I[jl], 0, 0, 0);
       }
     }
     // B = W o G in the output layout: register v of lane l is row
-    // j = 16 jq + 4 v + l / 16 of tile jb, column kcol
+    // j = 32 rh + 16 jl + 4 v + l / 16 of tile jb, column kcol
 #pragma unroll
-    for (int jq = 0; jq < 4; ++jq)
+    for (int jl = 0; jl < 2; ++jl)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int jglob = jb * T + 16 * jq + 4 * v + kl;
-        const double re = R[jq][v], im = I[jq][v];
+        const int jglob = jb * T + 32 * rh + 16 * jl + 4 * v + kl;
+        const double re = R[jl][v], im = I[jl][v];
         const double xv = re * re + im * im;
         const bool use = valid && jglob != kglob && jglob < a.n && kglob < a.n;
         const double wt = use ? exp((xv - s) * inv_delta - logS) : 0.0;
-        R[jq][v] = wt * re;
-        I[jq][v] = wt * im;
+        R[jl][v] = wt * re;
+        I[jl][v] = wt * im;
       }
-    // P += U_jb B: K runs over the 64 rows j in steps of 4 (t = 4 jq + v)
+    // P += U_jb B over this wave's rows: K runs over them in steps of 4
 #pragma unroll
-    for (int jq = 0; jq < 4; ++jq)
+    for (int jl = 0; jl < 2; ++jl)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * jq + 4 * v + kl;
+        const int j = 32 * rh + 16 * jl + 4 * v + kl;
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb) {
           if (mb < MB) {
             const double am = Uj[j * ldp + 16 * mb + (lane & 15)];
-            P1[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, R[jq][v], P1[mb], 0, 0, 0);
-            P2[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, I[jq][v], P2[mb], 0, 0, 0);
+            P1[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, R[jl][v], P1[mb], 0, 0, 0);
+            P2[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, I[jl][v], P2[mb], 0, 0, 0);
           }
         }
       }
   }
-  // partial slot (kb, ch): [2][64 columns][2d rows]
-  double* dst = a.partial + ((size_t)(kb * nch + ch) * 2) * T * (2 * a.d);
+  // partial slot (kb, ch, rh): [2][64 columns][2d rows]
+  double* dst = a.partial + ((size_t)((kb * nch + ch) * 2 + rh) * 2) * T * (2 * a.d);
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     if (mb < MB) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * mb + 4 * v + kl;
-        const int col = 16 * w + (lane & 15);
         if (m < 2 * a.d) {
-          dst[(size_t)col * (2 * a.d) + m] = P1[mb][v];
-          dst[(size_t)T * (2 * a.d) + (size_t)col * (2 * a.d) + m] = P2[mb][v];
+          dst[(size_t)kcol * (2 * a.d) + m] = P1[mb][v];
+          dst[(size_t)T * (2 * a.d) + (size_t)kcol * (2 * a.d) + m] = P2[mb][v];
         }
       }
     }
   }
 }
 
-// One wave per column k: add the slots (kb, 0 .. nch - 1) in order, combine
+// One wave per column k: add the slots (kb, ch, rh) in order, combine
 // into D_k, project and scale.  Lane i takes entries i, i + 64, ...
 __global__ __launch_bounds__(64) void k_lse_grad_finish(GradArgs a, int nch) {
   const int k = blockIdx.x;
@@ -198,8 +203,8 @@ __global__ __launch_bounds__(64) void k_lse_grad_finish(GradArgs a, int nch) {
   for (int q = 0; q < 8; ++q) dre[q] = dim[q] = 0.0;
   for (int i = lane, q = 0; i < d; i += 64, ++q) {
     double p1e = 0.0, p1o = 0.0, p2e = 0.0, p2o = 0.0;
-    for (int ch = 0; ch < nch; ++ch) {
-      const double* src = a.partial + ((size_t)(kb * nch + ch) * 2) * T * (2 * d) + (size_t)kc * (2 * d);
+    for (int sl = 0; sl < 2 * nch; ++sl) {  // slots (ch, rh) in order
+      const double* src = a.partial + ((size_t)(kb * nch * 2 + sl) * 2) * T * (2 * d) + (size_t)kc * (2 * d);
       p1e += src[2 * i];
       p1o += src[2 * i + 1];
       p2e += src[(size_t)T * (2 * d) + 2 * i];
@@ -235,7 +240,7 @@ int lse_grad_chunks(int nkb) {
 hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s) {
   const int nkb = (a.n + T - 1) / T;
   const int nch = lse_grad_chunks(nkb);
-  hipLaunchKernelGGL(k_lse_grad, dim3(nkb, nch), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_lse_grad, dim3(nkb, nch), dim3(kThreadsG), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lse_grad_finish, dim3(a.n), dim3(64), 0, s, a, nch);
