@@ -42,6 +42,7 @@ from .coherence import (  # noqa: F401
     gram,
     coherence,
     coherence_sq_upper,
+    coherence_pair,
     coherence_bruteforce,
     welch_bound,
     orthoplex_bound,

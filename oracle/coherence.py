@@ -71,6 +71,24 @@ def coherence(Phi, normalize=True):
     return float(np.max(np.abs(G[iu])))
 
 
+def coherence_pair(Phi):
+    """A pair attaining the coherence: (mu, j, k) with j < k and
+    |<phi_j, phi_k>| = mu, the first such pair in the order j * N + k (the
+    pair is not unique in general; the value is).  A zero or non-finite
+    column gives (inf, -1, -1)."""
+    Phi, norms = normalize_columns(Phi)
+    if not np.all(np.isfinite(norms) & (norms > 0.0)):
+        return math.inf, -1, -1
+    G = gram(Phi)
+    N = G.shape[0]
+    if N < 2:
+        raise ValueError("coherence needs at least two vectors")
+    iu = np.triu_indices(N, k=1)          # row-major order: increasing j * N + k
+    g = G[iu]
+    q = int(np.argmax(g.real * g.real + g.imag * g.imag))
+    return float(abs(g[q])), int(iu[0][q]), int(iu[1][q])
+
+
 def coherence_bruteforce(Phi):
     """The same definition written as explicit loops over pairs j < k, with
     each inner product summed term by term.  For tiny frames only."""

@@ -152,3 +152,45 @@ def test_zero_and_nonfinite_columns():
     assert oracle.coherence(F) == math.inf
     _, norms = oracle.normalize_columns(inputs.random_frame(6, 3, 2))
     assert np.all(norms > 0)
+
+
+def _pair_bruteforce(F):
+    """Loops over j < k in order, keeping the first pair of largest squared
+    modulus (inner products summed term by term)."""
+    d, n = F.shape
+    cols = [F[:, j] / math.sqrt(sum(abs(z) ** 2 for z in F[:, j])) for j in range(n)]
+    best, bj, bk = -1.0, -1, -1
+    for j in range(n):
+        for k in range(j + 1, n):
+            acc = 0j
+            for i in range(d):
+                acc += cols[j][i].conjugate() * cols[k][i]
+            m = acc.real * acc.real + acc.imag * acc.imag
+            if m > best:
+                best, bj, bk = m, j, k
+    return math.sqrt(best), bj, bk
+
+
+@pytest.mark.parametrize("n,d,seed", [(2, 1, 0), (5, 3, 1), (9, 2, 2), (12, 4, 3), (7, 7, 4)])
+def test_coherence_pair_bruteforce(n, d, seed):
+    F = inputs.random_frame(n, d, seed=seed)
+    mu, j, k = oracle.coherence_pair(F)
+    mb, bj, bk = _pair_bruteforce(F)
+    assert abs(mu - mb) <= 1e-13 and (j, k) == (bj, bk) and j < k
+    assert abs(mu - oracle.coherence(F)) <= 1e-15
+
+
+def test_coherence_pair_ties_and_invalid():
+    """An orthonormal basis plus one repeated vector: the only nonzero pair
+    is the repeat; e_1, e_2 and (e_1 + e_2) tie exactly at 1/sqrt 2 on the
+    pairs (0, 2) and (1, 2), so the first, (0, 2), is returned; a zero
+    column gives (inf, -1, -1)."""
+    F = np.eye(4, dtype=complex)
+    F = np.concatenate([F, F[:, 2:3] * 1j], axis=1)
+    mu, j, k = oracle.coherence_pair(F)
+    assert (j, k) == (2, 4) and abs(mu - 1.0) <= 1e-15
+    mu, j, k = oracle.coherence_pair(np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 1.0]], dtype=complex))
+    assert (j, k) == (0, 2) and abs(mu - math.sqrt(0.5)) <= 2.3e-16   # the normalised entries are rounded
+    F = inputs.random_frame(6, 3, seed=1)
+    F[:, 3] = 0
+    assert oracle.coherence_pair(F) == (math.inf, -1, -1)
