@@ -159,6 +159,19 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
                                double* mu_out, void* workspace, size_t workspace_bytes,
                                hipStream_t stream);
 
+/*
+ * A pair attaining the coherence (section I definition, FP64): *mu_out
+ * (device) <- mu as trstmi_coherence computes it in TRSTMI_MODE_FP64, and
+ * pair_out[0..1] (device int64) <- (j, k), j < k, the first pair in the
+ * order j * n + k whose |<phi_j, phi_k>|^2 has exactly the bits of the
+ * maximum (the pair is not unique in general; the value is).  A zero or
+ * non-finite column gives +inf and (-1, -1).  Costs a second pass over the
+ * Gram tiles.  Workspace: trstmi_coherence_workspace_bytes(n, d,
+ * TRSTMI_MODE_FP64).  Stream-ordered.
+ */
+trstmi_status trstmi_coherence_pair(int64_t n, int64_t d, const double* frame, double* mu_out, int64_t* pair_out,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Bytes of workspace trstmi_lse needs for an n x d frame. */
 size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d);
 
@@ -462,6 +475,12 @@ trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* 
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* trstmi_last_error(void);
+
+/* Releases the library's internal state (the pooled HIP events of kernel
+ * timing, after waiting for any still pending; totals are cleared and timing
+ * is switched off).  Call it before the process releases its devices; the
+ * library stays usable and recreates what it needs on demand. */
+trstmi_status trstmi_shutdown(void);
 
 /* ABI version of this library (increases when a declaration changes). */
 int32_t trstmi_abi_version(void);

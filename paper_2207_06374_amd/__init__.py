@@ -106,6 +106,26 @@ def coherence(frame, n, d, mode=MODE_FP64, mu_out=None, workspace=None, stream=N
     return mu_out
 
 
+def coherence_pair(frame, n, d, workspace=None, stream=None):
+    """FP64 coherence of a device frame and a pair (j, k), j < k, attaining
+    it (the first in the order j * n + k).  Returns device tensors (mu of
+    shape (1,), pair int64 of shape (2,))."""
+    torch = _torch()
+    mu = torch.empty(1, dtype=torch.float64, device=frame.device)
+    pair = torch.empty(2, dtype=torch.int64, device=frame.device)
+    if workspace is None:
+        need = _abi.lib().trstmi_coherence_workspace_bytes(int(n), int(d), MODE_FP64)
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=frame.device)
+    _abi.check(_abi.lib().trstmi_coherence_pair(int(n), int(d), _ptr(frame), _ptr(mu), _ptr(pair), _ptr(workspace),
+                                                workspace.numel(), _stream(stream)), "trstmi_coherence_pair")
+    return mu, pair
+
+
+def shutdown():
+    """Release the library's internal state (pooled timing events)."""
+    _abi.check(_abi.lib().trstmi_shutdown(), "trstmi_shutdown")
+
+
 def lse_workspace_bytes(n, d):
     return _abi.lib().trstmi_lse_workspace_bytes(int(n), int(d))
 

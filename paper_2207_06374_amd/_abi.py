@@ -129,6 +129,7 @@ SIGNATURES = {
     "trstmi_workspace_bytes": (_sz, [_P(Params)]),
     "trstmi_coherence_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "trstmi_coherence": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "trstmi_coherence_pair": (_i32, [_i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_lse_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_lse": (_i32, [_i64, _i64, _vp, ctypes.c_double, _i32, _vp, _vp, _sz, _vp]),
     "trstmi_lse_grad_workspace_bytes": (_sz, [_i64, _i64]),
@@ -156,6 +157,7 @@ SIGNATURES = {
     "trstmi_timing_reset": (_i32, []),
     "trstmi_timing_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_i64)]),
     "trstmi_last_error": (ctypes.c_char_p, []),
+    "trstmi_shutdown": (_i32, []),
     "trstmi_abi_version": (_i32, []),
 }
 

@@ -627,6 +627,35 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
   return TRSTMI_OK;
 }
 
+trstmi_status trstmi_coherence_pair(int64_t n, int64_t d, const double* frame, double* mu_out, int64_t* pair_out,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (!frame || !mu_out || !pair_out) return fail(TRSTMI_E_INVALID_ARG, "frame, mu_out and pair_out must be device pointers");
+  if (((uintptr_t)frame & 15) || ((uintptr_t)mu_out & 7) || ((uintptr_t)pair_out & 7))
+    return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_coherence_workspace_bytes(n, d, TRSTMI_MODE_FP64);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  char* ws = (char*)workspace;
+  const int32_t ld = ld_mode(d, TRSTMI_MODE_FP64);
+  uint64_t* mx = (uint64_t*)(ws + align256((size_t)n * ld * 8));
+  PerturbArgs pa{};
+  pa.base = frame;
+  pa.have_z = 0;
+  pa.n = n;
+  pa.d = (int32_t)d;
+  pa.out = ws;
+  pa.out_kind = kOutF64;
+  pa.out_ld = ld;
+  pa.out_slot_stride = n * ld;
+  pa.zero_max = mx;
+  TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
+  GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
+  TRY_HIP(launch_gram_f64(g, 1, stream), "gram_f64");
+  TRY_HIP(launch_gram_f64_pair(g, mx + 1, mu_out, pair_out, stream), "gram_f64_pair");
+  return TRSTMI_OK;
+}
+
 size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d) {
   if (check_size(n, d)) return 0;
   const int64_t nt = (n + kTileF64 - 1) / kTileF64;
@@ -1291,6 +1320,23 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
-int32_t trstmi_abi_version(void) { return 6; }
+trstmi_status trstmi_shutdown(void) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> g(T.mu);
+  for (auto& r : T.pending) {
+    (void)hipEventSynchronize(r.stop);
+    T.pool.push_back(r.start);
+    T.pool.push_back(r.stop);
+  }
+  T.pending.clear();
+  for (hipEvent_t e : T.pool) (void)hipEventDestroy(e);
+  T.pool.clear();
+  T.totals.clear();
+  T.on = false;
+  T.only.clear();
+  return TRSTMI_OK;
+}
+
+int32_t trstmi_abi_version(void) { return 7; }
 
 }  // extern "C"

@@ -48,9 +48,13 @@ struct SumExp {
   double* partial;         // [tile][2]: block sum S_b, block maximum x_b
 };
 
-template <bool SUMEXP>
+// Epilogues of the tile: the maximum, the smooth maximum, or the search for
+// the first pair attaining a known maximum.
+enum { kEpiMax = 0, kEpiLse = 1, kEpiPair = 2 };
+
+template <int EPI>
 __device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int bi, int bj, double* As, double* Bs,
-                                              uint64_t* red, const SumExp& se) {
+                                              uint64_t* red, const SumExp& se, uint64_t* pair = nullptr) {
   const double* base = (const double*)a.cand + (size_t)slot * a.slot_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -115,7 +119,31 @@ __device__ __forceinline__ void gram_f64_tile(const GramArgs& a, int slot, int b
     }
   }
 
-  if constexpr (SUMEXP) {
+  if constexpr (EPI == kEpiPair) {
+    // the first pair (in the order i * n + j) whose |G|^2 has the bits of the
+    // maximum found by the maximum epilogue with the same arithmetic
+    const uint64_t target = a.cand_max[slot];
+    uint64_t first = ~0ull;
+    if (!skip) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = bi * T + wr * 32 + r * 16 + 4 * v + (lane >> 4);
+            const int j = bj * T + wc * 32 + c * 16 + (lane & 15);
+            const double re = accR[r][c][v], im = accI[r][c][v];
+            const uint64_t mb = (uint64_t)__double_as_longlong(re * re + im * im);
+            const uint64_t q = (uint64_t)i * (uint64_t)a.n + (uint64_t)j;
+            if (i < j && j < a.n && mb == target && q < first) first = q;
+          }
+    }
+    first = ~wave_max_u64(~first);
+    if (lane == 0 && first != ~0ull) atomicMin((unsigned long long*)pair, (unsigned long long)first);
+    return;
+  }
+  if constexpr (EPI == kEpiLse) {
     // the block's maximum of |G|^2 (bit patterns: NaN above +inf), then its sum
     uint64_t bm = 0;
     if (!skip) {
@@ -203,7 +231,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramArgs a) {
   __shared__ uint64_t red[4];
   int bi, bj;
   tile_decode(blockIdx.x, a.nt, bi, bj);
-  gram_f64_tile<false>(a, blockIdx.y, bi, bj, As, Bs, red, SumExp{});
+  gram_f64_tile<kEpiMax>(a, blockIdx.y, bi, bj, As, Bs, red, SumExp{});
 }
 
 __global__ __launch_bounds__(256) void k_gram_f64_lse(GramArgs a, SumExp se) {
@@ -212,7 +240,33 @@ __global__ __launch_bounds__(256) void k_gram_f64_lse(GramArgs a, SumExp se) {
   __shared__ uint64_t red[4];
   int bi, bj;
   tile_decode(blockIdx.x, a.nt, bi, bj);
-  gram_f64_tile<true>(a, 0, bi, bj, As, Bs, red, se);
+  gram_f64_tile<kEpiLse>(a, 0, bi, bj, As, Bs, red, se);
+}
+
+__global__ __launch_bounds__(256) void k_gram_f64_pair(GramArgs a, uint64_t* pair) {
+  __shared__ double As[T * LDA];
+  __shared__ double Bs[T * LDA];
+  __shared__ uint64_t red[4];
+  int bi, bj;
+  tile_decode(blockIdx.x, a.nt, bi, bj);
+  gram_f64_tile<kEpiPair>(a, 0, bi, bj, As, Bs, red, SumExp{}, pair);
+}
+
+__global__ void k_pair_init(uint64_t* pair) { *pair = ~0ull; }
+
+// mu = sqrt(max |G|^2) and the pair (j, k) = (q / n, q mod n); (-1, -1) and
+// +inf for a zero or non-finite column.
+__global__ void k_pair_finish(const uint64_t* max_bits, const uint64_t* pair, int64_t n, double* mu, int64_t* jk) {
+  const uint64_t b = *max_bits, q = *pair;
+  if (b >= kInfBits64 || q == ~0ull) {
+    *mu = __builtin_inf();
+    jk[0] = -1;
+    jk[1] = -1;
+    return;
+  }
+  *mu = sqrt(__longlong_as_double((int64_t)b));
+  jk[0] = (int64_t)(q / (uint64_t)n);
+  jk[1] = (int64_t)(q % (uint64_t)n);
 }
 
 // F = s + delta log S with S = sum_b S_b exp((x_b - s) / delta), added in a
@@ -254,6 +308,17 @@ __global__ __launch_bounds__(256) void k_lse_finish(const uint64_t* s_bits, cons
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s) {
   const int tiles = a.nt * (a.nt + 1) / 2;
   hipLaunchKernelGGL(k_gram_f64, dim3(tiles, slots), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_f64_pair(const GramArgs& a, uint64_t* pair, double* mu, int64_t* jk, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_init, dim3(1), dim3(1), 0, s, pair);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int tiles = a.nt * (a.nt + 1) / 2;
+  hipLaunchKernelGGL(k_gram_f64_pair, dim3(tiles), dim3(256), 0, s, a, pair);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pair_finish, dim3(1), dim3(1), 0, s, a.cand_max, pair, (int64_t)a.n, mu, jk);
   return hipGetLastError();
 }
 

@@ -163,6 +163,10 @@ int batch_lds_floats();
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
+// After launch_gram_f64 on one frame (slot 0): the first pair j < k in the
+// order j * n + k whose |G|^2 has the maximum's bits, into *pair (scratch),
+// then mu = sqrt(max) and jk = (j, k) (or +inf and (-1, -1)).
+hipError_t launch_gram_f64_pair(const GramArgs& a, uint64_t* pair, double* mu, int64_t* jk, hipStream_t s);
 // Smooth maximum (one frame, slot 0), one pass over the tiles: per block
 // (S_b, x_b) into partial[tile][2] and the maximum |G|^2 bits into
 // a.cand_max[0] (zeroed beforehand); then F = s + delta log S into

@@ -287,3 +287,16 @@ def test_miso_argument_checks(L):
     assert call(wsb=need - 1) == abi.E_WORKSPACE
     assert call(ws=None) == abi.E_WORKSPACE
     assert L.trstmi_abi_version() >= 5
+
+
+def test_coherence_pair_and_shutdown_without_device(L):
+    need = L.trstmi_coherence_workspace_bytes(100, 8, abi.MODE_FP64)
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    assert L.trstmi_coherence_pair(1, 8, p, p, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence_pair(100, 8, None, p, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence_pair(100, 8, p, p, None, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence_pair(100, 8, p, p, ctypes.c_void_p(4100), ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence_pair(100, 8, p, p, p, ws, need - 1, None) == abi.E_WORKSPACE
+    assert L.trstmi_shutdown() == abi.OK
+    assert L.trstmi_abi_version() >= 7

@@ -161,3 +161,46 @@ def test_round_bf16_matches_oracle_bitwise():
     g = lib.round_bf16(torch.from_numpy(y).cuda()).cpu().numpy().view(np.uint16)
     assert (g[0] & 0x7F80) == 0x7F80 and (g[0] & 0x7F) != 0
     assert g[1] == 0x7F80 and g[2] == 0xFF80
+
+
+def _gpu_pair(F):
+    d, n = F.shape
+    mu, pair = lib.coherence_pair(lib.frame_to_device(F), n, d)
+    return float(mu.item()), tuple(int(x) for x in pair.cpu().numpy())
+
+
+@pytest.mark.parametrize("n,d", [(2, 1), (3, 2), (16, 4), (65, 3), (129, 5), (257, 33), (300, 64), (70, 200),
+                                 (1000, 32)])
+def test_coherence_pair_matches_oracle(n, d):
+    """The pair's modulus is the coherence; on random frames the maximum is
+    unique by a wide margin, so the pair is the oracle's."""
+    F = inputs.random_frame(n, d, seed=n + 17 * d)
+    mu, (j, k) = _gpu_pair(F)
+    ref, rj, rk = oracle.coherence_pair(F)
+    print(f"n={n} d={d} mu={mu!r} pair=({j},{k}) ref=({rj},{rk})", flush=True)
+    assert abs(mu - ref) <= 1e-12 and 0 <= j < k < n
+    Phi, _ = oracle.normalize_columns(F)
+    assert abs(abs(np.vdot(Phi[:, j], Phi[:, k])) - ref) <= 1e-12
+    G = np.abs(Phi.conj().T @ Phi)
+    top = np.sort(G[np.triu_indices(n, 1)])[-2:]
+    if top.size == 1 or top[1] - top[0] > 1e-12:
+        assert (j, k) == (rj, rk)
+    assert _gpu_mu(F, lib.MODE_FP64) == mu
+
+
+def test_coherence_pair_ties_invalid_and_full_size():
+    mu, pair = _gpu_pair(np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 1.0]], dtype=complex))
+    assert pair == (0, 2) and abs(mu - math.sqrt(0.5)) <= 2.3e-16
+    for name in sorted(frames.KNOWN):
+        build, ref = frames.KNOWN[name]
+        F = build()
+        mu, (j, k) = _gpu_pair(F)
+        Phi, _ = oracle.normalize_columns(F)
+        assert abs(mu - ref) <= 1e-12 and 0 <= j < k and abs(abs(np.vdot(Phi[:, j], Phi[:, k])) - ref) <= 1e-12
+    F = inputs.random_frame(40, 5, seed=3)
+    F[:, 17] = 0
+    assert _gpu_pair(F) == (math.inf, (-1, -1))
+    F = oracle.haar_init(oracle.Params(n=4096, d=64, seed=0)).frame
+    mu, pair = _gpu_pair(F)
+    ref, rj, rk = oracle.coherence_pair(F)
+    assert abs(mu - ref) <= 1e-12 and pair == (rj, rk)
