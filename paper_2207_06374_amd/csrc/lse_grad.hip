@@ -80,7 +80,17 @@ __device__ __forceinline__ void put_cols(const double2 pre[kPre], int ldp, doubl
   }
 }
 
+// MB = 16-row blocks of the 2d output rows (1 .. 8).  The second product's
+// k steps (8 per wave and tile) are spread over Q = 8 / MB accumulator sets
+// per row block, so that for small d they form Q independent chains instead
+// of one serial chain; the sets are added in a fixed order at the end.  The
+// LDS column stride follows from MB: 2d rounded up to a power of two >= 16,
+// plus one.
+template <int MB>
 __global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
+  constexpr int Q = 8 / MB;
+  constexpr int NSL = MB * Q;
+  constexpr int LDP = (MB <= 1 ? 16 : MB <= 2 ? 32 : MB <= 4 ? 64 : 128) + 1;
   __shared__ double Uk[T * kMaxLdp];
   __shared__ double Uj[T * kMaxLdp];
   const int kb = blockIdx.x, ch = blockIdx.y;
@@ -90,9 +100,8 @@ __global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
   const int w = threadIdx.x >> 6;
   const int cg = w & 3;   // column group: columns 16 cg .. 16 cg + 15 of tile kb
   const int rh = w >> 2;  // row half: rows 32 rh .. 32 rh + 31 of tile jb
-  const int ldp = a.ldp;
+  constexpr int ldp = LDP;
   const int K4 = (2 * a.d + 3) & ~3;
-  const int MB = (2 * a.d + 15) / 16;
   const uint64_t sb = *a.s_bits;
   const bool valid = sb < kInfBits64;
   const double s = __longlong_as_double((int64_t)sb);
@@ -101,11 +110,11 @@ __global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
 
   stage_cols(a.frame, a.ld, a.n, a.d, kb * T, ldp, Uk);
 
-  v4f64 P1[8], P2[8];
+  v4f64 P1[NSL], P2[NSL];
 #pragma unroll
-  for (int mb = 0; mb < 8; ++mb) {
-    P1[mb] = v4f64{0.0, 0.0, 0.0, 0.0};
-    P2[mb] = v4f64{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < NSL; ++q) {
+    P1[q] = v4f64{0.0, 0.0, 0.0, 0.0};
+    P2[q] = v4f64{0.0, 0.0, 0.0, 0.0};
   }
   const int kl = lane >> 4;
   const bool odd = kl & 1;
@@ -157,28 +166,33 @@ __global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = 32 * rh + 16 * jl + 4 * v + kl;
+        const int sl = ((4 * jl + v) % Q) * MB;  // this k step's accumulator set
 #pragma unroll
-        for (int mb = 0; mb < 8; ++mb) {
-          if (mb < MB) {
-            const double am = Uj[j * ldp + 16 * mb + (lane & 15)];
-            P1[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, R[jl][v], P1[mb], 0, 0, 0);
-            P2[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, I[jl][v], P2[mb], 0, 0, 0);
-          }
+        for (int mb = 0; mb < MB; ++mb) {
+          const double am = Uj[j * ldp + 16 * mb + (lane & 15)];
+          P1[sl + mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, R[jl][v], P1[sl + mb], 0, 0, 0);
+          P2[sl + mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, I[jl][v], P2[sl + mb], 0, 0, 0);
         }
       }
   }
+  // add the accumulator sets in order
+#pragma unroll
+  for (int q = 1; q < Q; ++q)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      P1[mb] += P1[q * MB + mb];
+      P2[mb] += P2[q * MB + mb];
+    }
   // partial slot (kb, ch, rh): [2][64 columns][2d rows]
   double* dst = a.partial + ((size_t)((kb * nch + ch) * 2 + rh) * 2) * T * (2 * a.d);
 #pragma unroll
-  for (int mb = 0; mb < 8; ++mb) {
-    if (mb < MB) {
+  for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = 16 * mb + 4 * v + kl;
-        if (m < 2 * a.d) {
-          dst[(size_t)kcol * (2 * a.d) + m] = P1[mb][v];
-          dst[(size_t)T * (2 * a.d) + (size_t)kcol * (2 * a.d) + m] = P2[mb][v];
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int m = 16 * mb + 4 * v + kl;
+      if (m < 2 * a.d) {
+        dst[(size_t)kcol * (2 * a.d) + m] = P1[mb][v];
+        dst[(size_t)T * (2 * a.d) + (size_t)kcol * (2 * a.d) + m] = P2[mb][v];
       }
     }
   }
@@ -240,7 +254,17 @@ int lse_grad_chunks(int nkb) {
 hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s) {
   const int nkb = (a.n + T - 1) / T;
   const int nch = lse_grad_chunks(nkb);
-  hipLaunchKernelGGL(k_lse_grad, dim3(nkb, nch), dim3(kThreadsG), 0, s, a);
+  const dim3 grid(nkb, nch), block(kThreadsG);
+  switch ((2 * a.d + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_lse_grad<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_lse_grad<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_lse_grad<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_lse_grad<4>, grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_lse_grad<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_lse_grad<6>, grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL(k_lse_grad<7>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_lse_grad<8>, grid, block, 0, s, a); break;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lse_grad_finish, dim3(a.n), dim3(64), 0, s, a, nch);
