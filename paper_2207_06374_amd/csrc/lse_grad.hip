@@ -246,9 +246,30 @@ __global__ __launch_bounds__(64) void k_lse_grad_finish(GradArgs a, int nch) {
 }  // namespace
 
 int lse_grad_chunks(int nkb) {
-  // about 512 blocks: row tiles split into at most nkb runs
-  int nch = (512 + nkb - 1) / nkb;
-  return nch < 1 ? 1 : (nch > nkb ? nkb : nch);
+  // One 512-thread block fits a CU (LDS), so blocks run in rounds of 256
+  // (the CU count).  Row tiles are split into nch runs: at least enough for
+  // about 512 blocks, at most runs of 4 tiles, and within that range the
+  // smallest count whose grid fills its last round to 97 % (else the best
+  // fill).  At N = 18000 (282 tiles a side), 282 x 2 = 564 blocks took
+  // three rounds with the last one 22 % full; 282 x 8 = 2256 fill nine
+  // rounds to 98 %.
+  constexpr int kCUs = 256;
+  int lo = (512 + nkb - 1) / nkb;
+  lo = lo < 1 ? 1 : (lo > nkb ? nkb : lo);
+  const int hi = nkb / 4 > lo ? nkb / 4 : lo;
+  int best = lo;
+  double best_fill = -1.0;
+  for (int c = lo; c <= hi; ++c) {
+    const int64_t blocks = (int64_t)nkb * c;
+    const int64_t rounds = (blocks + kCUs - 1) / kCUs;
+    const double f = (double)blocks / (double)(rounds * kCUs);
+    if (f >= 0.97) return c;
+    if (f > best_fill) {
+      best_fill = f;
+      best = c;
+    }
+  }
+  return best;
 }
 
 hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s) {
