@@ -305,12 +305,12 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // (low 16 bits exactly 0x8000) or an FP32 subnormal (class mask 0x90: the
 // negative and positive subnormal classes of v_cmp_class_f32).
 __device__ __forceinline__ bool bf16_via_f32_unsafe(float f) {
-  return ((__float_as_uint(f) & 0xFFFFu) == 0x8000u) | __builtin_amdgcn_classf(f, 0x90);
+  return (unsigned)((__float_as_uint(f) & 0xFFFFu) == 0x8000u) | (unsigned)__builtin_amdgcn_classf(f, 0x90);
 }
 
 __device__ __forceinline__ uint32_t bf16x2_rne(double x0, double x1) {
   const f32x2 f = {(float)x0, (float)x1};
-  const bool slow = bf16_via_f32_unsafe(f[0]) | bf16_via_f32_unsafe(f[1]);
+  const bool slow = (unsigned)bf16_via_f32_unsafe(f[0]) | (unsigned)bf16_via_f32_unsafe(f[1]);
   if (__ballot(slow) && slow)
     return (uint32_t)f64_to_bf16_rne(x0) | ((uint32_t)f64_to_bf16_rne(x1) << 16);
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
