@@ -89,7 +89,10 @@ def _gpu_grad(F, delta):
     return out.cpu().numpy().tolist(), lib.frame_from_device(g, n, d)
 
 
-GRAD_SHAPES = [(2, 1), (3, 2), (16, 4), (65, 3), (100, 7), (129, 5), (200, 16), (257, 33), (300, 64)]
+# every output row-block count MB = ceil(2d / 16) of the kernel (d = 8 | 9,
+# 16 | 17, 32 | 33, 40 | 41, 48, 56, 64), ragged tiles
+GRAD_SHAPES = [(2, 1), (3, 2), (16, 4), (65, 3), (100, 7), (150, 8), (90, 9), (129, 5), (200, 16), (130, 20),
+               (77, 32), (257, 33), (140, 45), (70, 56), (300, 64)]
 
 
 @pytest.mark.parametrize("n,d", GRAD_SHAPES)
@@ -123,4 +126,16 @@ def test_lse_grad_invalid_repeatable_and_full_size():
     F = oracle.haar_init(p).frame
     (s, f), g = _gpu_grad(F, 1e-3)
     g_ref = oracle.smooth_max_grad(F, 1e-3)
+    assert float(np.max(np.abs(g - g_ref))) <= 2e-11 * max(1.0, float(np.max(np.abs(g_ref))))
+
+
+def test_lse_grad_many_row_runs():
+    """A frame whose row tiles are split into many runs per column block (47
+    tiles a side), against the oracle."""
+    n, d, delta = 3000, 4, 1e-2
+    F = inputs.random_frame(n, d, seed=31)
+    (s, f), g = _gpu_grad(F, delta)
+    s_ref, f_ref = oracle.smooth_max(F, delta)
+    g_ref = oracle.smooth_max_grad(F, delta)
+    assert abs(s - s_ref) <= 1e-14 and abs(f - f_ref) <= _tol(n, delta)
     assert float(np.max(np.abs(g - g_ref))) <= 2e-11 * max(1.0, float(np.max(np.abs(g_ref))))

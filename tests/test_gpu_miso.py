@@ -47,6 +47,7 @@ def _check_channels(C, H, idx, gain, dist, cols=None):
 
 
 SHAPES = [(1, 4, 100), (2, 1, 65), (16, 4, 1000), (64, 8, 777), (100, 7, 130), (200, 33, 300), (65, 16, 64),
+          (70, 63, 129), (90, 65, 130),
           (300, 128, 70), (17, 512, 65), (1000, 3, 2049), (4096, 64, 200)]
 
 
