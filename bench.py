@@ -314,9 +314,10 @@ def run_serving(lib, count, max_steps, pool_gib):
             for r in inputs.serving_requests(count, seed=1)]
     srv = serve.Server(pool_bytes=int(pool_gib * 2 ** 30), max_active=16, chunk=64, candidates=64, mode="bf16")
     stats = srv.run(reqs, progress=log)
+    srv.close()
     stats["workload"] = (f"{count} requests, Poisson arrivals mean gap 5 ms, d in {{8,16,32,64,128}}, N in [2d, 8d], "
                          f"target 1.10 x Welch or {max_steps} steps, 64 candidates, BF16 screen + FP64 recheck, "
-                         f"pool {pool_gib} GiB, 16 slots (one stream each)")
+                         f"pool {pool_gib} GiB, native server with 16 slots (a thread and a stream each)")
     return stats
 
 

@@ -476,6 +476,97 @@ trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* 
 /* Message of the last failed call on this thread ("" if none). */
 const char* trstmi_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Serving form: a solve server with continuous admission on one GPU.
+ * Requests are queued on submission; slot threads (each with a HIP stream of
+ * its own, default priority) take the request at the head of the queue as
+ * soon as its footprint fits in the caller's device pool, run
+ * trstmi_init_haar and trstmi_solve in that range, and release it.  First in
+ * line is served first; a request larger than the pool is rejected at once.
+ * Each result is what the same request gives solved alone (its own seed and
+ * stream id).
+ * ------------------------------------------------------------------------- */
+enum {
+  TRSTMI_REQ_QUEUED = 0,
+  TRSTMI_REQ_RUNNING = 1,
+  TRSTMI_REQ_DONE = 2,     /* finished states from here on */
+  TRSTMI_REQ_ERROR = 3,
+  TRSTMI_REQ_REJECTED = 4,
+  TRSTMI_REQ_CANCELLED = 5
+};
+
+typedef struct trstmi_server trstmi_server;  /* opaque */
+
+typedef struct {
+  void* pool;              /* device memory owned by the caller, 256-byte aligned, kept until destroy */
+  uint64_t pool_bytes;     /* >= 256 */
+  int32_t slots;           /* solves at once, 1 .. 64 */
+  int32_t chunk;           /* steps per captured graph of trstmi_solve, >= 1 */
+  int32_t candidates;      /* per step, >= 1 */
+  int32_t mode;            /* TRSTMI_MODE_* */
+  int32_t recheck_topk;    /* BF16 screen: candidates re-evaluated in FP64, >= 1 */
+  int32_t reserved0;
+  double radius0;          /* > 0 */
+  double target_factor;    /* default target = target_factor x Welch bound, >= 0 */
+} trstmi_server_params;
+
+typedef struct {
+  int64_t n, d;
+  uint64_t seed, stream_id;  /* the random start and perturbations (each < 2^32) */
+  double target_mu;          /* NaN: target_factor x Welch(n, d); <= 0: no target */
+  int64_t max_steps;
+} trstmi_request;
+
+typedef struct {
+  int32_t status;          /* TRSTMI_REQ_* */
+  int32_t reached;         /* done with mu <= target_mu */
+  double mu;               /* exact FP64 coherence of the final frame (NaN until done) */
+  int64_t steps;
+  double target_mu;
+  double queue_s;          /* submission to admission (NaN if never admitted) */
+  double run_s;            /* admission to completion (NaN until finished) */
+  uint64_t footprint;      /* bytes of the pool the request holds while it runs */
+} trstmi_request_result;
+
+typedef struct {
+  uint64_t pool_capacity, pool_used, pool_peak;
+  int32_t active, queued;
+  int64_t submitted;
+} trstmi_server_stats;
+
+/* Bytes of pool one request with these parameters holds while it runs
+ * (workspace, frame and state scalars, each rounded up to 256 bytes); 0 if
+ * the parameters are invalid. */
+size_t trstmi_request_footprint(const trstmi_params* p);
+
+/* Starts a server (its slot threads and their streams) on the current
+ * device; *out receives it. */
+trstmi_status trstmi_server_create(const trstmi_server_params* params, trstmi_server** out);
+
+/* Queues a request; *id (host) receives its id.  A request that cannot run
+ * (invalid sizes, or a footprint above the pool) is recorded as
+ * TRSTMI_REQ_REJECTED with a message (read it through poll). */
+trstmi_status trstmi_server_submit(trstmi_server* server, const trstmi_request* request, int64_t* id);
+
+/* Current state of a request, without waiting.  For a request that ended in
+ * an error or was rejected, trstmi_last_error() then holds its message. */
+trstmi_status trstmi_server_poll(trstmi_server* server, int64_t id, trstmi_request_result* out);
+
+/* Waits until the request has finished (any finished state) or timeout_s
+ * seconds have passed (timeout_s < 0: no limit), then reports as poll. */
+trstmi_status trstmi_server_wait(trstmi_server* server, int64_t id, double timeout_s,
+                                 trstmi_request_result* out);
+
+/* Removes a still-queued request (TRSTMI_E_INVALID_ARG once it runs). */
+trstmi_status trstmi_server_cancel(trstmi_server* server, int64_t id);
+
+/* Pool use (now and peak), running and queued requests, submissions. */
+trstmi_status trstmi_server_get_stats(trstmi_server* server, trstmi_server_stats* out);
+
+/* Lets the running requests finish, cancels the queued ones, joins the slot
+ * threads and frees the server (the pool stays the caller's). */
+trstmi_status trstmi_server_destroy(trstmi_server* server);
+
 /* Releases the library's internal state (the pooled HIP events of kernel
  * timing, after waiting for any still pending; totals are cleared and timing
  * is switched off).  Call it before the process releases its devices; the

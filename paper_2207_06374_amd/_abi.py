@@ -123,6 +123,32 @@ class TRReport(ctypes.Structure):
                 ("cg_exit", ctypes.c_int32), ("accepted", ctypes.c_int32)]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("candidates", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("recheck_topk", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("radius0", ctypes.c_double),
+                ("target_factor", ctypes.c_double)]
+
+
+class ServeRequest(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64),
+                ("target_mu", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reached", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("target_mu", ctypes.c_double), ("queue_s", ctypes.c_double),
+                ("run_s", ctypes.c_double), ("footprint", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("pool_capacity", ctypes.c_uint64), ("pool_used", ctypes.c_uint64), ("pool_peak", ctypes.c_uint64),
+                ("active", ctypes.c_int32), ("queued", ctypes.c_int32), ("submitted", ctypes.c_int64)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_REJECTED, REQ_CANCELLED = range(6)
+
+
 # name: (restype, argtypes)
 SIGNATURES = {
     "trstmi_default_params": (None, [_P(Params), _i64, _i64]),
@@ -157,6 +183,14 @@ SIGNATURES = {
     "trstmi_timing_reset": (_i32, []),
     "trstmi_timing_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_i64)]),
     "trstmi_last_error": (ctypes.c_char_p, []),
+    "trstmi_request_footprint": (_sz, [_P(Params)]),
+    "trstmi_server_create": (_i32, [_P(ServerParams), _P(ctypes.c_void_p)]),
+    "trstmi_server_submit": (_i32, [_vp, _P(ServeRequest), _P(_i64)]),
+    "trstmi_server_poll": (_i32, [_vp, _i64, _P(RequestResult)]),
+    "trstmi_server_wait": (_i32, [_vp, _i64, ctypes.c_double, _P(RequestResult)]),
+    "trstmi_server_cancel": (_i32, [_vp, _i64]),
+    "trstmi_server_get_stats": (_i32, [_vp, _P(ServerStats)]),
+    "trstmi_server_destroy": (_i32, [_vp]),
     "trstmi_shutdown": (_i32, []),
     "trstmi_abi_version": (_i32, []),
 }

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtrstmi.so")
 
 SOURCES = ["perturb.hip", "gram_f64.hip", "gram_f32.hip", "gram_bf16.hip", "select.hip", "batch.hip", "lse_grad.hip",
-           "miso.hip",
+           "miso.hip", "server.hip",
            "trust_region.hip", "api.hip"]
 
 HIPCC_FLAGS = [

@@ -549,6 +549,11 @@ trstmi_status batch_prepare(const trstmi_batch_params* p, const trstmi_batch_ins
 
 }  // namespace
 
+namespace trstmi {
+// The calling thread's error message, for other parts of the library.
+trstmi_status set_last_error(trstmi_status code, const std::string& msg) { return fail(code, msg); }
+}  // namespace trstmi
+
 extern "C" {
 
 void trstmi_default_params(trstmi_params* p, int64_t n, int64_t d) {
@@ -1337,6 +1342,6 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 7; }
+int32_t trstmi_abi_version(void) { return 8; }
 
 }  // extern "C"

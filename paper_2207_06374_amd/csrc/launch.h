@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "trstmi.h"
 
 namespace trstmi {
@@ -207,6 +209,9 @@ struct MisoArgs {
 int64_t miso_blocks(int64_t m);
 // The quantiser, then (if summary is not null) summary = (mean dist, mean gain).
 hipError_t launch_miso(const MisoArgs& a, double* summary, hipStream_t s);
+
+// The calling thread's error message (what trstmi_last_error returns).
+trstmi_status set_last_error(trstmi_status code, const std::string& msg);
 
 // Trust-region step (trust_region.hip): the vectors' workspace bytes, and the
 // step itself given a trstmi_lse_grad workspace of lws_bytes at ws.

@@ -1,79 +1,34 @@
 """Serving form: a stream of solve requests with continuous admission.
 
-Requests (N, d, seed, arrival time) arrive over time.  A request is admitted
-as soon as a slot is free and its device footprint (workspace + frame +
-scalars) fits in the memory pool; it then runs on the GPU on its slot's own
-HIP stream, concurrently with the requests already running, until its
-coherence reaches the target (default 1.10 x the Welch bound) or its step
-limit.  Frames, radii and step counters stay resident in device memory for
-the whole solve; the host only polls a done flag once per chunk of
-graph-captured steps.  Requests arriving while others run are admitted as
-soon as slots and memory free up (no batch boundary to wait for).  A request
-larger than the whole pool is rejected with a status, never queued forever.
+The server itself is native (the library's trstmi_server_* entry points):
+slot threads with a HIP stream each take the request at the head of the
+queue as soon as its device footprint (workspace, frame, state scalars) fits
+in the caller's pool, run the Haar start and the solve there (graph-captured
+chunks of steps, one done-flag poll per chunk) and release the range.  A
+request larger than the whole pool is rejected at once.  This module submits
+requests at their arrival times and collects the results.
 
-Every result is a pure function of the request (its own seed and stream):
+Every result is a pure function of the request (its own seed and stream id):
 the same alone and in any mix.
 """
 
 from __future__ import annotations
 
-import bisect
+import ctypes
 import dataclasses
 import math
-import threading
 import time
+import weakref
 from typing import List, Optional
 
 import numpy as np
 
-from . import MODES, DeviceState, Solver, _torch, default_params, init_haar, solve, workspace_bytes
+from . import MODES, Solver, _abi, _torch, default_params
 
 
 def welch_bound(n, d):
     """sqrt((N - d) / (d (N - 1))), 0 for N <= d."""
     return math.sqrt(max(0.0, (n - d) / (d * (n - 1))))
-
-
-class OffsetAllocator:
-    """First-fit allocator of 256-byte aligned ranges in [0, capacity)."""
-
-    ALIGN = 256
-
-    def __init__(self, capacity):
-        self.capacity = int(capacity)
-        self.free = [(0, self.capacity)]          # sorted (offset, size)
-        self.used = 0
-        self.peak = 0
-
-    @classmethod
-    def round(cls, size):
-        return (int(size) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
-
-    def alloc(self, size):
-        size = self.round(size)
-        for k, (off, sz) in enumerate(self.free):
-            if sz >= size:
-                if sz == size:
-                    self.free.pop(k)
-                else:
-                    self.free[k] = (off + size, sz - size)
-                self.used += size
-                self.peak = max(self.peak, self.used)
-                return off
-        return None
-
-    def release(self, off, size):
-        size = self.round(size)
-        k = bisect.bisect_left(self.free, (off, 0))
-        self.free.insert(k, (off, size))
-        # merge with neighbours
-        if k + 1 < len(self.free) and self.free[k][0] + self.free[k][1] == self.free[k + 1][0]:
-            self.free[k] = (self.free[k][0], self.free[k][1] + self.free[k + 1][1])
-            self.free.pop(k + 1)
-        if k > 0 and self.free[k - 1][0] + self.free[k - 1][1] == self.free[k][0]:
-            self.free[k - 1] = (self.free[k - 1][0], self.free[k - 1][1] + self.free[k][1])
-            self.free.pop(k)
-        self.used -= size
 
 
 @dataclasses.dataclass
@@ -86,7 +41,7 @@ class Request:
     target_mu: Optional[float] = None   # None: target_factor x Welch
     max_steps: int = 20000
     # results
-    status: str = "pending"   # pending | queued | running | done | rejected | error
+    status: str = "pending"   # pending | queued | running | done | rejected | error | cancelled
     admit: float = math.nan
     finish: float = math.nan
     mu: float = math.nan
@@ -99,7 +54,18 @@ class Request:
         return self.finish - self.arrival
 
 
+def _destroy(handle, pool):
+    _abi.lib().trstmi_server_destroy(handle)
+    del pool
+
+
+_STATUS = {_abi.REQ_QUEUED: "queued", _abi.REQ_RUNNING: "running", _abi.REQ_DONE: "done", _abi.REQ_ERROR: "error",
+           _abi.REQ_REJECTED: "rejected", _abi.REQ_CANCELLED: "cancelled"}
+
+
 def request_params(req, candidates, mode, recheck_topk, radius0, target_factor):
+    """The solve parameters the server uses for a request (stream id = the
+    request's id)."""
     target = req.target_mu if req.target_mu is not None else target_factor * welch_bound(req.n, req.d)
     return default_params(req.n, req.d, candidates=candidates, mode=mode, recheck_topk=recheck_topk,
                           seed=req.seed, stream_id=req.id & 0xFFFFFFFF, radius0=radius0, max_steps=req.max_steps,
@@ -108,125 +74,98 @@ def request_params(req, candidates, mode, recheck_topk, radius0, target_factor):
 
 def footprint(params):
     """Device bytes one request holds while admitted: workspace, frame, scalars."""
-    frame = 16 * params.n * params.d
-    return OffsetAllocator.round(workspace_bytes(params)) + OffsetAllocator.round(frame) + 256
+    return int(_abi.lib().trstmi_request_footprint(ctypes.byref(params)))
 
 
 class Server:
-    """Continuous-admission solve server on one GPU."""
+    """Continuous-admission solve server on one GPU (the native server over a
+    torch-allocated pool)."""
 
     def __init__(self, pool_bytes, max_active=8, chunk=64, candidates=64, mode="bf16", recheck_topk=8,
                  radius0=0.05, target_factor=1.10, device="cuda"):
         torch = _torch()
-        self.torch = torch
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
-        self.alloc = OffsetAllocator(pool_bytes)
-        self.max_active = int(max_active)
-        # one stream per slot: a stream is never shared by two running requests
-        # (each captures its chunk of steps into a graph on its own stream)
-        self.free_streams = [torch.cuda.Stream(device=device) for _ in range(self.max_active)]
-        self.chunk = int(chunk)
         self.candidates = int(candidates)
         self.mode = MODES.get(mode, mode)
-        self.recheck_topk = int(recheck_topk)
-        self.radius0 = float(radius0)
         self.target_factor = float(target_factor)
-        self.lock = threading.Condition()
-        self.active = 0
+        p = _abi.ServerParams(ctypes.c_void_p(self.pool.data_ptr()), int(pool_bytes), int(max_active), int(chunk),
+                              int(candidates), int(self.mode), int(recheck_topk), 0, float(radius0),
+                              float(target_factor))
+        handle = ctypes.c_void_p()
+        _abi.check(_abi.lib().trstmi_server_create(ctypes.byref(p), ctypes.byref(handle)), "trstmi_server_create")
+        self.handle = handle
+        # destroy (join the slot threads) when the server is collected or at
+        # interpreter exit, before the HIP runtime goes away; the pool stays
+        # referenced until then
+        self._finalizer = weakref.finalize(self, _destroy, handle, self.pool)
 
-    def _views(self, off, params):
-        """State tensors and workspace carved out of the pool at `off`."""
-        torch = self.torch
-        ws_bytes = OffsetAllocator.round(workspace_bytes(params))
-        fr_bytes = OffsetAllocator.round(16 * params.n * params.d)
-        base = self.pool[off:off + ws_bytes + fr_bytes + 256]
-        ws = base[:ws_bytes]
-        frame = base[ws_bytes:ws_bytes + 16 * params.n * params.d].view(torch.float64)
-        sc = base[ws_bytes + fr_bytes:ws_bytes + fr_bytes + 256]
-        st = DeviceState(frame=frame, mu=sc[0:8].view(torch.float64), radius=sc[8:16].view(torch.float64),
-                         step=sc[16:24].view(torch.int64), flags=sc[24:28].view(torch.int32))
-        return ws, st
+    def close(self):
+        """Let running requests finish, cancel queued ones, stop the slots."""
+        self._finalizer()
 
-    def _run_one(self, req, params, off, size, stream, t0):
-        torch = self.torch
-        try:
-            ws, st = self._views(off, params)
-            with torch.cuda.stream(stream):
-                init_haar(params, st, ws, stream=stream)
-                solve(params, st, ws, chunk=self.chunk, stream=stream)
-                stream.synchronize()
-                req.mu = float(st.mu.item())
-                req.steps = int(st.step.item())
-            req.reached = req.mu <= params.target_mu
-            req.status = "done"
-        except Exception as exc:  # noqa: BLE001
-            req.status = "error"
-            req.error = str(exc)
-        req.finish = time.perf_counter() - t0
-        with self.lock:
-            self.alloc.release(off, size)
-            self.free_streams.append(stream)
-            self.active -= 1
-            self.lock.notify_all()
+    def submit(self, req):
+        rq = _abi.ServeRequest(int(req.n), int(req.d), int(req.seed), int(req.id) & 0xFFFFFFFF,
+                               math.nan if req.target_mu is None else float(req.target_mu), int(req.max_steps))
+        rid = ctypes.c_int64()
+        _abi.check(_abi.lib().trstmi_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(rid)),
+                   "trstmi_server_submit")
+        return rid.value
 
-    def run(self, requests: List[Request], poll_s=0.002, progress=None, progress_every_s=10.0):
-        """Serve `requests` (arrival times relative to now).  Returns a dict of
-        statistics; per-request results are written into the requests.
-        `progress(text)`, if given, is called about every progress_every_s."""
+    def result(self, rid, wait_s=0.0):
+        """(result struct, message) of a submitted request, waiting up to
+        wait_s seconds (< 0: until it finishes)."""
+        out = _abi.RequestResult()
+        if wait_s == 0.0:
+            st = _abi.lib().trstmi_server_poll(self.handle, int(rid), ctypes.byref(out))
+        else:
+            st = _abi.lib().trstmi_server_wait(self.handle, int(rid), float(wait_s), ctypes.byref(out))
+        _abi.check(st, "trstmi_server_poll")
+        msg = _abi.lib().trstmi_last_error().decode(errors="replace") if out.status in (
+            _abi.REQ_ERROR, _abi.REQ_REJECTED) else ""
+        return out, msg
+
+    def stats(self):
+        s = _abi.ServerStats()
+        _abi.check(_abi.lib().trstmi_server_get_stats(self.handle, ctypes.byref(s)), "trstmi_server_get_stats")
+        return s
+
+    def run(self, requests: List[Request], progress=None, progress_every_s=10.0):
+        """Serve `requests`, each submitted at its arrival time (relative to
+        now).  Returns a dict of statistics; per-request results are written
+        into the requests.  `progress(text)`, if given, is called about every
+        progress_every_s while requests are outstanding."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
         t0 = time.perf_counter()
-        last_report = t0
-        queue = []
-        threads = []
-        k = 0
-        while True:
-            now = time.perf_counter() - t0
-            if progress and time.perf_counter() - last_report >= progress_every_s:
-                last_report = time.perf_counter()
-                finished = sum(r.status in ("done", "rejected", "error") for r in reqs)
-                progress(f"serving t={now:.1f}s finished={finished}/{len(reqs)} active={self.active} "
-                         f"queued={len(queue)}")
-            while k < len(reqs) and reqs[k].arrival <= now:      # arrivals
-                r = reqs[k]
-                k += 1
-                params = request_params(r, self.candidates, self.mode, self.recheck_topk, self.radius0,
-                                        self.target_factor)
-                size = footprint(params)
-                if size > self.alloc.capacity:
-                    r.status = "rejected"
-                    r.error = f"footprint {size} B exceeds the pool ({self.alloc.capacity} B)"
-                    r.finish = now
-                    continue
-                r.status = "queued"
-                queue.append((r, params, size))
-            with self.lock:
-                while queue and self.active < self.max_active:   # admission, first in line first
-                    r, params, size = queue[0]
-                    off = self.alloc.alloc(size)
-                    if off is None:
-                        break
-                    queue.pop(0)
-                    self.active += 1
-                    r.status = "running"
-                    r.admit = time.perf_counter() - t0
-                    stream = self.free_streams.pop()
-                    th = threading.Thread(target=self._run_one, args=(r, params, off, size, stream, t0),
-                                          daemon=True)
-                    threads.append(th)
-                    th.start()
-                if k == len(reqs) and not queue and self.active == 0:
+        ids = []
+        for r in reqs:
+            delay = r.arrival - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(self.submit(r))
+            r.status = "queued"
+        last = time.perf_counter()
+        for r, rid in zip(reqs, ids):
+            while True:
+                out, msg = self.result(rid, wait_s=1.0)
+                if out.status >= _abi.REQ_DONE:
                     break
-                wait = poll_s
-                if k < len(reqs):
-                    wait = min(max(0.0, reqs[k].arrival - (time.perf_counter() - t0)), 0.05)
-                if self.active:
-                    self.lock.wait(timeout=max(wait, 1e-4))
-            if not self.active:
-                time.sleep(wait)
-        for th in threads:
-            th.join()
+                if progress and time.perf_counter() - last >= progress_every_s:
+                    last = time.perf_counter()
+                    s = self.stats()
+                    progress(f"serving t={last - t0:.1f}s active={s.active} queued={s.queued}")
+            r.status = _STATUS[out.status]
+            r.error = msg
+            r.mu = out.mu
+            r.steps = int(out.steps)
+            r.reached = bool(out.reached)
+            if out.status in (_abi.REQ_REJECTED, _abi.REQ_CANCELLED):
+                r.finish = r.arrival
+            else:
+                r.admit = r.arrival + out.queue_s
+                r.finish = r.admit + out.run_s
         wall = time.perf_counter() - t0
-        return summarize(reqs, wall, self.candidates, self.alloc.peak, self.alloc.capacity)
+        s = self.stats()
+        return summarize(reqs, wall, self.candidates, s.pool_peak, s.pool_capacity)
 
 
 def summarize(reqs, wall, candidates, peak_bytes, cap_bytes):

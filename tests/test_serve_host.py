@@ -1,49 +1,51 @@
-"""Host logic of the serving form (CPU only): the pool allocator and the
-admission footprint."""
+"""Host logic of the serving form (CPU only): the native pool allocator
+(compiled alone with g++ from its header) and the admission target."""
 
 import math
+import os
+import shutil
+import subprocess
+import tempfile
 
 import pytest
 
 serve = pytest.importorskip("paper_2207_06374_amd.serve")
 
-
-def test_allocator_first_fit_merge_and_peak():
-    a = serve.OffsetAllocator(4096)
-    x = a.alloc(1000)            # rounds to 1024
-    y = a.alloc(1024)
-    z = a.alloc(2048)
-    assert (x, y, z) == (0, 1024, 2048)
-    assert a.alloc(1) is None and a.used == 4096 and a.peak == 4096
-    a.release(y, 1024)
-    assert a.alloc(2048) is None            # only 1024 free
-    a.release(x, 1000)
-    assert a.free == [(0, 2048)]            # merged with the neighbour
-    assert a.alloc(2048) == 0
-    a.release(0, 2048)
-    a.release(z, 2048)
-    assert a.free == [(0, 4096)] and a.used == 0
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_allocator_never_exceeds_capacity():
-    import random
-    rnd = random.Random(0)
-    a = serve.OffsetAllocator(1 << 20)
-    live = []
-    for _ in range(2000):
-        if live and rnd.random() < 0.5:
-            off, size = live.pop(rnd.randrange(len(live)))
-            a.release(off, size)
-        else:
-            size = rnd.randrange(1, 1 << 16)
-            off = a.alloc(size)
-            if off is not None:
-                for o, s in live:
-                    assert off + serve.OffsetAllocator.round(size) <= o or o + serve.OffsetAllocator.round(s) <= off
-                live.append((off, size))
-        assert 0 <= a.used <= a.capacity and a.peak <= a.capacity
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_pool_allocator_first_fit_merge_peak_and_random_sequences():
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = os.path.join(tmp, "pool_alloc_check")
+        subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", "-I",
+                        os.path.join(ROOT, "paper_2207_06374_amd", "csrc"),
+                        os.path.join(ROOT, "tests", "pool_alloc_check.cpp"), "-o", exe], check=True)
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+        assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout
 
 
 def test_welch_target():
     assert serve.welch_bound(16, 8) == math.sqrt(8 / (8 * 15))
     assert serve.welch_bound(4, 8) == 0.0
+
+
+def test_footprint_and_server_argument_checks_without_device():
+    """The footprint is workspace + frame + scalars, each rounded to 256
+    bytes; the server rejects bad parameters before touching a device."""
+    import ctypes
+
+    from paper_2207_06374_amd import _abi, default_params, workspace_bytes
+    p = default_params(300, 16, candidates=32, mode="bf16", recheck_topk=8)
+    r256 = lambda x: (x + 255) // 256 * 256
+    assert serve.footprint(p) == r256(workspace_bytes(p)) + r256(16 * 300 * 16) + 256
+    L = _abi.lib()
+    h = ctypes.c_void_p()
+    good = dict(pool=ctypes.c_void_p(1 << 20), pool_bytes=1 << 20, slots=2, chunk=8, candidates=32, mode=2,
+                recheck_topk=8, reserved0=0, radius0=0.05, target_factor=1.1)
+    for k, v in (("pool", ctypes.c_void_p(0)), ("pool", ctypes.c_void_p((1 << 20) + 8)), ("pool_bytes", 100),
+                 ("slots", 0), ("slots", 65), ("chunk", 0), ("candidates", 0), ("radius0", 0.0)):
+        bad = _abi.ServerParams(**dict(good, **{k: v}))
+        assert L.trstmi_server_create(ctypes.byref(bad), ctypes.byref(h)) == _abi.E_INVALID_ARG, k
+    assert L.trstmi_server_submit(None, None, None) == _abi.E_INVALID_ARG
+    assert L.trstmi_server_destroy(None) == _abi.OK
