@@ -57,3 +57,27 @@ def test_serving_reaches_target_on_easy_requests():
     stats = srv.run(reqs)
     assert stats["reached_target"] == 4
     assert all(r.steps < 2000 and r.mu <= 0.95 for r in reqs)
+
+
+def test_cancel_wait_and_stats():
+    """With one slot, later requests queue behind the first: a queued one can
+    be cancelled (and then never runs), a running one cannot; a short wait
+    returns before the end; the others finish with their usual results."""
+    srv = serve.Server(pool_bytes=1 << 26, max_active=1, chunk=8, candidates=32)
+    reqs = [serve.Request(id=k, arrival=0.0, n=40, d=6, seed=k, max_steps=400) for k in range(3)]
+    ids = [srv.submit(r) for r in reqs]
+    out, _ = srv.result(ids[0], wait_s=0.001)
+    assert out.status in (lib._abi.REQ_QUEUED, lib._abi.REQ_RUNNING, lib._abi.REQ_DONE)
+    assert lib._abi.lib().trstmi_server_cancel(srv.handle, ids[2]) == lib._abi.OK
+    s = srv.stats()
+    assert s.submitted == 3 and s.active <= 1
+    done0, _ = srv.result(ids[0], wait_s=-1.0)
+    done1, _ = srv.result(ids[1], wait_s=-1.0)
+    gone, _ = srv.result(ids[2])
+    assert done0.status == done1.status == lib._abi.REQ_DONE and gone.status == lib._abi.REQ_CANCELLED
+    assert lib._abi.lib().trstmi_server_cancel(srv.handle, ids[0]) == lib._abi.E_INVALID_ARG
+    for r, o in zip(reqs[:2], (done0, done1)):
+        F, mu, radius, step, flags = serve.solve_alone(r, candidates=32, mode="bf16", chunk=8)
+        assert o.mu == mu and o.steps == step
+    assert srv.stats().pool_used == 0
+    srv.close()
