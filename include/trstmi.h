@@ -276,6 +276,8 @@ typedef struct {
   int32_t cg_max_iter;     /* >= 1, or 0 for 2 d N */
   double fd_step;          /* > 0 */
   int32_t concurrency;     /* starts run at once (one host thread and stream each), 1 .. 64 */
+  int32_t first_restart;   /* the starts are l = first_restart .. first_restart + restarts - 1, >= 0
+                              (one run of L starts may be split into several calls) */
 } trstmi_opt_params;
 
 /* Bytes of workspace trstmi_optimize needs with `concurrency` starts in

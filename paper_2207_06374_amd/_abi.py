@@ -114,7 +114,7 @@ class OptParams(ctypes.Structure):
                 ("deltas", ctypes.POINTER(ctypes.c_double)), ("steps_per_delta", ctypes.c_int32),
                 ("radius0", ctypes.c_double), ("radius_min", ctypes.c_double), ("radius_max", ctypes.c_double),
                 ("eta", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
-                ("fd_step", ctypes.c_double), ("concurrency", ctypes.c_int32)]
+                ("fd_step", ctypes.c_double), ("concurrency", ctypes.c_int32), ("first_restart", ctypes.c_int32)]
 
 
 class TRReport(ctypes.Structure):

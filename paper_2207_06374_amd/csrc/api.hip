@@ -875,7 +875,7 @@ struct OptWorker {
     const size_t cws_bytes = trstmi_coherence_workspace_bytes(n, d, 0);
     double* mu_dev = (double*)(cws + align256(cws_bytes));
     trstmi_status rs;
-    for (int32_t l = first; l < op->restarts; l += stride) {
+    for (int32_t l = op->first_restart + first; l < op->first_restart + op->restarts; l += stride) {
       if (abort->load(std::memory_order_relaxed)) break;
       PerturbArgs pa{};
       pa.n = n;
@@ -938,7 +938,8 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op,
   bool ok = op->restarts >= 1 && op->n_deltas >= 1 && op->deltas && op->steps_per_delta >= 1 && pos(op->radius0) &&
             op->radius_min >= 0.0 && op->radius_max >= op->radius0 && std::isfinite(op->radius_max) &&
             op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) && op->cg_max_iter >= 0 && pos(op->fd_step) &&
-            op->concurrency >= 1 && op->concurrency <= 64;
+            op->concurrency >= 1 && op->concurrency <= 64 && op->first_restart >= 0 &&
+            (int64_t)op->first_restart + op->restarts <= INT32_MAX;
   for (int32_t k = 0; ok && k < op->n_deltas; ++k) ok = pos(op->deltas[k]);
   if (!ok) return fail(TRSTMI_E_INVALID_ARG, "invalid optimiser parameters");
   if (!best_frame || ((uintptr_t)best_frame & 15)) return fail(TRSTMI_E_INVALID_ARG, "best_frame: null or misaligned");
@@ -1342,6 +1343,6 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 8; }
+int32_t trstmi_abi_version(void) { return 9; }
 
 }  // extern "C"

@@ -237,26 +237,27 @@ def test_optimize_argument_checks(L):
     best = ctypes.c_int32()
     p = ctypes.c_void_p(4096)
     ws = ctypes.c_void_p(1 << 20)
-    good = abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1)
+    good = abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, 0)
     assert L.trstmi_optimize(9, 65, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
                              None) == abi.E_UNSUPPORTED
     bad_dl = (ctypes.c_double * 2)(0.1, -1.0)
-    for bad in (abi.OptParams(0, 0, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1),
-                abi.OptParams(0, 2, 2, bad_dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1),
-                abi.OptParams(0, 2, 2, dl, 0, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1),
-                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 0.01, 0.1, 1e-10, 0, 1e-6, 1),
-                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 0),
-                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 65)):
+    for bad in (abi.OptParams(0, 0, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, 0),
+                abi.OptParams(0, 2, 2, bad_dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, 0),
+                abi.OptParams(0, 2, 2, dl, 0, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, 0),
+                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 0.01, 0.1, 1e-10, 0, 1e-6, 1, 0),
+                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 0, 0),
+                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 65, 0),
+                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, -1)):
         assert L.trstmi_optimize(9, 3, ctypes.byref(bad), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
                                  None) == abi.E_INVALID_ARG
     assert L.trstmi_optimize(9, 3, ctypes.byref(good), p, None, ctypes.byref(best), ws, need,
                              None) == abi.E_INVALID_ARG
     assert L.trstmi_optimize(9, 3, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws, need - 1,
                              None) == abi.E_WORKSPACE
-    four = abi.OptParams(0, 8, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 4)
+    four = abi.OptParams(0, 8, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 4, 0)
     assert L.trstmi_optimize(9, 3, ctypes.byref(four), p, ctypes.byref(mu), ctypes.byref(best), ws, 4 * need - 1,
                              None) == abi.E_WORKSPACE
-    assert L.trstmi_abi_version() >= 6
+    assert L.trstmi_abi_version() >= 9
 
 
 def test_miso_argument_checks(L):

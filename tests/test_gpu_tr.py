@@ -157,3 +157,16 @@ def test_optimize_concurrency_does_not_change_the_result():
     print(f"mu={mu1!r} {mu4!r} {mu6!r} restart={l1} {l4} {l6}", flush=True)
     assert mu1 == mu4 == mu6 and l1 == l4 == l6
     assert torch.equal(f1, f4) and torch.equal(f1, f6)
+
+
+def test_optimize_split_into_calls_equals_one_run():
+    """Starts l = 0..5 in one call, or as l = 0..2 and l = 3..5 in two calls
+    (first_restart): the best of the two calls is the one call's result."""
+    n, d = 16, 4
+    kw = dict(deltas=(1e-1, 1e-2), steps_per_delta=10, seed=5, concurrency=3)
+    f, mu, l = lib.optimize(n, d, restarts=6, **kw)
+    fa, mua, la = lib.optimize(n, d, restarts=3, first_restart=0, **kw)
+    fb, mub, lb = lib.optimize(n, d, restarts=3, first_restart=3, **kw)
+    best = (mua, la, fa) if mua <= mub else (mub, lb, fb)
+    assert 0 <= la < 3 <= lb < 6
+    assert best[0] == mu and best[1] == l and torch.equal(best[2], f)
