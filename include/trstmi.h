@@ -562,6 +562,10 @@ trstmi_status trstmi_server_wait(trstmi_server* server, int64_t id, double timeo
 /* Removes a still-queued request (TRSTMI_E_INVALID_ARG once it runs). */
 trstmi_status trstmi_server_cancel(trstmi_server* server, int64_t id);
 
+/* Drops the record of a finished request (any finished state), so that a
+ * long-running server does not keep every result; its id is then unknown. */
+trstmi_status trstmi_server_forget(trstmi_server* server, int64_t id);
+
 /* Pool use (now and peak), running and queued requests, submissions. */
 trstmi_status trstmi_server_get_stats(trstmi_server* server, trstmi_server_stats* out);
 

@@ -189,6 +189,7 @@ SIGNATURES = {
     "trstmi_server_poll": (_i32, [_vp, _i64, _P(RequestResult)]),
     "trstmi_server_wait": (_i32, [_vp, _i64, ctypes.c_double, _P(RequestResult)]),
     "trstmi_server_cancel": (_i32, [_vp, _i64]),
+    "trstmi_server_forget": (_i32, [_vp, _i64]),
     "trstmi_server_get_stats": (_i32, [_vp, _P(ServerStats)]),
     "trstmi_server_destroy": (_i32, [_vp]),
     "trstmi_shutdown": (_i32, []),

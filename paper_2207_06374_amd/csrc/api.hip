@@ -1343,6 +1343,6 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 9; }
+int32_t trstmi_abi_version(void) { return 10; }
 
 }  // extern "C"

@@ -250,10 +250,11 @@ trstmi_status trstmi_server_wait(trstmi_server* s, int64_t id, double timeout_s,
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->recs.find(id);
   if (it == s->recs.end()) return server_fail(TRSTMI_E_INVALID_ARG, "unknown request id");
+  const bool forever = timeout_s < 0 || timeout_s > 1e9;  // (a deadline that far out would overflow)
   const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
-                                        std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 0.0));
-  while (it->second.status < TRSTMI_REQ_DONE && (timeout_s < 0 || Clock::now() < until)) {
-    if (timeout_s < 0)
+                                        std::chrono::duration<double>(!forever && timeout_s > 0 ? timeout_s : 0.0));
+  while (it->second.status < TRSTMI_REQ_DONE && (forever || Clock::now() < until)) {
+    if (forever)
       s->cv.wait(lk);
     else
       s->cv.wait_until(lk, until);
@@ -276,6 +277,17 @@ trstmi_status trstmi_server_cancel(trstmi_server* s, int64_t id) {
   it->second.status = TRSTMI_REQ_CANCELLED;
   it->second.t_admit = it->second.t_finish = Clock::now();
   s->cv.notify_all();
+  return TRSTMI_OK;
+}
+
+trstmi_status trstmi_server_forget(trstmi_server* s, int64_t id) {
+  if (!s) return server_fail(TRSTMI_E_INVALID_ARG, "server must be a host pointer");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->recs.find(id);
+  if (it == s->recs.end()) return server_fail(TRSTMI_E_INVALID_ARG, "unknown request id");
+  if (it->second.status < TRSTMI_REQ_DONE)
+    return server_fail(TRSTMI_E_INVALID_ARG, "only a finished request can be forgotten");
+  s->recs.erase(it);
   return TRSTMI_OK;
 }
 

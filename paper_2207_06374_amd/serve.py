@@ -153,6 +153,7 @@ class Server:
                     last = time.perf_counter()
                     s = self.stats()
                     progress(f"serving t={last - t0:.1f}s active={s.active} queued={s.queued}")
+            _abi.lib().trstmi_server_forget(self.handle, int(rid))
             r.status = _STATUS[out.status]
             r.error = msg
             r.mu = out.mu

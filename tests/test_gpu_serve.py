@@ -80,4 +80,9 @@ def test_cancel_wait_and_stats():
         F, mu, radius, step, flags = serve.solve_alone(r, candidates=32, mode="bf16", chunk=8)
         assert o.mu == mu and o.steps == step
     assert srv.stats().pool_used == 0
+    L = lib._abi.lib()
+    assert L.trstmi_server_forget(srv.handle, ids[0]) == lib._abi.OK
+    assert L.trstmi_server_forget(srv.handle, ids[0]) == lib._abi.E_INVALID_ARG   # now unknown
+    out = lib._abi.RequestResult()
+    assert L.trstmi_server_poll(srv.handle, ids[0], out) == lib._abi.E_INVALID_ARG
     srv.close()

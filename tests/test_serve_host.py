@@ -49,3 +49,4 @@ def test_footprint_and_server_argument_checks_without_device():
         assert L.trstmi_server_create(ctypes.byref(bad), ctypes.byref(h)) == _abi.E_INVALID_ARG, k
     assert L.trstmi_server_submit(None, None, None) == _abi.E_INVALID_ARG
     assert L.trstmi_server_destroy(None) == _abi.OK
+    assert L.trstmi_server_forget(None, 0) == _abi.E_INVALID_ARG
