@@ -258,6 +258,9 @@ trstmi_status trstmi_server_wait(trstmi_server* s, int64_t id, double timeout_s,
       s->cv.wait(lk);
     else
       s->cv.wait_until(lk, until);
+    // another thread may have forgotten the record meanwhile: look it up again
+    it = s->recs.find(id);
+    if (it == s->recs.end()) return server_fail(TRSTMI_E_INVALID_ARG, "the request was forgotten while waiting");
   }
   return fill_result(s, id, out);
 }
