@@ -110,9 +110,9 @@ Outcome trstmi_server::run_one(const Record& r, hipStream_t s) {
 }
 
 void trstmi_server::work() {
-  hipSetDevice(device);
   hipStream_t s = nullptr;
-  const hipError_t he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  hipError_t he = hipSetDevice(device);
+  if (he == hipSuccess) he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   for (;;) {
     int64_t id = -1;
     {
@@ -156,7 +156,7 @@ void trstmi_server::work() {
     }
     cv.notify_all();
   }
-  if (s) hipStreamDestroy(s);
+  if (s) (void)hipStreamDestroy(s);
 }
 
 extern "C" {
