@@ -117,7 +117,7 @@ def _table2():
     return rows
 
 
-@pytest.mark.parametrize("d,restarts", [(2, 8), (3, 6)])
+@pytest.mark.parametrize("d,restarts", [(2, 8), (3, 6), (4, 32), (5, 50)])
 def test_optimize_reaches_table2(d, restarts):
     """Alg. 2 (continuation over delta, random restarts, trust-region steps)
     reaches the printed Table II coherence at N = d^2, which is also the
