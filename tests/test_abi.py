@@ -301,3 +301,23 @@ def test_coherence_pair_and_shutdown_without_device(L):
     assert L.trstmi_coherence_pair(100, 8, p, p, p, ws, need - 1, None) == abi.E_WORKSPACE
     assert L.trstmi_shutdown() == abi.OK
     assert L.trstmi_abi_version() >= 7
+
+
+def test_c_abi_from_plain_c():
+    """A C11 program includes the header, links the library and calls the
+    host-side entry points (no GPU needed)."""
+    import os
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2207_06374_amd")
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = os.path.join(tmp, "c_abi_check")
+        subprocess.run(["gcc", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"),
+                        "-I", "/opt/rocm/include", os.path.join(root, "tests", "c_abi_check.c"), "-o", exe,
+                        "-L", pkg, "-ltrstmi", "-Wl,-rpath," + pkg], check=True, capture_output=True)
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+        assert r.returncode == 0 and r.stdout.strip() == "ok", (r.returncode, r.stdout, r.stderr)
