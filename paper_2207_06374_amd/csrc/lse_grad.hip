@@ -248,13 +248,15 @@ __global__ __launch_bounds__(64) void k_lse_grad_finish(GradArgs a, int nch) {
 int lse_grad_chunks(int nkb) {
   // One 512-thread block fits a CU (LDS), so blocks run in rounds of 256
   // (the CU count).  Row tiles are split into nch runs: at least enough for
-  // about 512 blocks, at most runs of 4 tiles, and within that range the
+  // one round of blocks, at most runs of 4 tiles, and within that range the
   // smallest count whose grid fills its last round to 97 % (else the best
-  // fill).  At N = 18000 (282 tiles a side), 282 x 2 = 564 blocks took
-  // three rounds with the last one 22 % full; 282 x 8 = 2256 fill nine
-  // rounds to 98 %.
+  // fill).  Each run writes its own partial sums (2 x 64 x 2d doubles per
+  // wave pair), so fewer runs also mean less traffic: at N = 4096 four runs
+  // (256 blocks, one full round) write half the partials of eight.  At
+  // N = 18000 (282 tiles a side), 282 x 2 = 564 blocks took three rounds
+  // with the last one 22 % full; 282 x 8 = 2256 fill nine rounds to 98 %.
   constexpr int kCUs = 256;
-  int lo = (512 + nkb - 1) / nkb;
+  int lo = (kCUs + nkb - 1) / nkb;
   lo = lo < 1 ? 1 : (lo > nkb ? nkb : lo);
   const int hi = nkb / 4 > lo ? nkb / 4 : lo;
   int best = lo;
