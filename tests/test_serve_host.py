@@ -18,8 +18,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_pool_allocator_first_fit_merge_peak_and_random_sequences():
     with tempfile.TemporaryDirectory() as tmp:
         exe = os.path.join(tmp, "pool_alloc_check")
-        subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", "-I",
-                        os.path.join(ROOT, "paper_2207_06374_amd", "csrc"),
+        # host code only: built with g++ under the address and undefined-behaviour sanitizers
+        subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", "-Werror", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=undefined", "-I", os.path.join(ROOT, "paper_2207_06374_amd", "csrc"),
                         os.path.join(ROOT, "tests", "pool_alloc_check.cpp"), "-o", exe], check=True)
         r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
         assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout
