@@ -178,20 +178,29 @@ def _argmin_lowest(values, allowed=None):
 def screen_error_bound(d):
     """Largest possible |screened - exact| coherence for unit columns in C^d.
 
-    Rounding the real and imaginary parts of an entry to bfloat16 (relative
-    error at most u = 2^-8 each) moves the complex entry by at most u times
-    its modulus, so by the triangle and Cauchy-Schwarz inequalities the
-    complex inner product of two unit columns moves by at most 2u + u^2.
-    Summing 2d exact bf16 products in binary32 moves each of Re and Im by at
-    most gamma_{2d} (1 + u)^2 with gamma_n = n v / (1 - n v), v = 2^-24; the
-    two together give the factor sqrt(2).  A few binary32 roundings in |G|^2
-    and the square root, and the FP64 value's own rounding, are covered by
-    the last two terms.
+    Input rounding: rounding the real and imaginary parts of an entry to
+    bfloat16 (relative error at most u = 2^-8 each) moves the complex entry by
+    at most u times its modulus, so a unit column moves by at most u in norm
+    and, by the triangle and Cauchy-Schwarz inequalities, the complex inner
+    product of two unit columns moves by at most 2u + u^2.
+
+    Accumulation: products of two bfloat16 values are exact in binary32; Re
+    and Im are each a sum of 2d such products, whose absolute values add up to
+    at most |phi^| |psi^| <= (1 + u)^2.  Assuming only that every addition of
+    the binary32 accumulation is faithful (its error is below one ulp of its
+    result, in whatever direction the hardware rounds or truncates), each sum
+    is off by at most gamma_{2d} (1 + u)^2 with gamma_n = n w / (1 - n w),
+    w = 2^-23 (round to nearest alone would allow 2^-24); Re and Im together
+    give the factor sqrt(2).
+
+    Epilogue: a few binary32 roundings in |G|^2 and the square root (8 v,
+    v = 2^-24), and the FP64 value's own rounding (1e-12).
     """
     u = 2.0 ** -8
+    w = 2.0 ** -23
     v = 2.0 ** -24
     n = 2 * d
-    gamma = n * v / (1.0 - n * v)
+    gamma = n * w / (1.0 - n * w)
     return (2 * u + u * u) + math.sqrt(2.0) * gamma * (1 + u) ** 2 + 8 * v + 1e-12
 
 
@@ -199,10 +208,13 @@ def _is_done(p, mu, t):
     return (p.target_mu > 0 and mu <= p.target_mu) or t >= p.max_steps
 
 
-def step(p: Params, state: State, Z=None):
+def step(p: Params, state: State, Z=None, exact_all=True):
     """One step of the candidate search from ``state`` (not modified).
 
     ``Z`` (shape (C, d, n)) replaces the generator's draws when given.
+    ``exact_all=False`` (bf16 mode only) evaluates the exact FP64 coherence
+    of the rechecked candidates only, the only ones any decision reads; the
+    others get NaN in ``cand_mu_fp64``.
     Returns (new_state, StepReport).
     """
     if p.mode not in MODES:
@@ -213,7 +225,8 @@ def step(p: Params, state: State, Z=None):
     if Z is None:
         Z = perturbations(p, state.t)
     Phi_c, valid = make_candidates(state.frame, state.radius, p.d, Z)
-    mu64 = evaluate_candidates(Phi_c, valid, "fp64")
+    skip = p.mode == "bf16" and not exact_all
+    mu64 = np.full(C, math.nan) if skip else evaluate_candidates(Phi_c, valid, "fp64")
     tau = p.tie_threshold()
     rechecked = None
     screen_gap = math.inf
@@ -230,6 +243,8 @@ def step(p: Params, state: State, Z=None):
         k = min(p.recheck_topk, C)
         order = sorted(range(C), key=lambda c: (cand_mu[c], c))
         rechecked = np.array(order[:k], dtype=np.int64)
+        if skip:
+            mu64[rechecked] = evaluate_candidates(Phi_c[rechecked], valid[rechecked], "fp64")
         if k < C:
             screen_gap = float(cand_mu[order[k]] - cand_mu[order[k - 1]])
         allowed = np.zeros(C, dtype=bool)
