@@ -86,7 +86,9 @@ enum {
  * radius_min); 0 < radius_min <= radius0 <= radius_max, grow >= 1,
  * 0 < shrink <= 1.  A step perturbs every column by radius in RMS norm:
  * Y_c = Phi + (radius / sqrt(d)) Z_c with Z_c i.i.d. CN(0, 1).
- * target_mu <= 0 disables the target; max_steps >= 0.  near_tie <= 0 selects
+ * target_mu <= 0 disables the target; 0 <= max_steps <= 2^32 - 1 (the step
+ * index is one 32-bit word of the random-number counter, so more steps would
+ * repeat draws; larger values are rejected).  near_tie <= 0 selects
  * the mode's default (2e-12 for FP64 decisions, 4e-6 for FP32).
  */
 typedef struct trstmi_params {
@@ -364,22 +366,38 @@ trstmi_status trstmi_candidates(const trstmi_params* p, const double* frame, con
                                 double* out, hipStream_t stream);
 
 /*
- * One step of the search on *state (no-op if DONE).  Draws the C
- * perturbations of step *step (or reads explicit_z: device, C x 2*d*n doubles,
- * candidate c at offset c*2*d*n, same layout as a frame), renormalises,
- * evaluates every candidate's coherence in the mode's arithmetic, selects c*
- * = argmin over (mu_c, c), accepts iff mu_{c*} < *mu, updates frame, mu,
- * radius, step and flags.  report may be NULL.
+ * One step of the search on *state (no-op if DONE).  The trust region is the
+ * one of Alg. 1 (section IV): a radius that grows after a successful step and
+ * shrinks after a failed one; the objective is the coherence of section I
+ * (largest modulus of an off-diagonal Gram entry of the column-normalised
+ * frame, section IV).  The paper fixes neither the random perturbation nor the
+ * radius constants; this step reads them as stated under trstmi_params.
+ * Draws the C perturbations of step *step (or reads explicit_z: device,
+ * C x 2*d*n doubles, candidate c at offset c*2*d*n, same layout as a frame),
+ * renormalises, evaluates every candidate's coherence in the mode's
+ * arithmetic, selects c* = argmin over (mu_c, c), accepts iff mu_{c*} < *mu,
+ * updates frame, mu, radius, step and flags.  report may be NULL.
+ * Invalid candidates (a column of zero or non-finite norm) are not an error:
+ * their coherence is +inf and they never win; a step whose candidates are all
+ * invalid rejects and sets TRSTMI_FLAG_NO_VALID.
+ * Errors: TRSTMI_E_INVALID_ARG (parameters, NULL or misaligned state
+ * pointers), TRSTMI_E_UNSUPPORTED (BF16 screen with d > 128),
+ * TRSTMI_E_WORKSPACE, TRSTMI_E_HIP; nothing is launched on an error found on
+ * the host.
  */
 trstmi_status trstmi_step(const trstmi_params* p, const trstmi_state* state, void* workspace,
                           size_t workspace_bytes, const double* explicit_z,
                           const trstmi_report* report, hipStream_t stream);
 
 /*
- * Steps until DONE, checking the device flag after every `chunk` steps
- * (chunk >= 1).  Launches of each chunk are captured once into a HIP graph
- * and replayed.  Blocks the calling thread; returns after the stream has
- * finished the last chunk.
+ * One run of the search from *state until DONE (the target coherence is met
+ * or step == max_steps): the inner loop of one random start of Alg. 2
+ * (section IV), with trstmi_step as the iteration.  Checks the device flag
+ * after every `chunk` steps (chunk >= 1).  Launches of each chunk are
+ * captured once into a HIP graph and replayed.  Blocks the calling thread;
+ * returns after the stream has finished the last chunk.  The result equals
+ * that of calling trstmi_step until DONE, bit for bit.
+ * Errors: as trstmi_step; chunk < 1 gives TRSTMI_E_INVALID_ARG.
  */
 trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, void* workspace,
                            size_t workspace_bytes, int32_t chunk, hipStream_t stream);

@@ -131,6 +131,7 @@ trstmi_status drain_timing() {
 }
 
 constexpr int64_t kMaxN = 1 << 18;
+constexpr int64_t kMaxSteps = 0xFFFFFFFFLL;  // steps are counted in one 32-bit Philox counter word
 constexpr int64_t kMaxChannels = 2147483647;  // channels per quantiser call (int32 indices)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -223,7 +224,8 @@ trstmi_status check_params(const trstmi_params* p) {
   if (!ok_r) return fail(TRSTMI_E_INVALID_ARG, "need finite 0 < radius_min <= radius0 <= radius_max");
   if (!(std::isfinite(p->grow) && p->grow >= 1.0) || !(std::isfinite(p->shrink) && p->shrink > 0 && p->shrink <= 1.0))
     return fail(TRSTMI_E_INVALID_ARG, "need grow >= 1 and 0 < shrink <= 1");
-  if (p->max_steps < 0) return fail(TRSTMI_E_INVALID_ARG, "max_steps must be >= 0");
+  // the step index is one 32-bit word of the Philox counter: steps 0 .. 2^32 - 2
+  if (p->max_steps < 0 || p->max_steps > kMaxSteps) return fail(TRSTMI_E_INVALID_ARG, "max_steps must be in [0, 2^32 - 1]");
   if (std::isnan(p->target_mu) || std::isnan(p->near_tie)) return fail(TRSTMI_E_INVALID_ARG, "NaN parameter");
   return TRSTMI_OK;
 }
@@ -250,18 +252,22 @@ double tau_of(const trstmi_params* p) {
   return p->mode == TRSTMI_MODE_FP32 ? 4e-6 : 2e-12;
 }
 
-// Certified bound on |screened - exact| coherence for unit columns in C^d:
-// rounding the real and imaginary parts of an entry to bfloat16 (relative
-// error <= u = 2^-8 each) moves the complex entry by at most u times its
-// modulus, so the complex inner product of two unit columns moves by at most
-// 2u + u^2 (triangle and Cauchy-Schwarz inequalities); FP32 accumulation of
-// 2d exact products moves Re and Im each by at most gamma_{2d} (1 + u)^2
-// (gamma_n = n v / (1 - n v), v = 2^-24), sqrt(2) for the two together; the
-// last terms cover the FP32 epilogue and FP64 rounding.
+// Certified bound on |screened - exact| coherence for unit columns in C^d.
+// Input: rounding the real and imaginary parts of an entry to bfloat16
+// (relative error <= u = 2^-8 each) moves the complex entry by at most u
+// times its modulus, so the complex inner product of two unit columns moves
+// by at most 2u + u^2 (triangle and Cauchy-Schwarz inequalities).
+// Accumulation: bf16 x bf16 products are exact in FP32 and the MFMA adds 2d
+// of them per real part, with |terms| summing to <= (1 + u)^2.  The only
+// assumption made about v_mfma_f32_16x16x32_bf16 is that each addition is
+// faithful (error below one ulp of its result, any rounding direction), so
+// each part is off by <= gamma_{2d} (1 + u)^2 with gamma_n = n w / (1 - n w),
+// w = 2^-23; sqrt(2) for Re and Im together.  The last terms cover the FP32
+// epilogue (8 v, v = 2^-24) and the FP64 value's rounding.
 double screen_eps(int64_t d) {
-  const double u = std::ldexp(1.0, -8), v = std::ldexp(1.0, -24);
-  const double nv = 2.0 * d * v;
-  const double gamma = nv / (1.0 - nv);
+  const double u = std::ldexp(1.0, -8), w = std::ldexp(1.0, -23), v = std::ldexp(1.0, -24);
+  const double nw = 2.0 * d * w;
+  const double gamma = nw / (1.0 - nw);
   return (2 * u + u * u) + std::sqrt(2.0) * gamma * (1 + u) * (1 + u) + 8 * v + 1e-12;
 }
 
@@ -462,7 +468,7 @@ trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_inst
     const trstmi_batch_instance& I = inst[i];
     if (I.n < 2 || I.n > kBatchMaxN || I.d < 1 || I.d > kBatchMaxD)
       return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": need 2 <= n <= 256, 1 <= d <= 16");
-    if (I.max_steps < 0 || std::isnan(I.target_mu))
+    if (I.max_steps < 0 || I.max_steps > kMaxSteps || std::isnan(I.target_mu))
       return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": bad max_steps or target");
     const int64_t need = (int64_t)I.n * batch_ldk(I.d);
     int32_t w = I.waves_per_item;

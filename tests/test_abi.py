@@ -71,7 +71,8 @@ def test_defaults_and_workspace(L):
 @pytest.mark.parametrize("field,value", [("n", 1), ("d", 0), ("d", 513), ("candidates", 0),
                                          ("candidates", 40000), ("radius0", 0.0), ("radius0", 2.0),
                                          ("radius_min", -1.0), ("grow", 0.5), ("shrink", 0.0),
-                                         ("shrink", 1.5), ("max_steps", -1), ("seed", 2 ** 32),
+                                         ("shrink", 1.5), ("max_steps", -1), ("max_steps", 2 ** 32),
+                                         ("max_steps", 10 ** 12), ("seed", 2 ** 32),
                                          ("stream_id", 2 ** 33), ("mode", 7), ("radius0", float("nan"))])
 def test_invalid_params_rejected_on_host(L, field, value):
     p = _params(L, **{field: value})
@@ -81,6 +82,15 @@ def test_invalid_params_rejected_on_host(L, field, value):
     status = L.trstmi_step(ctypes.byref(p), ctypes.byref(st), fake, 1 << 40, None, None, None)
     assert status == abi.E_INVALID_ARG
     assert L.trstmi_last_error()
+
+
+def test_step_limit_is_the_counter_word(L):
+    """The step index is one 32-bit word of the random-number counter: the
+    largest accepted step limit is 2^32 - 1."""
+    p = _params(L, max_steps=2 ** 32 - 1)
+    assert L.trstmi_workspace_bytes(ctypes.byref(p)) > 0
+    p.max_steps = 2 ** 32
+    assert L.trstmi_workspace_bytes(ctypes.byref(p)) == 0
 
 
 def test_bf16_topk_range(L):
