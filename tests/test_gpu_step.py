@@ -161,22 +161,54 @@ def test_done_state_is_noop_and_target_stops():
 
 @pytest.mark.parametrize("mode", ["fp64", "bf16"])
 def test_small_solve_matches_oracle(mode):
-    """The small workload (N=16 in C^4, 64 candidates, radius 0.1) solved on the
-    GPU with graph-captured chunks equals the oracle's solve (compared until
-    the first near tie)."""
-    steps = 300
-    s, p = _pair(16, 4, 64, mode=mode, radius0=0.1, max_steps=steps, k=8)
+    """The small workload (N=16 in C^4, 64 candidates, radius 0.1, 2000 steps)
+    solved on the GPU with graph-captured chunks follows the oracle's
+    trajectory.  The run is cut into segments at the oracle's near-tie
+    decisions: between two of them the GPU solve must reach the oracle's
+    state (frame, mu, radius, step); the near-tie step itself is taken by the
+    GPU alone and the oracle resyncs to its state."""
+    total = 2000
+    s, p = _pair(16, 4, 64, mode=mode, radius0=0.1, max_steps=total, k=8)
     s.init_haar()
-    s.solve(chunk=64)
+    st = oracle.haar_init(p)
+    F0, mu0, _, _, _ = s.host_state()
+    assert np.max(np.abs(F0 - st.frame)) <= 1e-14 and abs(mu0 - st.mu) <= 1e-12
+    segments = ties = solved_steps = 0
+    mus = [mu0]
+    while True:
+        ost, stop = st, total
+        while ost.t < total:
+            nxt, rep = oracle.step(p, ost, exact_all=False)
+            if rep.near_tie:
+                stop = ost.t
+                break
+            ost = nxt
+        if stop > st.t:
+            s.params.max_steps = stop
+            s.state.flags.fill_(0)
+            s.solve(chunk=64)
+            segments += 1
+            solved_steps += stop - st.t
+        F, mu, radius, t, flags = s.host_state()
+        assert t == stop, f"segment ending at {stop}"
+        assert abs(mu - ost.mu) <= 1e-12, f"step {stop}"
+        assert radius == ost.radius, f"step {stop}"
+        assert np.max(np.abs(F - ost.frame)) <= 1e-12, f"step {stop}"
+        mus.append(mu)
+        if stop >= total:
+            break
+        s.params.max_steps = total
+        s.state.flags.fill_(0)
+        s.step(with_report=False)
+        ties += 1
+        st = _sync_oracle(s, p)
+        mus.append(st.mu)
     F, mu, radius, t, flags = s.host_state()
-    ref, hist = oracle.solve(p, record=True)
-    assert t == steps and flags & lib.FLAG_DONE
-    if any(h[4] for h in hist):
-        pytest.skip("near tie in the oracle trajectory; step parity covers this case")
-    assert abs(mu - ref.mu) <= 1e-12
-    assert radius == ref.radius
-    assert np.max(np.abs(F - ref.frame)) <= 1e-12
+    print(f"{mode}: {segments} solve segments ({solved_steps} steps), {ties} near-tie steps", flush=True)
+    assert t == total and flags & lib.FLAG_DONE
+    assert all(b <= a for a, b in zip(mus, mus[1:]))       # mu never increases
     assert mu >= oracle.welch_bound(16, 4) - 1e-12
+    assert solved_steps > 0
 
 
 def test_step_matches_solve_bitwise():

@@ -192,3 +192,20 @@ def test_accept_is_strict():
     st2.mu = np.nextafter(rep.best_mu, 1.0)
     _, rep3 = oracle.step(p, st2, Z)
     assert rep3.accepted
+
+
+def test_bf16_exact_all_false_changes_no_decision():
+    """exact_all=False skips the FP64 values no decision reads: the same
+    rechecked set, choice, frame, radius and FP64 values of the rechecked."""
+    p = _params(n=64, d=8, candidates=24, mode="bf16", recheck_topk=5, radius0=0.2)
+    st = oracle.haar_init(p)
+    for _ in range(3):
+        a, ra = oracle.step(p, st)
+        b, rb = oracle.step(p, st, exact_all=False)
+        assert ra.best == rb.best and ra.accepted == rb.accepted and ra.near_tie == rb.near_tie
+        assert a.mu == b.mu and a.radius == b.radius and np.array_equal(a.frame, b.frame)
+        assert np.array_equal(ra.rechecked, rb.rechecked)
+        assert np.array_equal(ra.cand_mu, rb.cand_mu)
+        assert np.array_equal(ra.cand_mu_fp64[ra.rechecked], rb.cand_mu_fp64[rb.rechecked])
+        assert np.isnan(rb.cand_mu_fp64).sum() == 24 - 5
+        st = a
