@@ -72,15 +72,47 @@ STEP_KERNELS = ("perturb", "gram_f64", "gram_f32", "gram_bf16", "topk", "perturb
                 "commit")
 
 
-def run_mode(lib, torch, wl, mode, steps, warmup, topk=8, breakdown_steps=10):
-    """Timed steps with HIP events around the Gram kernel only (the other
-    kernels' events would add to the step), then a few steps with every kernel
-    timed for the per-kernel breakdown."""
-    s = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode=mode, recheck_topk=topk, radius0=wl.radius0,
-                   max_steps=10 ** 12, seed=wl.seed, stream_id=wl.stream_id)
-    s.init_haar()
-    for _ in range(warmup):
+def warm_up(lib, torch, s, mode, min_steps, min_s=1.0, max_s=20.0, window=200):
+    """Untimed steps until the Gram kernel's average launch time is steady:
+    at least ``min_steps`` steps and ``min_s`` seconds, then windows of
+    ``window`` steps until two consecutive window averages agree within 1 %
+    (at most ``max_s`` seconds).  Clocks ramp up over the first second of a
+    fresh process; timing before that reads them low."""
+    t0 = time.perf_counter()
+    for _ in range(min_steps):
         s.step(with_report=False)
+    torch.cuda.synchronize()
+    prev = None
+    lib.timing_only(GRAM_KERNEL[mode])
+    while True:
+        lib.timing_reset()
+        lib.timing_enable(True)
+        for k in range(window):
+            s.step(with_report=False)
+            if k % 32 == 31:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        lib.timing_enable(False)
+        ms, cnt = lib.timing_read(GRAM_KERNEL[mode])
+        avg = ms / max(cnt, 1)
+        el = time.perf_counter() - t0
+        if el >= max_s or (el >= min_s and prev is not None and abs(avg - prev) <= 0.01 * prev):
+            break
+        prev = avg
+    lib.timing_only(None)
+    lib.timing_reset()
+    return {"seconds": time.perf_counter() - t0, "last_window_gram_us": 1e3 * avg}
+
+
+def run_mode(lib, torch, wl, mode, steps, warmup, topk=8, breakdown_steps=10, min_warm_s=1.0, window=200):
+    """Timed steps with HIP events around the Gram kernel only (the other
+    kernels' events would add to the step), after a warm-up that runs until
+    the Gram time is steady; then a few steps with every kernel timed for the
+    per-kernel breakdown."""
+    s = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode=mode, recheck_topk=topk, radius0=wl.radius0,
+                   max_steps=2 ** 32 - 1, seed=wl.seed, stream_id=wl.stream_id)
+    s.init_haar()
+    warm = warm_up(lib, torch, s, mode, warmup, min_s=min_warm_s, window=window)
     torch.cuda.synchronize()
     lib.timing_reset()
     lib.timing_only(GRAM_KERNEL[mode])
@@ -122,7 +154,64 @@ def run_mode(lib, torch, wl, mode, steps, warmup, topk=8, breakdown_steps=10):
         "gram_tflops": achieved,
         "gram_frac": achieved / PEAK_TFLOPS[mode],
         "flops_per_launch": flops_launch,
+        "warmup": warm,
     }
+
+
+def run_small_solve(lib, torch, wl, chunk=64):
+    """The small workload as one full solve: N=16 in C^4, 64 candidates,
+    radius 0.1, 2000 FP64 steps from the Haar start (seed 0), graph-captured
+    chunks; wall time of trstmi_solve and the final coherence."""
+    s = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode="fp64", radius0=wl.radius0, max_steps=wl.steps,
+                   seed=wl.seed, stream_id=wl.stream_id)
+    s.init_haar()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve(chunk)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    F, mu, radius, t, flags = s.host_state()
+    return {"workload": f"N={wl.n}, d={wl.d}, {wl.candidates} candidates, radius {wl.radius0}, {wl.steps} FP64 steps, "
+                        f"Haar start seed {wl.seed}; trstmi_solve with graph-captured chunks of {chunk} steps",
+            "gpu_wall_s": wall, "steps": t, "final_mu": mu, "final_radius": radius,
+            "welch": math.sqrt((wl.n - wl.d) / (wl.d * (wl.n - 1)))}
+
+
+def run_equal_mu(lib, torch, wl, probe_steps=300, cap_factor=4, chunk=16):
+    """Seconds for the FP64, FP32 and BF16-screen forms to reach one common
+    coherence from the same Haar start (seed 0) at N=4096, d=64, C=128.  The
+    target T is the exact coherence the BF16 form reaches after
+    ``probe_steps`` steps; each form then solves from the start with target
+    T (the FP32 form with T - 4e-6, so that its FP32 coherence, within 2e-6
+    of the exact one, certifies mu <= T).  Every final frame is re-evaluated
+    with the library's FP64 coherence; the frames are returned for the
+    oracle's check in the CPU leg."""
+    probe = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode="bf16", radius0=wl.radius0,
+                       max_steps=probe_steps, seed=wl.seed, stream_id=wl.stream_id)
+    probe.init_haar()
+    probe.solve(chunk)
+    target = float(probe.state.mu.item())
+    del probe
+    out, frames = {"target_mu": target, "probe_steps": probe_steps}, {}
+    for mode in ("bf16", "fp32", "fp64"):
+        goal = target - 4e-6 if mode == "fp32" else target
+        s = lib.Solver(wl.n, wl.d, candidates=wl.candidates, mode=mode, radius0=wl.radius0,
+                       max_steps=cap_factor * probe_steps, seed=wl.seed, stream_id=wl.stream_id, target_mu=goal)
+        s.init_haar()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(chunk)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        F, mu, radius, t, flags = s.host_state()
+        mu64 = float(lib.coherence(s.state.frame, wl.n, wl.d, lib.MODE_FP64).item())
+        out[mode] = {"seconds": wall, "steps": t, "state_mu": mu, "fp64_mu": mu64, "reached": mu64 <= target,
+                     "evals_per_s": wl.candidates * t / wall}
+        frames[mode] = F
+        log(f"equal mu {mode}: {t} steps in {wall:.2f} s, FP64 mu {mu64:.10f} (target {target:.10f})")
+        del s
+        torch.cuda.empty_cache()
+    return out, frames
 
 
 def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
@@ -321,38 +410,86 @@ def run_serving(lib, count, max_steps, pool_gib):
     return stats
 
 
-def cpu_baseline(wl, budget_s):
-    """The FP64 oracle (numpy) on a bounded sample of the workload: one step of
-    the BF16-screen form with c candidates, c chosen so the run takes about
-    ``budget_s`` seconds."""
-    import oracle
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"),
-                      default=1)
-    except Exception:  # noqa: BLE001
-        threads = len(os.sched_getaffinity(0))
-    p = oracle.Params(n=wl.n, d=wl.d, candidates=1, mode="bf16", recheck_topk=1, radius0=wl.radius0,
-                      seed=wl.seed, stream_id=wl.stream_id, max_steps=10 ** 9)
-    st = oracle.haar_init(p)
-    t0 = time.perf_counter()
-    oracle.step(p, st)
-    one = time.perf_counter() - t0
-    c = int(max(2, min(wl.candidates, budget_s / max(one, 1e-3))))
-    p.candidates = c
-    p.recheck_topk = min(8, c)
-    t0 = time.perf_counter()
-    oracle.step(p, st)
-    el = time.perf_counter() - t0
-    return {
-        "value": c / el,
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_info():
+    from threadpoolctl import threadpool_info
+    for i in threadpool_info():
+        if i.get("user_api") == "blas":
+            return {"library": i.get("internal_api"), "version": i.get("version"), "threads": i.get("num_threads"),
+                    "architecture": i.get("architecture")}
+    return {"library": "unknown", "threads": 1}
+
+
+def cpu_baseline(large, medium, small, budget_s, equal_frames=None):
+    """The FP64 oracle (numpy, the oracle as it stands) on bounded samples of
+    the workloads, on this host's cores:
+
+    * the throughput workload (N=4096, d=64, radius 0.05, Haar start seed 0):
+      one FP64-form step with c of the 128 candidates (perturb, renormalise,
+      one FP64 Gram + max per candidate, select), with every BLAS thread and
+      with one;
+    * the plain workload (N=1024, d=32): one FP64 step with all 256 candidates;
+    * the small workload (N=16, d=4, 64 candidates): the full 2000-step solve;
+    * the oracle's coherence of the final frames of the equal-coherence runs.
+    """
+    import numpy as np
+    import oracle
+    from threadpoolctl import threadpool_limits
+
+    blas = _blas_info()
+    res = {"cpu_model": _cpu_model(), "blas": blas, "host_cpus": len(os.sched_getaffinity(0))}
+
+    def step_rate(wl, c, mode="fp64"):
+        p = oracle.Params(n=wl.n, d=wl.d, candidates=c, mode=mode, radius0=wl.radius0, seed=wl.seed,
+                          stream_id=wl.stream_id, max_steps=10 ** 9)
+        st = oracle.haar_init(p)
+        t0 = time.perf_counter()
+        oracle.step(p, st)
+        el = time.perf_counter() - t0
+        return c / el, el
+
+    # size the headline sample from one candidate
+    _, one = step_rate(large, 1)
+    c_all = int(max(2, min(large.candidates, 0.3 * budget_s / max(one, 1e-3))))
+    rate_all, el_all = step_rate(large, c_all)
+    with threadpool_limits(limits=1, user_api="blas"):
+        _, one1 = step_rate(large, 1)
+        c_one = int(max(2, min(large.candidates, 0.2 * budget_s / max(one1, 1e-3))))
+        rate_one, el_one = step_rate(large, c_one)
+    res.update({
+        "value": rate_all,
         "unit": "evals/s",
-        "cores": int(threads),
+        "cores": int(blas.get("threads") or 1),
         "kind": "oracle",
-        "sample": f"one step with {c} of the {wl.candidates} candidates (BF16-screen form: perturb, "
-                  f"renormalise, FP64 and BF16-input Gram + max, select), N={wl.n}, d={wl.d}, numpy FP64; "
-                  f"{el:.1f} s",
-    }
+        "sample": f"one FP64-form step with {c_all} of the {large.candidates} candidates at N={large.n}, d={large.d} "
+                  f"(perturb, renormalise, one FP64 Gram + max per candidate, select), numpy + "
+                  f"{blas.get('library')} with {blas.get('threads')} threads; {el_all:.1f} s",
+        "one_thread": {"value": rate_one, "unit": "evals/s", "candidates": c_one, "seconds": el_one},
+    })
+    rate_med, el_med = step_rate(medium, medium.candidates)
+    res["plain_workload"] = {"value": rate_med, "unit": "evals/s", "seconds": el_med,
+                             "sample": f"one FP64 step with all {medium.candidates} candidates at N={medium.n}, "
+                                       f"d={medium.d}"}
+    p0 = oracle.Params(n=small.n, d=small.d, candidates=small.candidates, mode="fp64", radius0=small.radius0,
+                       seed=small.seed, stream_id=small.stream_id, max_steps=small.steps)
+    t0 = time.perf_counter()
+    st0, _ = oracle.solve(p0)
+    res["small_solve"] = {"wall_s": time.perf_counter() - t0, "final_mu": st0.mu, "steps": st0.t,
+                          "sample": f"the full {small.steps}-step FP64 solve at N={small.n}, d={small.d}, "
+                                    f"{small.candidates} candidates"}
+    if equal_frames:
+        res["equal_mu_oracle_check"] = {m: oracle.coherence(np.asarray(F)) for m, F in equal_frames.items()}
+    return res
 
 
 def copy_calibration(torch, mib):
@@ -376,12 +513,21 @@ def main():
     ap.add_argument("--other-modes", default="fp64,fp32",
                     help="also time these plain forms on the same workload (comma list, '' for none)")
     ap.add_argument("--other-steps", type=int, default=10)
+    ap.add_argument("--min-warmup-s", type=float, default=1.0,
+                    help="warm up at least this long, and until the Gram time is steady, before the timed steps")
+    ap.add_argument("--plain-modes", default="fp64,fp32",
+                    help="forms timed on the plain workload N=1024, d=32, 256 candidates ('' for none)")
+    ap.add_argument("--no-small-solve", dest="small_solve", action="store_false",
+                    help="skip the full 2000-step solve of the small workload")
+    ap.add_argument("--equal-mu-steps", type=int, default=300,
+                    help="steps of the BF16 form that fix the common target of the equal-coherence comparison "
+                         "(0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
     ap.add_argument("--miso-evals", type=int, default=10,
                     help="codebook quantiser calls to time (4096 codewords, d = 64, 65536 channels; 0: skip)")
-    ap.add_argument("--table2-dims", default="2,3,4,5,6",
+    ap.add_argument("--table2-dims", default="2,3,4,5",
                     help="dimensions d for the optimiser at N = d^2 (Table II comparison; empty: skip)")
     ap.add_argument("--smooth-max-evals", type=int, default=10,
                     help="evaluations of the section IV smooth maximum at the throughput shape (0: skip)")
@@ -409,14 +555,28 @@ def main():
     import paper_2207_06374_amd as lib
 
     wl = inputs.LARGE
-    main_res = run_mode(lib, torch, wl, "bf16", args.steps, args.warmup)
-    log(f"bf16 screen: {main_res['evals_per_s']:.0f} evals/s")
+    main_res = run_mode(lib, torch, wl, "bf16", args.steps, args.warmup, min_warm_s=args.min_warmup_s)
+    log(f"bf16 screen: {main_res['evals_per_s']:.0f} evals/s, Gram {main_res['gram']['avg_us']:.1f} us "
+        f"(warm-up {main_res['warmup']['seconds']:.1f} s)")
     others = {}
     for m in [x for x in args.other_modes.split(",") if x]:
-        r = run_mode(lib, torch, wl, m, args.other_steps, 2)
+        r = run_mode(lib, torch, wl, m, args.other_steps, 2, min_warm_s=0.5, window=20)
         log(f"{m}: {r['evals_per_s']:.0f} evals/s")
         others[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
         others[m]["gram_avg_us"] = r["gram"]["avg_us"]
+    plain = {}
+    for m in [x for x in args.plain_modes.split(",") if x]:
+        r = run_mode(lib, torch, inputs.MEDIUM, m, args.other_steps, 2, min_warm_s=0.5, window=20)
+        log(f"plain workload {m}: {r['evals_per_s']:.0f} evals/s, Gram {100 * r['gram_frac']:.1f} % of peak")
+        plain[m] = {k: r[k] for k in ("evals_per_s", "ms_per_step", "gram_tflops", "gram_frac", "final_mu")}
+        plain[m]["gram_avg_us"] = r["gram"]["avg_us"]
+        plain[m]["workload"] = (f"N={inputs.MEDIUM.n}, d={inputs.MEDIUM.d}, {inputs.MEDIUM.candidates} candidates, "
+                                f"radius {inputs.MEDIUM.radius0}, Haar start seed 0, {m.upper()} Gram on MFMA")
+    small = run_small_solve(lib, torch, inputs.SMALL) if args.small_solve else None
+    if small:
+        log(f"small solve: {small['steps']} steps in {small['gpu_wall_s']:.2f} s, mu {small['final_mu']:.10f}")
+    equal, equal_frames = (run_equal_mu(lib, torch, wl, args.equal_mu_steps) if args.equal_mu_steps > 0
+                           else (None, None))
 
     smooth = run_smooth_max(lib, torch, wl, args.smooth_max_evals) if args.smooth_max_evals > 0 else None
     miso = run_miso(lib, torch, 4096, 64, 65536, args.miso_evals) if args.miso_evals > 0 else None
@@ -460,8 +620,12 @@ def main():
         },
         # every kernel timed, over a few extra steps after the timed region
         "kernels_avg_us": {k: round(v["avg_us"], 3) for k, v in main_res["kernels"].items()},
+        "warmup_until_steady": main_res["warmup"],
         "final_mu": main_res["final_mu"],
         "other_modes": others,
+        "plain_workload": plain,
+        "small_solve": small,
+        "equal_mu": equal,
         "batched": batched,
         "serving": serving,
         "smooth_max": smooth,
@@ -470,7 +634,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(wl, inputs.MEDIUM, inputs.SMALL, args.cpu_seconds, equal_frames)
         line["cpu_baseline"]["gpu_speedup"] = main_res["evals_per_s"] / line["cpu_baseline"]["value"]
     print(json.dumps(line), flush=True)
 
