@@ -65,6 +65,7 @@ from .smoothmax import (  # noqa: F401
     smooth_max,
     smooth_max_bruteforce,
     smooth_max_grad,
+    smooth_max_hess_vec,
 )
 from .trust_region import (  # noqa: F401
     TRParams,

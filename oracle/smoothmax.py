@@ -112,3 +112,54 @@ def smooth_max_grad(Y, delta):
     D = Phi @ (W * G)
     c = np.sum((Phi.conj() * D).real, axis=0)
     return 2.0 * (D - Phi * c[None, :]) / norms[None, :]
+
+
+def smooth_max_hess_vec(Y, V, delta):
+    """Exact Hessian-vector product of F_{s,delta} over x = |G_jk|^2 (j < k)
+    with respect to the unconstrained frame Y, in the direction V: the
+    derivative d/dt of ``smooth_max_grad(Y + t V)`` at t = 0 (B_k of Alg. 1
+    in §IV is the Hessian of the objective).  Same convention as the
+    gradient: the result H with <U, H> = sum Re(conj(U) H) equals the second
+    derivative of F along U and V.
+
+    Forward differentiation of every line of the gradient's chain:
+      r_k = |y_k|, phi_k = y_k / r_k:
+        dr_k = Re(phi_k^H v_k),  dphi_k = (v_k - phi_k dr_k) / r_k;
+      G = Phi^H Phi:  dG = dPhi^H Phi + Phi^H dPhi;
+      x_jk = |G_jk|^2:  dx_jk = 2 Re(conj(G_jk) dG_jk);
+      w_jk = e_jk / sum_{l<m} e_lm, e = exp((x - s) / delta) (the shift s
+        cancels, so its own derivative does not enter):
+        dw_jk = w_jk (dx_jk - sigma) / delta,  sigma = sum_{l<m} w_lm dx_lm;
+      D = Phi (W o G):  dD = dPhi (W o G) + Phi (dW o G + W o dG);
+      c_k = Re(phi_k^H D_k):  dc_k = Re(dphi_k^H D_k + phi_k^H dD_k);
+      g_k = 2 (D_k - phi_k c_k) / r_k:
+        dg_k = 2 (dD_k - dphi_k c_k - phi_k dc_k) / r_k - g_k dr_k / r_k.
+    Returns None for a frame with a zero or non-finite column."""
+    Y = np.asarray(Y, dtype=np.complex128)
+    V = np.asarray(V, dtype=np.complex128)
+    Phi, norms = normalize_columns(Y)
+    if not np.all(np.isfinite(norms) & (norms > 0.0)):
+        return None
+    N = Phi.shape[1]
+    dr = np.sum((Phi.conj() * V).real, axis=0)
+    dPhi = (V - Phi * dr[None, :]) / norms[None, :]
+    G = gram(Phi)
+    dG = dPhi.conj().T @ Phi + Phi.conj().T @ dPhi
+    X = G.real * G.real + G.imag * G.imag
+    dX = 2.0 * (G.conj() * dG).real
+    iu = np.triu_indices(N, k=1)
+    s = float(np.max(X[iu]))
+    np.fill_diagonal(X, s)
+    E = np.exp((X - s) / delta)
+    np.fill_diagonal(E, 0.0)
+    total = math.fsum(E[iu].tolist())
+    W = E / total
+    sigma = math.fsum((W[iu] * dX[iu]).tolist())
+    dW = W * (dX - sigma) / delta
+    np.fill_diagonal(dW, 0.0)
+    D = Phi @ (W * G)
+    dD = dPhi @ (W * G) + Phi @ (dW * G + W * dG)
+    c = np.sum((Phi.conj() * D).real, axis=0)
+    dc = np.sum((dPhi.conj() * D).real, axis=0) + np.sum((Phi.conj() * dD).real, axis=0)
+    g = 2.0 * (D - Phi * c[None, :]) / norms[None, :]
+    return 2.0 * (dD - dPhi * c[None, :] - Phi * dc[None, :]) / norms[None, :] - g * (dr / norms)[None, :]

@@ -16,7 +16,9 @@ The outer step is the textbook trust-region iteration (Nocedal & Wright,
 Alg. 4.1): rho = (f(Y) - f(Y + p)) / (m(0) - m(p)); rho < 1/4 shrinks the
 radius by 4; rho > 3/4 with the step on the boundary doubles it (up to a
 maximum); the step is taken when rho > eta.  Hessian-vector products are
-central differences of the gradient along the unit direction.
+exact (B = the Hessian of the objective, as Alg. 1's dagger states:
+``smooth_max_hess_vec``); central differences of the gradient along the
+unit direction remain as an option (``fd_step > 0``).
 
 Vectors are the real coordinates of a complex d x N frame: the dot product
 is sum Re(conj(u) v) and the gradient is ``smooth_max_grad``.
@@ -29,7 +31,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .smoothmax import smooth_max, smooth_max_grad
+from .smoothmax import smooth_max, smooth_max_grad, smooth_max_hess_vec
 
 EXIT_SMALL_RESIDUAL = 0
 EXIT_NEGATIVE_CURVATURE = 1
@@ -98,7 +100,7 @@ class TRParams:
     eta: float = 0.1
     cg_tol: float = 1e-8
     cg_max_iter: int = 20
-    fd_step: float = 1e-6        # central-difference step along the unit direction
+    fd_step: float = 0.0         # 0: exact Hessian products; > 0: central differences with this step
 
 
 @dataclass
@@ -126,13 +128,21 @@ def fd_hess_vec(Y, delta, h):
     return hv
 
 
+def exact_hess_vec(Y, delta):
+    """v -> B v with B the exact Hessian of the smooth maximum at Y."""
+    def hv(v):
+        return smooth_max_hess_vec(Y, v, delta)
+    return hv
+
+
 def tr_step(Y, p: TRParams):
     """One outer trust-region iteration on the smooth maximum over |G|^2.
     Returns (new frame, report)."""
     Y = np.asarray(Y, dtype=np.complex128)
     f0 = smooth_max(Y, p.delta)[1]
     g = smooth_max_grad(Y, p.delta)
-    step, iters, code, Bstep = cg_steihaug(g, fd_hess_vec(Y, p.delta, p.fd_step), p.radius, p.cg_tol, p.cg_max_iter)
+    hv = fd_hess_vec(Y, p.delta, p.fd_step) if p.fd_step > 0 else exact_hess_vec(Y, p.delta)
+    step, iters, code, Bstep = cg_steihaug(g, hv, p.radius, p.cg_tol, p.cg_max_iter)
     snorm = math.sqrt(rdot(step, step))
     pred = -(rdot(g, step) + 0.5 * rdot(step, Bstep))
     if snorm == 0.0 or not pred > 0.0:
@@ -159,7 +169,7 @@ class OptParams:
     eta: float = 0.1
     cg_tol: float = 1e-10
     cg_max_iter: int = 0                  # 0: 2 d N (the dimension of the real search space)
-    fd_step: float = 1e-6
+    fd_step: float = 0.0                  # 0: exact Hessian products
     seed: int = 0
 
 
