@@ -214,6 +214,28 @@ size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d);
 trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double delta, double* out,
                               double* grad, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Bytes of workspace trstmi_lse_hvp needs (0 if invalid or d > 64). */
+size_t trstmi_lse_hvp_workspace_bytes(int64_t n, int64_t d);
+
+/*
+ * Exact Hessian-vector product of the smooth maximum over x = |G_jk|^2 with
+ * respect to the unconstrained frame (section IV; Alg. 1 takes B_k to be the
+ * Hessian of the objective): out (device, 2 doubles) = (s, F) as
+ * trstmi_lse_grad gives them; hv (device, frame layout) = H v, the
+ * derivative of trstmi_lse_grad's gradient at `frame` along the direction v
+ * (device, frame layout), so that sum Re(conj(u) hv) is the second
+ * derivative of F along u and v.  Forward differentiation of the gradient's
+ * chain (column norms, Gram, |G|^2, the weights exp((x - s)/delta) / S, the
+ * product Phi (W o G) and the projection through the normalisation), in FP64
+ * with a fixed summation order (repeatable bits).  A zero or non-finite
+ * column gives out = (+inf, +inf) and a NaN product.  Requires n >= 2,
+ * 1 <= d <= 64 (TRSTMI_E_UNSUPPORTED above), delta finite and > 0; workspace
+ * of trstmi_lse_hvp_workspace_bytes(n, d) bytes.  Stream-ordered.
+ */
+trstmi_status trstmi_lse_hvp(int64_t n, int64_t d, const double* frame, const double* v, double delta,
+                             double* out, double* hv, void* workspace, size_t workspace_bytes,
+                             hipStream_t stream);
+
 /* Exit of Steihaug CG (trstmi_tr_report.cg_exit). */
 enum {
   TRSTMI_CG_SMALL_RESIDUAL = 0,      /* |r| < cg_tol: interior step */
@@ -230,7 +252,8 @@ typedef struct {
   double eta;         /* the step is taken when rho > eta, 0 <= eta < 1/4 */
   double cg_tol;      /* residual norm that ends CG, > 0 */
   int32_t cg_max_iter;/* >= 1 */
-  double fd_step;     /* central-difference step of Hessian-vector products, > 0 */
+  double fd_step;     /* 0: exact Hessian-vector products (trstmi_lse_hvp); > 0: central
+                         differences of the gradient with this step instead */
 } trstmi_tr_params;
 
 typedef struct {
@@ -251,7 +274,8 @@ size_t trstmi_tr_workspace_bytes(int64_t n, int64_t d);
  * with the textbook's completion of the printed listing (boundary test on
  * the new iterate, residual test on the new residual, the beta / direction
  * update; negative curvature goes to the boundary point with the lower
- * model value); B p by central differences of trstmi_lse_grad along p/|p|.
+ * model value); B p exactly (B = the Hessian at the frame, trstmi_lse_hvp),
+ * or by central differences of trstmi_lse_grad along p/|p| if fd_step > 0.
  * Then rho = (F(frame) - F(frame + p)) / (m(0) - m(p)); rho < 1/4 divides
  * the radius by 4, rho > 3/4 with |p| = radius doubles it (up to
  * radius_max), and frame <- frame + p when rho > eta.  *rep (host) gets
@@ -276,7 +300,7 @@ typedef struct {
   double eta;              /* 0 <= eta < 1/4 */
   double cg_tol;           /* > 0 */
   int32_t cg_max_iter;     /* >= 1, or 0 for 2 d N */
-  double fd_step;          /* > 0 */
+  double fd_step;          /* 0: exact Hessian-vector products; > 0: central differences */
   int32_t concurrency;     /* starts run at once (one host thread and stream each), 1 .. 64 */
   int32_t first_restart;   /* the starts are l = first_restart .. first_restart + restarts - 1, >= 0
                               (one run of L starts may be split into several calls) */
@@ -497,14 +521,20 @@ trstmi_status trstmi_timing_read(const char* kernel, double* total_ms, int64_t* 
 const char* trstmi_last_error(void);
 
 /* ---------------------------------------------------------------------------
- * Serving form: a solve server with continuous admission on one GPU.
- * Requests are queued on submission; slot threads (each with a HIP stream of
- * its own, default priority) take the request at the head of the queue as
- * soon as its footprint fits in the caller's device pool, run
- * trstmi_init_haar and trstmi_solve in that range, and release it.  First in
- * line is served first; a request larger than the pool is rejected at once.
- * Each result is what the same request gives solved alone (its own seed and
- * stream id).
+ * Serving form: a solve server with continuous batching on one GPU.
+ * Requests are queued on submission.  One engine thread (with a HIP stream
+ * of its own, default priority) keeps a table of admitted requests in
+ * device memory and advances all of them together: per step, each kernel of
+ * the BF16-screen step (trstmi_step's) is launched once per group of
+ * admitted requests with the same d, every request running exactly its own
+ * single-search arithmetic.  After every `chunk` steps the engine reads back
+ * every request's state in one copy, retires the finished ones and admits
+ * the requests at the head of the queue into the freed rows as long as
+ * their footprint fits in the caller's pool (first in line is served first;
+ * a request larger than the pool is rejected at once).  While the admitted
+ * set is unchanged a chunk is captured once into a HIP graph and replayed.
+ * Each result is what trstmi_init_haar + trstmi_solve give for the same
+ * request alone (its own seed and stream id), bit for bit, in any mix.
  * ------------------------------------------------------------------------- */
 enum {
   TRSTMI_REQ_QUEUED = 0,
@@ -518,12 +548,14 @@ enum {
 typedef struct trstmi_server trstmi_server;  /* opaque */
 
 typedef struct {
-  void* pool;              /* device memory owned by the caller, 256-byte aligned, kept until destroy */
-  uint64_t pool_bytes;     /* >= 256 */
-  int32_t slots;           /* solves at once, 1 .. 64 */
-  int32_t chunk;           /* steps per captured graph of trstmi_solve, >= 1 */
+  void* pool;              /* device memory owned by the caller, 256-byte aligned, kept until destroy;
+                              its first trstmi_server_table_bytes(slots) bytes hold the engine table,
+                              the rest the admitted requests */
+  uint64_t pool_bytes;     /* > trstmi_server_table_bytes(slots) + 256 */
+  int32_t slots;           /* requests admitted at once (rows of the table), 1 .. 1024 */
+  int32_t chunk;           /* steps between admissions and state read-backs, >= 1 */
   int32_t candidates;      /* per step, >= 1 */
-  int32_t mode;            /* TRSTMI_MODE_* */
+  int32_t mode;            /* TRSTMI_MODE_BF16_SCREEN (others: TRSTMI_E_UNSUPPORTED) */
   int32_t recheck_topk;    /* BF16 screen: candidates re-evaluated in FP64, >= 1 */
   int32_t reserved0;
   double radius0;          /* > 0 */
@@ -559,8 +591,17 @@ typedef struct {
  * the parameters are invalid. */
 size_t trstmi_request_footprint(const trstmi_params* p);
 
-/* Starts a server (its slot threads and their streams) on the current
- * device; *out receives it. */
+/* Bytes at the start of the pool that hold the engine table for `slots`
+ * rows (0 if slots is out of range). */
+size_t trstmi_server_table_bytes(int32_t slots);
+
+/* The Welch bound sqrt((n - d) / (d (n - 1))) (0 for n <= d; section II),
+ * the default target of a request is target_factor times it.  NaN for
+ * n < 2 or d < 1. */
+double trstmi_welch_bound(int64_t n, int64_t d);
+
+/* Starts a server (its engine thread and stream) on the current device;
+ * *out receives it. */
 trstmi_status trstmi_server_create(const trstmi_server_params* params, trstmi_server** out);
 
 /* Queues a request; *id (host) receives its id.  A request that cannot run
@@ -587,8 +628,8 @@ trstmi_status trstmi_server_forget(trstmi_server* server, int64_t id);
 /* Pool use (now and peak), running and queued requests, submissions. */
 trstmi_status trstmi_server_get_stats(trstmi_server* server, trstmi_server_stats* out);
 
-/* Lets the running requests finish, cancels the queued ones, joins the slot
- * threads and frees the server (the pool stays the caller's). */
+/* Lets the running requests finish, cancels the queued ones, joins the
+ * engine thread and frees the server (the pool stays the caller's). */
 trstmi_status trstmi_server_destroy(trstmi_server* server);
 
 /* Releases the library's internal state (the pooled HIP events of kernel

@@ -166,15 +166,37 @@ def lse_grad(frame, n, d, delta, out=None, grad=None, workspace=None, stream=Non
     return out, grad
 
 
+def lse_hvp_workspace_bytes(n, d):
+    return _abi.lib().trstmi_lse_hvp_workspace_bytes(int(n), int(d))
+
+
+def lse_hvp(frame, v, n, d, delta, out=None, hv=None, workspace=None, stream=None):
+    """Exact Hessian-vector product of the smooth maximum over |G_jk|^2 at
+    the (unnormalised) device frame along the device direction v (frame
+    layout).  Returns (out, hv): out = (s, F); hv has the frame's layout."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=frame.device)
+    if hv is None:
+        hv = torch.empty_like(frame)
+    need = lse_hvp_workspace_bytes(n, d)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=frame.device)
+    _abi.check(_abi.lib().trstmi_lse_hvp(int(n), int(d), _ptr(frame), _ptr(v), float(delta), _ptr(out), _ptr(hv),
+                                         _ptr(workspace), workspace.numel(), _stream(stream)), "trstmi_lse_hvp")
+    return out, hv
+
+
 def tr_workspace_bytes(n, d):
     return _abi.lib().trstmi_tr_workspace_bytes(int(n), int(d))
 
 
-def tr_step(frame, n, d, delta, radius, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg_max_iter=20, fd_step=1e-6,
+def tr_step(frame, n, d, delta, radius, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg_max_iter=20, fd_step=0.0,
             workspace=None, stream=None):
     """One trust-region step (Steihaug CG + ratio test) on the smooth maximum
-    of the device frame, updated in place when the step is taken.  Returns the
-    report as a dict."""
+    of the device frame, updated in place when the step is taken.  fd_step 0
+    uses exact Hessian-vector products, fd_step > 0 central differences of
+    the gradient.  Returns the report as a dict."""
     torch = _torch()
     p = _abi.TRParams(float(delta), float(radius), float(radius_max), float(eta), float(cg_tol), int(cg_max_iter),
                       float(fd_step))
@@ -187,7 +209,7 @@ def tr_step(frame, n, d, delta, radius, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg
 
 
 def optimize(n, d, restarts=None, deltas=(1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4), steps_per_delta=40, seed=0,
-             radius0=0.1, radius_min=1e-10, radius_max=1.0, eta=0.1, cg_tol=1e-10, cg_max_iter=0, fd_step=1e-6,
+             radius0=0.1, radius_min=1e-10, radius_max=1.0, eta=0.1, cg_tol=1e-10, cg_max_iter=0, fd_step=0.0,
              concurrency=None, first_restart=0, device="cuda", workspace=None, stream=None):
     """The outer procedure of Alg. 2 (delta continuation and random restarts
     around trust-region steps).  Returns (best frame as a device tensor,

@@ -160,6 +160,10 @@ SIGNATURES = {
     "trstmi_lse": (_i32, [_i64, _i64, _vp, ctypes.c_double, _i32, _vp, _vp, _sz, _vp]),
     "trstmi_lse_grad_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    "trstmi_server_table_bytes": (_sz, [_i32]),
+    "trstmi_welch_bound": (ctypes.c_double, [_i64, _i64]),
+    "trstmi_lse_hvp_workspace_bytes": (_sz, [_i64, _i64]),
+    "trstmi_lse_hvp": (_i32, [_i64, _i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_tr_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_tr_step": (_i32, [_i64, _i64, _vp, _P(TRParams), _P(TRReport), _vp, _sz, _vp]),
     "trstmi_optimize_workspace_bytes": (_sz, [_i64, _i64, _i32]),

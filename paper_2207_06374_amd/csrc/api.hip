@@ -296,15 +296,8 @@ GramArgs gram_base(int64_t n, int64_t d, const void* cand, int64_t stride, int32
   return g;
 }
 
-trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char* ws, const double* z,
-                           const trstmi_report* rep, hipStream_t s) {
-  const Layout L = layout_of(p);
-  const int C = p->candidates;
-  uint64_t* cand_max = (uint64_t*)(ws + L.cand_max);
-  Decision* dec = (Decision*)(ws + L.dec);
-  const int64_t slot_stride = L.n * L.ldc;
-  const int64_t slot_stride64 = L.n * L.ld;
-
+PerturbArgs candidate_args(const trstmi_params* p, const trstmi_state* st, const Layout& L, char* ws,
+                           const double* z) {
   PerturbArgs pa = perturb_base(p);
   pa.base = st->frame;
   pa.radius = st->radius;
@@ -316,10 +309,13 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   pa.out = ws + L.cand;
   pa.out_kind = p->mode == TRSTMI_MODE_FP64 ? kOutF64 : (p->mode == TRSTMI_MODE_FP32 ? kOutF32 : kOutBF16);
   pa.out_ld = L.ldc;
-  pa.out_slot_stride = slot_stride;
-  pa.zero_max = cand_max;
-  TRY_HIP(TIMED("perturb", s, launch_perturb(pa, C, s)), "perturb");
+  pa.out_slot_stride = L.n * L.ldc;
+  pa.zero_max = (uint64_t*)(ws + L.cand_max);
+  return pa;
+}
 
+SelectArgs select_args(const trstmi_params* p, const trstmi_state* st, const Layout& L, char* ws,
+                       const trstmi_report* rep) {
   SelectArgs sa{};
   sa.tau = tau_of(p);
   sa.mu = st->mu;
@@ -332,85 +328,14 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   sa.radius_max = p->radius_max;
   sa.max_steps = p->max_steps;
   sa.target_mu = p->target_mu;
-  sa.dec = dec;
+  sa.dec = (Decision*)(ws + L.dec);
   sa.rep_best = rep ? rep->best : nullptr;
+  return sa;
+}
 
-  if (p->mode == TRSTMI_MODE_FP64 || p->mode == TRSTMI_MODE_FP32) {
-    const bool f32 = p->mode == TRSTMI_MODE_FP32;
-    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ldc, f32 ? kTileF32 : kTileF64, cand_max, st->flags);
-    TRY_HIP(TIMED(f32 ? "gram_f32" : "gram_f64", s, f32 ? launch_gram_f32(g, C, s) : launch_gram_f64(g, C, s)), "gram");
-    sa.cand_max = cand_max;
-    sa.count = C;
-    sa.is_f32 = f32 ? 1 : 0;
-    sa.rep_cand_mu = rep ? rep->cand_mu : nullptr;
-    TRY_HIP(TIMED("select", s, launch_select(sa, s)), "select");
-  } else {
-    uint32_t* tile_max = (uint32_t*)(ws + L.tile_max);
-    int32_t* rechecked = (int32_t*)(ws + L.rechecked);
-    double* thr = (double*)(ws + L.thr);
-    uint64_t* recheck_max = (uint64_t*)(ws + L.recheck_max);
-    GramArgs g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ldc, kTileBF16, cand_max, st->flags);
-    g.tile_max = tile_max;
-    TRY_HIP(TIMED("gram_bf16", s, launch_gram_bf16(g, C, s)), "gram_bf16");
-
-    TopkArgs ta{};
-    ta.cand_max = cand_max;
-    ta.C = C;
-    ta.k = L.k;
-    ta.eps = screen_eps(L.d);
-    ta.screen_tie = 2e-5;
-    ta.flags = st->flags;
-    ta.rechecked = rechecked;
-    ta.thr = thr;
-    ta.dec = dec;
-    ta.rep_cand_mu = rep ? rep->cand_mu : nullptr;
-    ta.rep_rechecked = rep ? rep->rechecked : nullptr;
-    ta.tile_max = tile_max;
-    ta.screen_nt = nt_of(L.n, kTileBF16);
-    ta.list = (int2*)(ws + L.list);
-    ta.list_count = (int32_t*)(ws + L.list_count);
-    ta.list_cap = (int32_t)(L.k * ntiles_of(L.n, kTileBF16));
-    TRY_HIP(TIMED("topk", s, launch_topk(ta, s)), "topk");
-
-    PerturbArgs pr = pa;
-    pr.cand_idx = rechecked;
-    pr.out = ws + L.recheck;
-    pr.out_kind = kOutF64;
-    pr.out_ld = L.ld;
-    pr.out_slot_stride = slot_stride64;
-    pr.zero_max = recheck_max;
-    TRY_HIP(TIMED("perturb_recheck", s, launch_perturb(pr, L.k, s)), "perturb_recheck");
-
-    RecheckArgs ra{};
-    ra.screen = (const uint16_t*)(ws + L.cand);
-    ra.screen_stride = slot_stride;
-    ra.ldk16 = L.ldc;
-    ra.cand64 = (const double*)(ws + L.recheck);
-    ra.stride64 = slot_stride64;
-    ra.ld64 = L.ld;
-    ra.n = (int32_t)L.n;
-    ra.d = (int32_t)L.d;
-    ra.nt = nt_of(L.n, kTileBF16);
-    ra.k = L.k;
-    ra.list = (const int2*)(ws + L.list);
-    ra.count = (const int32_t*)(ws + L.list_count);
-    ra.list_cap = ta.list_cap;
-    ra.rechecked = rechecked;
-    ra.thr = thr;
-    ra.recheck_max = recheck_max;
-    ra.flags = st->flags;
-    TRY_HIP(TIMED("recheck", s, launch_recheck_pairs(ra, s)), "recheck");
-
-    sa.cand_max = recheck_max;
-    sa.count = L.k;
-    sa.is_f32 = 0;
-    sa.slot_cand = rechecked;
-    sa.use_screen_near = 1;
-    sa.rep_cand_mu = rep ? rep->recheck_mu : nullptr;
-    TRY_HIP(TIMED("select", s, launch_select(sa, s)), "select");
-  }
-
-  // commit: regenerate the accepted candidate in FP64 into the frame, in place
+// commit: regenerate the accepted candidate in FP64 into the frame, in place
+PerturbArgs commit_args(const trstmi_params* p, const trstmi_state* st, const Layout& L, char* ws, const double* z) {
+  Decision* dec = (Decision*)(ws + L.dec);
   PerturbArgs pc = perturb_base(p);
   pc.base = st->frame;
   pc.radius = &dec->radius_old;
@@ -424,7 +349,122 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   pc.out_kind = kOutF64;
   pc.out_ld = (int32_t)(2 * L.d);
   pc.out_slot_stride = 2 * L.d * L.n;
-  TRY_HIP(TIMED("commit", s, launch_perturb(pc, 1, s)), "commit");
+  return pc;
+}
+
+}  // namespace
+
+namespace trstmi {
+
+// Every record of one BF16-screen step (parameters already validated, mode
+// TRSTMI_MODE_BF16_SCREEN).
+StepArgs bf16_step_args(const trstmi_params* p, const trstmi_state* st, char* ws, const double* z,
+                        const trstmi_report* rep) {
+  const Layout L = layout_of(p);
+  const int C = p->candidates;
+  const int64_t slot_stride = L.n * L.ldc;
+  const int64_t slot_stride64 = L.n * L.ld;
+  uint64_t* cand_max = (uint64_t*)(ws + L.cand_max);
+  StepArgs A{};
+  A.pa = candidate_args(p, st, L, ws, z);
+  A.sa = select_args(p, st, L, ws, rep);
+
+  uint32_t* tile_max = (uint32_t*)(ws + L.tile_max);
+  int32_t* rechecked = (int32_t*)(ws + L.rechecked);
+  double* thr = (double*)(ws + L.thr);
+  uint64_t* recheck_max = (uint64_t*)(ws + L.recheck_max);
+  A.g = gram_base(L.n, L.d, ws + L.cand, slot_stride, L.ldc, kTileBF16, cand_max, st->flags);
+  A.g.tile_max = tile_max;
+  gram_bf16_prepare(A.g, C);
+
+  TopkArgs& ta = A.ta;
+  ta.cand_max = cand_max;
+  ta.C = C;
+  ta.k = L.k;
+  ta.eps = screen_eps(L.d);
+  ta.screen_tie = 2e-5;
+  ta.flags = st->flags;
+  ta.rechecked = rechecked;
+  ta.thr = thr;
+  ta.dec = (Decision*)(ws + L.dec);
+  ta.rep_cand_mu = rep ? rep->cand_mu : nullptr;
+  ta.rep_rechecked = rep ? rep->rechecked : nullptr;
+  ta.tile_max = tile_max;
+  ta.screen_nt = nt_of(L.n, kTileBF16);
+  ta.list = (int2*)(ws + L.list);
+  ta.list_count = (int32_t*)(ws + L.list_count);
+  ta.list_cap = (int32_t)(L.k * ntiles_of(L.n, kTileBF16));
+
+  A.pr = A.pa;
+  A.pr.cand_idx = rechecked;
+  A.pr.out = ws + L.recheck;
+  A.pr.out_kind = kOutF64;
+  A.pr.out_ld = L.ld;
+  A.pr.out_slot_stride = slot_stride64;
+  A.pr.zero_max = recheck_max;
+
+  RecheckArgs& ra = A.ra;
+  ra.screen = (const uint16_t*)(ws + L.cand);
+  ra.screen_stride = slot_stride;
+  ra.ldk16 = L.ldc;
+  ra.cand64 = (const double*)(ws + L.recheck);
+  ra.stride64 = slot_stride64;
+  ra.ld64 = L.ld;
+  ra.n = (int32_t)L.n;
+  ra.d = (int32_t)L.d;
+  ra.nt = nt_of(L.n, kTileBF16);
+  ra.k = L.k;
+  ra.list = (const int2*)(ws + L.list);
+  ra.count = (const int32_t*)(ws + L.list_count);
+  ra.list_cap = ta.list_cap;
+  ra.rechecked = rechecked;
+  ra.thr = thr;
+  ra.recheck_max = recheck_max;
+  ra.flags = st->flags;
+
+  A.sa.cand_max = recheck_max;
+  A.sa.count = L.k;
+  A.sa.is_f32 = 0;
+  A.sa.slot_cand = rechecked;
+  A.sa.use_screen_near = 1;
+  A.sa.rep_cand_mu = rep ? rep->recheck_mu : nullptr;
+
+  A.pc = commit_args(p, st, L, ws, z);
+  return A;
+}
+
+}  // namespace trstmi
+
+namespace {
+
+trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char* ws, const double* z,
+                           const trstmi_report* rep, hipStream_t s) {
+  const Layout L = layout_of(p);
+  const int C = p->candidates;
+  if (p->mode == TRSTMI_MODE_BF16_SCREEN) {
+    const StepArgs A = bf16_step_args(p, st, ws, z, rep);
+    TRY_HIP(TIMED("perturb", s, launch_perturb(A.pa, C, s)), "perturb");
+    TRY_HIP(TIMED("gram_bf16", s, launch_gram_bf16(A.g, C, s)), "gram_bf16");
+    TRY_HIP(TIMED("topk", s, launch_topk(A.ta, s)), "topk");
+    TRY_HIP(TIMED("perturb_recheck", s, launch_perturb(A.pr, L.k, s)), "perturb_recheck");
+    TRY_HIP(TIMED("recheck", s, launch_recheck_pairs(A.ra, s)), "recheck");
+    TRY_HIP(TIMED("select", s, launch_select(A.sa, s)), "select");
+    TRY_HIP(TIMED("commit", s, launch_perturb(A.pc, 1, s)), "commit");
+    return TRSTMI_OK;
+  }
+  const PerturbArgs pa = candidate_args(p, st, L, ws, z);
+  TRY_HIP(TIMED("perturb", s, launch_perturb(pa, C, s)), "perturb");
+  const bool f32 = p->mode == TRSTMI_MODE_FP32;
+  uint64_t* cand_max = (uint64_t*)(ws + L.cand_max);
+  GramArgs g = gram_base(L.n, L.d, ws + L.cand, L.n * L.ldc, L.ldc, f32 ? kTileF32 : kTileF64, cand_max, st->flags);
+  TRY_HIP(TIMED(f32 ? "gram_f32" : "gram_f64", s, f32 ? launch_gram_f32(g, C, s) : launch_gram_f64(g, C, s)), "gram");
+  SelectArgs sa = select_args(p, st, L, ws, rep);
+  sa.cand_max = cand_max;
+  sa.count = C;
+  sa.is_f32 = f32 ? 1 : 0;
+  sa.rep_cand_mu = rep ? rep->cand_mu : nullptr;
+  TRY_HIP(TIMED("select", s, launch_select(sa, s)), "select");
+  TRY_HIP(TIMED("commit", s, launch_perturb(commit_args(p, st, L, ws, z), 1, s)), "commit");
   return TRSTMI_OK;
 }
 
@@ -558,6 +598,12 @@ trstmi_status batch_prepare(const trstmi_batch_params* p, const trstmi_batch_ins
 namespace trstmi {
 // The calling thread's error message, for other parts of the library.
 trstmi_status set_last_error(trstmi_status code, const std::string& msg) { return fail(code, msg); }
+
+void lse_grad_scalars(int64_t n, int64_t d, char* ws, const uint64_t** s_bits, const double** log_sum) {
+  const size_t frame_bytes = align256((size_t)n * ld_mode(d, TRSTMI_MODE_FP64) * 8);
+  *s_bits = (const uint64_t*)(ws + frame_bytes);
+  *log_sum = (const double*)(ws + trstmi_lse_workspace_bytes(n, d));
+}
 }  // namespace trstmi
 
 extern "C" {
@@ -813,6 +859,56 @@ trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double 
   return TRSTMI_OK;
 }
 
+size_t trstmi_lse_hvp_workspace_bytes(int64_t n, int64_t d) {
+  if (check_size(n, d) || d > 64) return 0;
+  return trstmi_lse_workspace_bytes(n, d) + 256 + hv_scratch_bytes(n, d);
+}
+
+trstmi_status trstmi_lse_hvp(int64_t n, int64_t d, const double* frame, const double* v, double delta, double* out,
+                             double* hv, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (d > 64) return fail(TRSTMI_E_UNSUPPORTED, "the Hessian-vector product supports d <= 64");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TRSTMI_E_INVALID_ARG, "delta must be finite and > 0");
+  if (!frame || !v || !out || !hv) return fail(TRSTMI_E_INVALID_ARG, "frame, v, out and hv must be device pointers");
+  if (((uintptr_t)frame & 15) || ((uintptr_t)v & 15) || ((uintptr_t)out & 7) || ((uintptr_t)hv & 15))
+    return fail(TRSTMI_E_INVALID_ARG, "misaligned pointer");
+  const size_t need = trstmi_lse_hvp_workspace_bytes(n, d);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  const size_t lse_bytes = trstmi_lse_workspace_bytes(n, d);
+  char* ws = (char*)workspace;
+  const int32_t ld = ld_mode(d, TRSTMI_MODE_FP64);
+  const size_t frame_bytes = align256((size_t)n * ld * 8);
+  uint64_t* mx = (uint64_t*)(ws + frame_bytes);
+  double* partial = (double*)(ws + frame_bytes + 256);
+  double* log_sum = (double*)(ws + lse_bytes);
+  const int64_t nt = (n + kTileF64 - 1) / kTileF64;
+  PerturbArgs pa{};
+  pa.base = frame;
+  pa.have_z = 0;
+  pa.n = n;
+  pa.d = (int32_t)d;
+  pa.out = ws;
+  pa.out_kind = kOutF64;
+  pa.out_ld = ld;
+  pa.out_slot_stride = n * ld;
+  pa.zero_max = mx;
+  TRY_HIP(launch_perturb(pa, 1, stream), "normalise");
+  GramArgs g = gram_base(n, d, ws, n * ld, ld, kTileF64, mx, nullptr);
+  TRY_HIP(launch_lse_pass(g, delta, 1, partial, stream), "lse_pass");
+  TRY_HIP(launch_lse_finish(mx, partial, nt * (nt + 1) / 2, delta, 1, out, log_sum, stream), "lse_finish");
+  HvArgs h{};
+  hv_layout(h, ws + lse_bytes + 256, n, d);
+  h.raw = frame;
+  h.v = v;
+  h.s_bits = mx;
+  h.log_sum = log_sum;
+  h.inv_delta = 1.0 / delta;
+  h.out = hv;
+  TRY_HIP(TIMED("lse_hv", stream, launch_lse_hv(h, stream)), "lse_hv");
+  return TRSTMI_OK;
+}
+
 size_t trstmi_tr_workspace_bytes(int64_t n, int64_t d) {
   const size_t g = trstmi_lse_grad_workspace_bytes(n, d);
   return g ? align256(g) + tr_vectors_bytes(n, d) : 0;
@@ -825,7 +921,7 @@ trstmi_status trstmi_tr_step(int64_t n, int64_t d, double* frame, const trstmi_t
   if (d > 64) return fail(TRSTMI_E_UNSUPPORTED, "the trust-region step supports d <= 64");
   if (!tp || !rep) return fail(TRSTMI_E_INVALID_ARG, "params and report must be host pointers");
   auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
-  if (!pos(tp->delta) || !pos(tp->radius) || !pos(tp->cg_tol) || !pos(tp->fd_step) ||
+  if (!pos(tp->delta) || !pos(tp->radius) || !pos(tp->cg_tol) || !(tp->fd_step == 0.0 || pos(tp->fd_step)) ||
       !(tp->radius_max >= tp->radius) || !std::isfinite(tp->radius_max) || !(tp->eta >= 0.0 && tp->eta < 0.25) ||
       tp->cg_max_iter < 1)
     return fail(TRSTMI_E_INVALID_ARG, "invalid trust-region parameters");
@@ -943,7 +1039,7 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op,
   auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
   bool ok = op->restarts >= 1 && op->n_deltas >= 1 && op->deltas && op->steps_per_delta >= 1 && pos(op->radius0) &&
             op->radius_min >= 0.0 && op->radius_max >= op->radius0 && std::isfinite(op->radius_max) &&
-            op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) && op->cg_max_iter >= 0 && pos(op->fd_step) &&
+            op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) && op->cg_max_iter >= 0 && (op->fd_step == 0.0 || pos(op->fd_step)) &&
             op->concurrency >= 1 && op->concurrency <= 64 && op->first_restart >= 0 &&
             (int64_t)op->first_restart + op->restarts <= INT32_MAX;
   for (int32_t k = 0; ok && k < op->n_deltas; ++k) ok = pos(op->deltas[k]);
@@ -1349,6 +1445,7 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 10; }
+int32_t trstmi_abi_version(void) { return 11; }
 
 }  // extern "C"
+

@@ -274,9 +274,8 @@ __device__ __forceinline__ void seg_decode(int s, int nt, int& bi, int& bj0, int
 // Narrow kernel.  Two blocks per CU while the whole-K rows fit (2d <= 160);
 // one block with the full register file (VGPRs and AGPRs) beyond that.
 template <int KS>
-__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) {
+__device__ __forceinline__ void gram_bf16_narrow(const GramArgs& a, int b) {
   if (a.flags && (*a.flags & kFlagDone)) return;
-  const int b = blockIdx.x;
   const int local = b >> 3;
   const int slot = (local / a.nseg) * 8 + (b & 7);
   const int seg = local % a.nseg;
@@ -478,9 +477,8 @@ __device__ __forceinline__ void seg_decode_k(int s, int nt, int& r, int& bj0, in
 }
 
 template <int KS>
-__global__ __launch_bounds__(256, 2) void k_gram_bf16_k(GramArgs a) {
+__device__ __forceinline__ void gram_bf16_wide(const GramArgs& a, int b) {
   if (a.flags && (*a.flags & kFlagDone)) return;
-  const int b = blockIdx.x;
   const int local = b >> 3;
   const int slot = (local / a.nseg) * 8 + (b & 7);
   const int seg = local % a.nseg;
@@ -538,6 +536,30 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16_k(GramArgs a) {
   }
 }
 
+template <int KS>
+__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) {
+  gram_bf16_narrow<KS>(a, blockIdx.x);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_gram_bf16_k(GramArgs a) {
+  gram_bf16_wide<KS>(a, blockIdx.x);
+}
+
+// Group launches: search blockIdx.y of the table (each record with its own
+// slots and nseg; blocks past a search's own grid return at once).
+template <int KS>
+__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16_tab(TabRef t) {
+  const GramArgs a = *(const GramArgs*)(t.base + (size_t)t.list[blockIdx.y] * t.stride);
+  gram_bf16_narrow<KS>(a, blockIdx.x);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_gram_bf16_k_tab(TabRef t) {
+  const GramArgs a = *(const GramArgs*)(t.base + (size_t)t.list[blockIdx.y] * t.stride);
+  gram_bf16_wide<KS>(a, blockIdx.x);
+}
+
 int k_segments(int nt) {
   int total = 0;
   for (int r = 0; 2 * r < nt; ++r) total += (nt - 2 * r + kSegK - 1) / kSegK;
@@ -581,15 +603,15 @@ __device__ __forceinline__ void pair_f64_part(const double* c64, int ld, int d, 
 // listed screen tile, A and B fragments read straight from global memory (no
 // LDS, no barrier), so every item of every listed tile runs at once.
 template <int KS>
-__global__ __launch_bounds__(64) void k_recheck_pairs(RecheckArgs a) {
+__device__ __forceinline__ void recheck_body(const RecheckArgs& a, int bx, int gx) {
   if (*a.flags & kFlagDone) return;
   __shared__ int2 hits[32 * 32];
   __shared__ int nhits;
   const int lane = threadIdx.x;
-  if (blockIdx.x == 0 && lane < a.k && !(a.thr[lane] > -__builtin_inf()))
+  if (bx == 0 && lane < a.k && !(a.thr[lane] > -__builtin_inf()))
     atomicMax((unsigned long long*)&a.recheck_max[lane], ~0ull);  // invalid candidate
   const int items = *a.count * 16;
-  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+  for (int it = bx; it < items; it += gx) {
     const int2 item = a.list[it >> 4];
     const int rq = (it >> 2) & 3, cq = it & 3;
     int bi, bj;
@@ -669,6 +691,17 @@ __global__ __launch_bounds__(64) void k_recheck_pairs(RecheckArgs a) {
     best = wave_max_u64(best);
     if (lane == 0 && best) atomicMax((unsigned long long*)&a.recheck_max[slot], (unsigned long long)best);
   }
+}
+
+template <int KS>
+__global__ __launch_bounds__(64) void k_recheck_pairs(RecheckArgs a) {
+  recheck_body<KS>(a, blockIdx.x, gridDim.x);
+}
+
+template <int KS>
+__global__ __launch_bounds__(64) void k_recheck_pairs_tab(TabRef t) {
+  const RecheckArgs a = *(const RecheckArgs*)(t.base + (size_t)t.list[blockIdx.y] * t.stride);
+  recheck_body<KS>(a, blockIdx.x, gridDim.x);
 }
 
 // General K: chunks of 128 bf16 through LDS, each wave a 64 x 64 quadrant.
@@ -779,23 +812,64 @@ __global__ __launch_bounds__(256) void k_gram_bf16_chunked(GramArgs a) {
 }
 
 template <int KS>
-hipError_t launch_rp(const RecheckArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_recheck_pairs<KS>, dim3(grid), dim3(64), 0, s, a);
+hipError_t launch_rp(const RecheckArgs& a, int grid, hipStream_t s, const TabRef* tab) {
+  if (tab)
+    hipLaunchKernelGGL(k_recheck_pairs_tab<KS>, dim3(grid, tab->count), dim3(64), 0, s, *tab);
+  else
+    hipLaunchKernelGGL(k_recheck_pairs<KS>, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
+// grid: blocks of the prepared record (or, for a group, the largest over
+// the group)
 template <int KS>
-hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s) {
+hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s, const TabRef* tab) {
   if constexpr (KS <= 4) {
-    (void)grid;
-    GramArgs k = a;
-    k.nseg = k_segments(a.nt);
-    const long g = (long)k.nseg * ((a.slots + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_gram_bf16_k<KS>, dim3((int)g), dim3(256), 0, s, k);
+    if (tab)
+      hipLaunchKernelGGL(k_gram_bf16_k_tab<KS>, dim3(grid, tab->count), dim3(256), 0, s, *tab);
+    else
+      hipLaunchKernelGGL(k_gram_bf16_k<KS>, dim3(grid), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_gram_bf16<KS>, dim3(grid), dim3(256), 0, s, a);
+    if (tab)
+      hipLaunchKernelGGL(k_gram_bf16_tab<KS>, dim3(grid, tab->count), dim3(256), 0, s, *tab);
+    else
+      hipLaunchKernelGGL(k_gram_bf16<KS>, dim3(grid), dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_gram_any(const GramArgs& a, int grid, hipStream_t s, const TabRef* tab) {
+  const int ks = a.ldk / 32;
+  switch (a.ldk % 32 == 0 ? ks : 0) {
+    case 1: return launch_ks<1>(a, grid, s, tab);
+    case 2: return launch_ks<2>(a, grid, s, tab);
+    case 3: return launch_ks<3>(a, grid, s, tab);
+    case 4: return launch_ks<4>(a, grid, s, tab);
+    case 5: return launch_ks<5>(a, grid, s, tab);
+    case 6: return launch_ks<6>(a, grid, s, tab);
+    case 7: return launch_ks<7>(a, grid, s, tab);
+    case 8: return launch_ks<8>(a, grid, s, tab);
+    default: {
+      if (tab) return hipErrorInvalidValue;  // the group form needs 2d <= 256
+      const long tiles = (long)a.nt * (a.nt + 1) / 2;
+      hipLaunchKernelGGL(k_gram_bf16_chunked, dim3((int)(tiles * ((a.slots + 7) / 8 * 8))), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+  }
+}
+
+hipError_t launch_rp_any(const RecheckArgs& a, int grid, hipStream_t s, const TabRef* tab) {
+  switch (a.ldk16 / 32) {
+    case 1: return launch_rp<1>(a, grid, s, tab);
+    case 2: return launch_rp<2>(a, grid, s, tab);
+    case 3: return launch_rp<3>(a, grid, s, tab);
+    case 4: return launch_rp<4>(a, grid, s, tab);
+    case 5: return launch_rp<5>(a, grid, s, tab);
+    case 6: return launch_rp<6>(a, grid, s, tab);
+    case 7: return launch_rp<7>(a, grid, s, tab);
+    case 8: return launch_rp<8>(a, grid, s, tab);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -806,44 +880,46 @@ int bf16_segments(int nt) {
   return total;
 }
 
+int gram_bf16_prepare(GramArgs& a, int slots) {
+  a.slots = slots;
+  const long slots8 = (slots + 7) / 8 * 8;
+  const int ks = a.ldk % 32 == 0 ? a.ldk / 32 : 0;
+  if (ks >= 1 && ks <= 4) {
+    a.nseg = k_segments(a.nt);
+  } else if (ks >= 5 && ks <= 8) {
+    a.nseg = bf16_segments(a.nt);
+  } else {
+    a.nseg = 0;
+    return (int)((long)a.nt * (a.nt + 1) / 2 * slots8);
+  }
+  return (int)((long)a.nseg * slots8);
+}
+
 hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
   GramArgs a = a_in;
-  a.slots = slots;
-  a.nseg = bf16_segments(a.nt);
-  const long slots8 = (slots + 7) / 8 * 8;
-  const long grid = (long)a.nseg * slots8;
-  const int ks = a.ldk / 32;
-  switch (a.ldk % 32 == 0 ? ks : 0) {
-    case 1: return launch_ks<1>(a, (int)grid, s);
-    case 2: return launch_ks<2>(a, (int)grid, s);
-    case 3: return launch_ks<3>(a, (int)grid, s);
-    case 4: return launch_ks<4>(a, (int)grid, s);
-    case 5: return launch_ks<5>(a, (int)grid, s);
-    case 6: return launch_ks<6>(a, (int)grid, s);
-    case 7: return launch_ks<7>(a, (int)grid, s);
-    case 8: return launch_ks<8>(a, (int)grid, s);
-    default: {
-      const long tiles = (long)a.nt * (a.nt + 1) / 2;
-      hipLaunchKernelGGL(k_gram_bf16_chunked, dim3((int)(tiles * slots8)), dim3(256), 0, s, a);
-      return hipGetLastError();
-    }
-  }
+  const int grid = gram_bf16_prepare(a, slots);
+  return launch_gram_any(a, grid, s, nullptr);
+}
+
+hipError_t launch_gram_bf16_tab(const TabRef& t, int ldk, int grid, hipStream_t s) {
+  GramArgs shape{};
+  shape.ldk = ldk;
+  return launch_gram_any(shape, grid, s, &t);
+}
+
+int recheck_grid(int list_cap) {
+  const long items = 16L * list_cap;
+  return (int)(items < 4096 ? items : 4096);
 }
 
 hipError_t launch_recheck_pairs(const RecheckArgs& a, hipStream_t s) {
-  const long items = 16L * a.list_cap;
-  const int grid = (int)(items < 4096 ? items : 4096);
-  switch (a.ldk16 / 32) {
-    case 1: return launch_rp<1>(a, grid, s);
-    case 2: return launch_rp<2>(a, grid, s);
-    case 3: return launch_rp<3>(a, grid, s);
-    case 4: return launch_rp<4>(a, grid, s);
-    case 5: return launch_rp<5>(a, grid, s);
-    case 6: return launch_rp<6>(a, grid, s);
-    case 7: return launch_rp<7>(a, grid, s);
-    case 8: return launch_rp<8>(a, grid, s);
-    default: return hipErrorInvalidValue;
-  }
+  return launch_rp_any(a, recheck_grid(a.list_cap), s, nullptr);
+}
+
+hipError_t launch_recheck_tab(const TabRef& t, int ldk16, int grid, hipStream_t s) {
+  RecheckArgs shape{};
+  shape.ldk16 = ldk16;
+  return launch_rp_any(shape, grid, s, &t);
 }
 
 }  // namespace trstmi

@@ -122,6 +122,38 @@ struct RecheckArgs {
   const int32_t* flags;
 };
 
+// Every argument record of one step of one search in the BF16-screen form,
+// as the single-search launches use them.  The serving engine keeps one per
+// admitted search in a device table and launches each kernel once for a
+// group of searches of the same d: the search is a grid dimension and each
+// block reads its record from the table, so every search runs exactly the
+// arithmetic of its own single-search step.
+struct StepArgs {
+  PerturbArgs pa;   // candidates (BF16 screen copies)
+  GramArgs g;       // screen (slots and nseg filled in)
+  TopkArgs ta;
+  PerturbArgs pr;   // FP64 regeneration of the rechecked candidates
+  RecheckArgs ra;
+  SelectArgs sa;
+  PerturbArgs pc;   // commit of the accepted candidate
+};
+
+// A group of records in a device table: record i of the group is at
+// base + list[i] * stride (base points at the member the kernel reads).
+struct TabRef {
+  const char* base;
+  size_t stride;
+  const int32_t* list;  // device [count]
+  int32_t count;
+};
+
+struct PollRecord {
+  int32_t flags;
+  int32_t pad;
+  int64_t step;
+  double mu;
+};
+
 struct InitFinishArgs {
   const uint64_t* max_bits;  // one value
   int32_t is_f32;
@@ -194,6 +226,30 @@ struct GradArgs {
 int lse_grad_chunks(int nkb);
 hipError_t launch_lse_grad(const GradArgs& a, hipStream_t s);
 
+// Exact Hessian-vector product of the smooth maximum (lse_hv.hip, d <= 64).
+struct HvArgs {
+  const double* raw;        // the frame Y (column stride 2d)
+  const double* v;          // the direction V (same layout)
+  const uint64_t* s_bits;   // max |G|^2 bits of Y
+  const double* log_sum;    // log of sum exp((x - s) / delta) over j < k
+  double inv_delta;
+  double* out;              // Hv (same layout)
+  // scratch, laid out by hv_layout
+  double* phi;              // normalised columns (stride 2d)
+  double* dphi;             // their derivative along V
+  double* r;                // [n] column norms
+  double* dr;               // [n] their derivative
+  double* partial;          // [chunks][n][2][2d] D and E partial sums
+  double* sigpart;          // [blocks] partial sums of sigma
+  double* sigma;            // [1]
+  int32_t n, d;
+};
+size_t hv_scratch_bytes(int64_t n, int64_t d);
+void hv_layout(HvArgs& a, char* scratch, int64_t n, int64_t d);
+hipError_t launch_lse_hv(const HvArgs& a, hipStream_t s);
+// Where trstmi_lse_grad leaves s (max |G|^2 bits) and log S in its workspace.
+void lse_grad_scalars(int64_t n, int64_t d, char* ws, const uint64_t** s_bits, const double** log_sum);
+
 // Beamforming-codebook quantiser (miso.hip).
 struct MisoArgs {
   const double* codebook;   // normalised codewords (column stride ldk, zero padded)
@@ -210,6 +266,12 @@ int64_t miso_blocks(int64_t m);
 // The quantiser, then (if summary is not null) summary = (mean dist, mean gain).
 hipError_t launch_miso(const MisoArgs& a, double* summary, hipStream_t s);
 
+// Every record of one BF16-screen step of a search (validated parameters,
+// mode TRSTMI_MODE_BF16_SCREEN) over its state and workspace, as
+// trstmi_step launches them; z and rep as trstmi_step's (nullable).
+StepArgs bf16_step_args(const trstmi_params* p, const trstmi_state* st, char* ws, const double* z,
+                        const trstmi_report* rep);
+
 // The calling thread's error message (what trstmi_last_error returns).
 trstmi_status set_last_error(trstmi_status code, const std::string& msg);
 
@@ -220,6 +282,17 @@ trstmi_status tr_step_impl(int64_t n, int64_t d, double* frame, const trstmi_tr_
                            char* ws, size_t lws_bytes, hipStream_t stream);
 hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
+// Fills a.slots and a.nseg as launch_gram_bf16 does; returns that launch's grid.
+int gram_bf16_prepare(GramArgs& a, int slots);
+int recheck_grid(int list_cap);
+// Group launches over a table (see StepArgs).  shape: a record with the
+// group's d, output kind and largest n; grid: the largest grid of the group.
+hipError_t launch_perturb_tab(const TabRef& t, const PerturbArgs& shape, int slots, hipStream_t s);
+hipError_t launch_gram_bf16_tab(const TabRef& t, int ldk, int grid, hipStream_t s);
+hipError_t launch_topk_tab(const TabRef& t, hipStream_t s);
+hipError_t launch_recheck_tab(const TabRef& t, int ldk16, int grid, hipStream_t s);
+hipError_t launch_select_tab(const TabRef& t, hipStream_t s);
+hipError_t launch_poll_tab(const TabRef& t, PollRecord* out, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
 hipError_t launch_recheck_pairs(const RecheckArgs& a, hipStream_t s);

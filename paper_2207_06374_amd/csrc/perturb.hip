@@ -75,7 +75,7 @@ __device__ __forceinline__ void store_zero_pad(const PerturbArgs& a, size_t slot
 // ceil(d/2) blocks (LPC * Q == d / 2), so no block is partial or missing;
 // lanes of columns past n compute on the last column and store nothing.
 template <int LPC, int Q, int OUT, bool DRAW, bool FULL>
-__global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
+__device__ __forceinline__ void perturb_body(const PerturbArgs& a, int bx, int gx, int slot) {
   static_assert(DRAW || !FULL, "the full split is compiled for the candidate form only");
   if (a.gate && ((*a.gate & a.gate_mask) != a.gate_want)) return;
   const double* const base = a.base;
@@ -86,8 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   GaussTab* const gtab = &gtab_s;
   fill_gauss_tab(gtab);
   __syncthreads();
-  const int slot = blockIdx.y;
-  if (a.zero_max && blockIdx.x == 0 && threadIdx.x == 0) a.zero_max[slot] = 0;
+  if (a.zero_max && bx == 0 && threadIdx.x == 0) a.zero_max[slot] = 0;
 
   const int c = a.cand_idx ? a.cand_idx[slot] : a.c0 + slot;
   const int64_t t = a.tstep ? *a.tstep : a.t_const;
@@ -102,8 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   const int wave = threadIdx.x >> 6;
   const int lq = lane & (LPC - 1);
 
-  for (int64_t col0 = (int64_t)blockIdx.x * kColsPerIter; col0 < a.n;
-       col0 += (int64_t)gridDim.x * kColsPerIter) {
+  for (int64_t col0 = (int64_t)bx * kColsPerIter; col0 < a.n; col0 += (int64_t)gx * kColsPerIter) {
     const int64_t col = col0 + wave * kColsPerWave + lane / LPC;
     const bool active = col < a.n;  // whole LPC groups share `active`
     const int64_t colr = FULL ? (active ? col : a.n - 1) : col;  // column read
@@ -190,6 +188,18 @@ __global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
   }
 }
 
+template <int LPC, int Q, int OUT, bool DRAW, bool FULL>
+__global__ __launch_bounds__(kThreads) void k_perturb(PerturbArgs a) {
+  perturb_body<LPC, Q, OUT, DRAW, FULL>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+// The same for a group of searches: search blockIdx.z of the table.
+template <int LPC, int Q, int OUT, bool DRAW, bool FULL>
+__global__ __launch_bounds__(kThreads) void k_perturb_tab(TabRef t) {
+  const PerturbArgs a = *(const PerturbArgs*)(t.base + (size_t)t.list[blockIdx.z] * t.stride);
+  perturb_body<LPC, Q, OUT, DRAW, FULL>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
 // FP64 frame -> FP32 copy with zero padding (no renormalisation).
 __global__ __launch_bounds__(kThreads) void k_convert_f32(const double* frame, int64_t n, int d, float* out,
                                                           int out_ld, uint64_t* zero_max) {
@@ -214,17 +224,24 @@ __global__ __launch_bounds__(kThreads) void k_round_bf16(const double* x, int64_
   }
 }
 
+// A group launch (tab != null) covers tab->count searches with the largest
+// n among them (a.n) and the same d.
 template <int LPC, int Q, int OUT, bool DRAW = false, bool FULL = false>
-hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
+hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s, const TabRef* tab) {
   constexpr int kColsPerIter = (kThreads / 64) * (64 / LPC);
   int64_t groups = (a.n + kColsPerIter - 1) / kColsPerIter;
   // about 2048 blocks across all slots (8 per CU, two resident rounds at 4
   // waves per SIMD), each looping over column groups, so that the per-block
   // table fill is spread over more entries
-  int64_t want = (2048 + slots - 1) / slots;
+  const int64_t total = (int64_t)slots * (tab ? tab->count : 1);
+  int64_t want = (2048 + total - 1) / total;
   if (want < 1) want = 1;
   const int gx = (int)(groups < want ? groups : want);
-  hipLaunchKernelGGL((k_perturb<LPC, Q, OUT, DRAW, FULL>), dim3(gx, slots), dim3(kThreads), 0, s, a);
+  if (tab)
+    hipLaunchKernelGGL((k_perturb_tab<LPC, Q, OUT, DRAW, FULL>), dim3(gx, slots, tab->count), dim3(kThreads), 0, s,
+                       *tab);
+  else
+    hipLaunchKernelGGL((k_perturb<LPC, Q, OUT, DRAW, FULL>), dim3(gx, slots), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -233,42 +250,53 @@ hipError_t launch_lpc(const PerturbArgs& a, int slots, hipStream_t s) {
 // FP64 bits are the same in every launch that writes it and its BF16 / FP32
 // screen copies are the roundings of those FP64 values.
 template <int OUT, bool DRAW>
-hipError_t launch_q4(const PerturbArgs& a, int nb, int slots, hipStream_t s) {
+hipError_t launch_q4(const PerturbArgs& a, int nb, int slots, hipStream_t s, const TabRef* tab) {
   if (DRAW && a.d % 2 == 0) {
     // full splits: d = 8, 16, 32, 64, 128, 256, 512
     switch (nb) {
-      case 4: return launch_lpc<1, 4, OUT, DRAW, DRAW>(a, slots, s);
-      case 8: return launch_lpc<2, 4, OUT, DRAW, DRAW>(a, slots, s);
-      case 16: return launch_lpc<4, 4, OUT, DRAW, DRAW>(a, slots, s);
-      case 32: return launch_lpc<8, 4, OUT, DRAW, DRAW>(a, slots, s);
-      case 64: return launch_lpc<16, 4, OUT, DRAW, DRAW>(a, slots, s);
-      case 128: return launch_lpc<32, 4, OUT, DRAW, DRAW>(a, slots, s);
-      case 256: return launch_lpc<64, 4, OUT, DRAW, DRAW>(a, slots, s);
+      case 4: return launch_lpc<1, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
+      case 8: return launch_lpc<2, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
+      case 16: return launch_lpc<4, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
+      case 32: return launch_lpc<8, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
+      case 64: return launch_lpc<16, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
+      case 128: return launch_lpc<32, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
+      case 256: return launch_lpc<64, 4, OUT, DRAW, DRAW>(a, slots, s, tab);
       default: break;
     }
   }
-  if (nb <= 4) return launch_lpc<1, 4, OUT, DRAW>(a, slots, s);
-  if (nb <= 8) return launch_lpc<2, 4, OUT, DRAW>(a, slots, s);
-  if (nb <= 16) return launch_lpc<4, 4, OUT, DRAW>(a, slots, s);
-  if (nb <= 32) return launch_lpc<8, 4, OUT, DRAW>(a, slots, s);
-  if (nb <= 64) return launch_lpc<16, 4, OUT, DRAW>(a, slots, s);
-  if (nb <= 128) return launch_lpc<32, 4, OUT, DRAW>(a, slots, s);
-  return launch_lpc<64, kMaxQ, OUT, DRAW>(a, slots, s);
+  if (nb <= 4) return launch_lpc<1, 4, OUT, DRAW>(a, slots, s, tab);
+  if (nb <= 8) return launch_lpc<2, 4, OUT, DRAW>(a, slots, s, tab);
+  if (nb <= 16) return launch_lpc<4, 4, OUT, DRAW>(a, slots, s, tab);
+  if (nb <= 32) return launch_lpc<8, 4, OUT, DRAW>(a, slots, s, tab);
+  if (nb <= 64) return launch_lpc<16, 4, OUT, DRAW>(a, slots, s, tab);
+  if (nb <= 128) return launch_lpc<32, 4, OUT, DRAW>(a, slots, s, tab);
+  return launch_lpc<64, kMaxQ, OUT, DRAW>(a, slots, s, tab);
 }
 
 }  // namespace
 
-hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
+namespace {
+hipError_t launch_perturb_any(const PerturbArgs& a, int slots, hipStream_t s, const TabRef* tab) {
   const int nb = (a.d + 1) / 2;
   const bool draw = a.base && a.have_z && !a.z_explicit;
   switch (a.out_kind) {
     case kOutF64:
-      return draw ? launch_q4<kOutF64, true>(a, nb, slots, s) : launch_q4<kOutF64, false>(a, nb, slots, s);
+      return draw ? launch_q4<kOutF64, true>(a, nb, slots, s, tab) : launch_q4<kOutF64, false>(a, nb, slots, s, tab);
     case kOutF32:
-      return draw ? launch_q4<kOutF32, true>(a, nb, slots, s) : launch_q4<kOutF32, false>(a, nb, slots, s);
+      return draw ? launch_q4<kOutF32, true>(a, nb, slots, s, tab) : launch_q4<kOutF32, false>(a, nb, slots, s, tab);
     default:
-      return draw ? launch_q4<kOutBF16, true>(a, nb, slots, s) : launch_q4<kOutBF16, false>(a, nb, slots, s);
+      return draw ? launch_q4<kOutBF16, true>(a, nb, slots, s, tab)
+                  : launch_q4<kOutBF16, false>(a, nb, slots, s, tab);
   }
+}
+}  // namespace
+
+hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
+  return launch_perturb_any(a, slots, s, nullptr);
+}
+
+hipError_t launch_perturb_tab(const TabRef& t, const PerturbArgs& shape, int slots, hipStream_t s) {
+  return launch_perturb_any(shape, slots, s, &t);
 }
 
 hipError_t launch_convert_f32(const double* frame, int64_t n, int32_t d, float* out, int32_t out_ld,

@@ -53,7 +53,7 @@ __device__ __forceinline__ void best2_merge(Best2& a, const Best2& o) {
   if (o.v2 < a.v2) a.v2 = o.v2;
 }
 
-__global__ __launch_bounds__(kThreads) void k_select(SelectArgs a) {
+__device__ __forceinline__ void select_body(const SelectArgs& a) {
   __shared__ Best2 sh[kThreads];
   const int tid = threadIdx.x;
   if (*a.flags & kFlagDone) {
@@ -110,8 +110,16 @@ __global__ __launch_bounds__(kThreads) void k_select(SelectArgs a) {
   if (a.rep_best) *a.rep_best = r.c1;
 }
 
+__global__ __launch_bounds__(kThreads) void k_select(SelectArgs a) { select_body(a); }
+
+// The same for a group of searches: search blockIdx.x of the table.
+__global__ __launch_bounds__(kThreads) void k_select_tab(TabRef t) {
+  const SelectArgs a = *(const SelectArgs*)(t.base + (size_t)t.list[blockIdx.x] * t.stride);
+  select_body(a);
+}
+
 // k smallest screened values by (mu_screen, c); thresholds for certified pruning.
-__global__ __launch_bounds__(kTopkThreads) void k_topk(TopkArgs a) {
+__device__ __forceinline__ void topk_body(const TopkArgs& a) {
   __shared__ double sv[kTopkThreads];
   __shared__ int sc[kTopkThreads];
   __shared__ uint32_t taken[kBitmapWords];
@@ -263,6 +271,27 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(TopkArgs a) {
   if (tid == 0) *a.list_count = list_n < a.list_cap ? list_n : a.list_cap;
 }
 
+__global__ __launch_bounds__(kTopkThreads) void k_topk(TopkArgs a) { topk_body(a); }
+
+__global__ __launch_bounds__(kTopkThreads) void k_topk_tab(TabRef t) {
+  const TopkArgs a = *(const TopkArgs*)(t.base + (size_t)t.list[blockIdx.x] * t.stride);
+  topk_body(a);
+}
+
+// State of every listed search after a run of group steps: (flags, step, mu)
+// through the state pointers of its select record.
+__global__ __launch_bounds__(64) void k_poll_tab(TabRef t, PollRecord* out) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= t.count) return;
+  const SelectArgs& a = *(const SelectArgs*)(t.base + (size_t)t.list[i] * t.stride);
+  PollRecord r;
+  r.flags = *a.flags;
+  r.pad = 0;
+  r.step = *a.step;
+  r.mu = *a.mu;
+  out[i] = r;
+}
+
 __global__ void k_init_finish(InitFinishArgs a) {
   if (threadIdx.x != 0) return;
   const double mu = bits_to_mu(*a.max_bits, a.is_f32);
@@ -286,6 +315,21 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
 
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_topk, dim3(1), dim3(kTopkThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_tab(const TabRef& t, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_tab, dim3(t.count), dim3(kThreads), 0, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_tab(const TabRef& t, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk_tab, dim3(t.count), dim3(kTopkThreads), 0, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_poll_tab(const TabRef& t, PollRecord* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_poll_tab, dim3((t.count + 63) / 64), dim3(64), 0, s, t, out);
   return hipGetLastError();
 }
 

@@ -7,8 +7,10 @@
 // Vectors are the real coordinates of the complex d x N frame (2dN doubles).
 // All vector work runs in the kernels below: dot products over a fixed
 // block partition with a fixed-order finish (repeatable bits), and linear
-// combinations.  Hessian-vector products are central differences of the
-// gradient (trstmi_lse_grad) along the unit direction.  The host part makes
+// combinations.  Hessian-vector products are exact (lse_hv.hip: B is the
+// Hessian of the smooth maximum, as Alg. 1 states), or, as an option,
+// central differences of the gradient (trstmi_lse_grad) along the unit
+// direction.  The host part makes
 // the scalar decisions of the algorithm, reading a few doubles per CG
 // iteration.
 
@@ -106,7 +108,7 @@ hipError_t dots(const Ctx& c, int nk, const double* u0, const double* v0, const 
 
 size_t tr_vectors_bytes(int64_t n, int64_t d) {
   const size_t vec = ((size_t)(2 * d * n) * 8 + 255) / 256 * 256;
-  return 9 * vec + 256 + 3 * kDotBlocks * 8;
+  return 9 * vec + 256 + 3 * kDotBlocks * 8 + hv_scratch_bytes(n, d);
 }
 
 // The trust-region step itself (arguments validated by the caller).
@@ -128,6 +130,14 @@ trstmi_status tr_step_impl(int64_t n, int64_t d, double* frame, const trstmi_tr_
   c.out2 = (double*)q;
   c.dots = (double*)(q + 64);
   c.partial = (double*)(q + 256);
+  const bool exact = !(tp->fd_step > 0.0);
+  HvArgs hv{};
+  if (exact) {
+    hv_layout(hv, q + 256 + 3 * kDotBlocks * 8, n, d);
+    lse_grad_scalars(n, d, ws, &hv.s_bits, &hv.log_sum);
+    hv.raw = frame;
+    hv.inv_delta = 1.0 / tp->delta;
+  }
 
 #define TR_HIP(expr)                                    \
   do {                                                  \
@@ -170,15 +180,23 @@ trstmi_status tr_step_impl(int64_t n, int64_t d, double* frame, const trstmi_tr_
   } else {
     for (int j = 0; j < tp->cg_max_iter; ++j) {
       iters = j + 1;
-      // B d by central differences along d / |d|
       TR_HIP(dots(c, 1, dd, dd, nullptr, nullptr, nullptr, nullptr, res));
       const double nd = std::sqrt(res[0]);
-      const double hs = tp->fd_step / nd;
-      TR_HIP(lincomb(c, 1.0, frame, hs, dd, Yp));
-      TR_CALL(grad_at(Yp, gp));
-      TR_HIP(lincomb(c, 1.0, frame, -hs, dd, Yp));
-      TR_CALL(grad_at(Yp, gm));
-      TR_HIP(lincomb(c, nd / (2.0 * tp->fd_step), gp, -nd / (2.0 * tp->fd_step), gm, Bd));
+      if (exact) {
+        // B d with B the Hessian at the frame (s and log S of the frame stay
+        // in the gradient's workspace: no gradient is evaluated elsewhere)
+        hv.v = dd;
+        hv.out = Bd;
+        TR_HIP(launch_lse_hv(hv, stream));
+      } else {
+        // B d by central differences along d / |d|
+        const double hs = tp->fd_step / nd;
+        TR_HIP(lincomb(c, 1.0, frame, hs, dd, Yp));
+        TR_CALL(grad_at(Yp, gp));
+        TR_HIP(lincomb(c, 1.0, frame, -hs, dd, Yp));
+        TR_CALL(grad_at(Yp, gm));
+        TR_HIP(lincomb(c, nd / (2.0 * tp->fd_step), gp, -nd / (2.0 * tp->fd_step), gm, Bd));
+      }
       TR_HIP(dots(c, 3, dd, Bd, z, dd, z, z, res));
       const double dBd = res[0], zd = res[1], zz = res[2];
       const double d2 = nd * nd;

@@ -1,15 +1,17 @@
-"""Serving form: a stream of solve requests with continuous admission.
+"""Serving form: a stream of solve requests served by continuous batching.
 
 The server itself is native (the library's trstmi_server_* entry points):
-slot threads with a HIP stream each take the request at the head of the
-queue as soon as its device footprint (workspace, frame, state scalars) fits
-in the caller's pool, run the Haar start and the solve there (graph-captured
-chunks of steps, one done-flag poll per chunk) and release the range.  A
-request larger than the whole pool is rejected at once.  This module submits
-requests at their arrival times and collects the results.
+one engine thread keeps every admitted request in a device table and
+advances all of them together, one launch of each step kernel per group of
+requests with the same d; after each chunk of steps it reads back every
+request's state at once, retires the finished ones and admits the requests
+at the head of the queue whose device footprint (workspace, frame, state
+scalars) fits in the caller's pool.  A request larger than the whole pool is
+rejected at once.  This module submits requests at their arrival times and
+collects the results.
 
 Every result is a pure function of the request (its own seed and stream id):
-the same alone and in any mix.
+the same alone, in any mix, and as a single solve gives it.
 """
 
 from __future__ import annotations
@@ -27,8 +29,8 @@ from . import MODES, Solver, _abi, _torch, default_params
 
 
 def welch_bound(n, d):
-    """sqrt((N - d) / (d (N - 1))), 0 for N <= d."""
-    return math.sqrt(max(0.0, (n - d) / (d * (n - 1))))
+    """sqrt((N - d) / (d (N - 1))), 0 for N <= d (the library's value)."""
+    return float(_abi.lib().trstmi_welch_bound(int(n), int(d)))
 
 
 @dataclasses.dataclass
@@ -81,9 +83,15 @@ class Server:
     """Continuous-admission solve server on one GPU (the native server over a
     torch-allocated pool)."""
 
-    def __init__(self, pool_bytes, max_active=8, chunk=64, candidates=64, mode="bf16", recheck_topk=8,
+    def __init__(self, pool_bytes, max_active=64, chunk=64, candidates=64, mode="bf16", recheck_topk=8,
                  radius0=0.05, target_factor=1.10, device="cuda"):
+        """pool_bytes: device bytes for the admitted requests (the engine's
+        table for max_active rows is added on top)."""
         torch = _torch()
+        table = int(_abi.lib().trstmi_server_table_bytes(int(max_active)))
+        if table == 0:
+            raise ValueError("max_active must be in [1, 1024]")
+        pool_bytes = int(pool_bytes) + table
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
         self.candidates = int(candidates)
         self.mode = MODES.get(mode, mode)
@@ -94,13 +102,13 @@ class Server:
         handle = ctypes.c_void_p()
         _abi.check(_abi.lib().trstmi_server_create(ctypes.byref(p), ctypes.byref(handle)), "trstmi_server_create")
         self.handle = handle
-        # destroy (join the slot threads) when the server is collected or at
+        # destroy (join the engine thread) when the server is collected or at
         # interpreter exit, before the HIP runtime goes away; the pool stays
         # referenced until then
         self._finalizer = weakref.finalize(self, _destroy, handle, self.pool)
 
     def close(self):
-        """Let running requests finish, cancel queued ones, stop the slots."""
+        """Let running requests finish, cancel queued ones, stop the engine."""
         self._finalizer()
 
     def submit(self, req):

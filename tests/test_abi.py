@@ -230,10 +230,24 @@ def test_tr_step_argument_checks(L):
     assert L.trstmi_tr_step(100, 65, p, ctypes.byref(good), ctypes.byref(rep), ws, need, None) == abi.E_UNSUPPORTED
     for bad in (abi.TRParams(0.0, 0.1, 1.0, 0.1, 1e-8, 20, 1e-6), abi.TRParams(0.05, -1.0, 1.0, 0.1, 1e-8, 20, 1e-6),
                 abi.TRParams(0.05, 0.1, 0.05, 0.1, 1e-8, 20, 1e-6), abi.TRParams(0.05, 0.1, 1.0, 0.3, 1e-8, 20, 1e-6),
-                abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 0, 1e-6), abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 20, 0.0)):
+                abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 0, 1e-6), abi.TRParams(0.05, 0.1, 1.0, 0.1, 1e-8, 20, -1e-6)):
         assert L.trstmi_tr_step(100, 8, p, ctypes.byref(bad), ctypes.byref(rep), ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_tr_step(100, 8, p, None, ctypes.byref(rep), ws, need, None) == abi.E_INVALID_ARG
     assert L.trstmi_tr_step(100, 8, p, ctypes.byref(good), ctypes.byref(rep), ws, need - 1, None) == abi.E_WORKSPACE
+
+
+def test_lse_hvp_argument_checks(L):
+    need = L.trstmi_lse_hvp_workspace_bytes(100, 8)
+    assert need > L.trstmi_lse_workspace_bytes(100, 8)
+    assert L.trstmi_lse_hvp_workspace_bytes(100, 65) == 0 and L.trstmi_lse_hvp_workspace_bytes(1, 8) == 0
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    assert L.trstmi_lse_hvp(100, 65, p, p, 0.1, p, p, ws, need, None) == abi.E_UNSUPPORTED
+    assert L.trstmi_lse_hvp(100, 8, p, p, 0.0, p, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse_hvp(100, 8, p, None, 0.1, p, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse_hvp(100, 8, p, ctypes.c_void_p(4104), 0.1, p, p, ws, need, None) == abi.E_INVALID_ARG
+    assert L.trstmi_lse_hvp(100, 8, p, p, 0.1, p, p, ws, need - 1, None) == abi.E_WORKSPACE
+    assert L.trstmi_abi_version() >= 11
 
 
 def test_optimize_argument_checks(L):
@@ -257,6 +271,7 @@ def test_optimize_argument_checks(L):
                 abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 0.01, 0.1, 1e-10, 0, 1e-6, 1, 0),
                 abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 0, 0),
                 abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 65, 0),
+                abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, -1e-6, 1, 0),
                 abi.OptParams(0, 2, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, -1)):
         assert L.trstmi_optimize(9, 3, ctypes.byref(bad), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
                                  None) == abi.E_INVALID_ARG

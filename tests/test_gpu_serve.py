@@ -1,5 +1,6 @@
-"""GPU checks of the serving form: continuous admission under a memory cap,
-and every request's result equal to the same request solved alone."""
+"""GPU checks of the serving form (continuous batching through the engine's
+request table): admission under a memory cap, and every request's result
+equal to the same request solved alone."""
 
 import numpy as np
 import pytest
@@ -36,6 +37,39 @@ def test_serving_mix_equals_alone_and_respects_pool_cap():
         assert mu == r.mu and step == r.steps, f"request {r.id}"
         assert r.steps <= r.max_steps
         assert (mu <= serve.welch_bound(r.n, r.d) * 1.10) == r.reached
+
+
+def test_serving_sizes_in_one_mix_equal_alone():
+    """The serving shapes (d in {32, 64, 128}, N in [2d, 8d], up to N = 1024
+    at d = 128) advanced together: several groups of d, and two requests per
+    group with different N (the group launch covers the largest), each with
+    exactly its single-solve result."""
+    reqs = []
+    for k, (d, n) in enumerate([(32, 64), (32, 250), (64, 512), (64, 140), (128, 1024), (128, 300), (16, 100)]):
+        reqs.append(serve.Request(id=100 + k, arrival=0.0, n=n, d=d, seed=k, max_steps=24))
+    srv = serve.Server(pool_bytes=1 << 30, max_active=16, chunk=8, candidates=64, mode="bf16")
+    stats = srv.run(reqs)
+    print(stats, flush=True)
+    assert stats["done"] == len(reqs) and stats["errors"] == 0
+    for r in reqs:
+        F, mu, radius, step, flags = serve.solve_alone(r, candidates=64, mode="bf16", chunk=8)
+        print(f"request {r.id} n={r.n} d={r.d}: mu={r.mu!r} alone={mu!r} steps={r.steps}", flush=True)
+        assert mu == r.mu and step == r.steps == 24
+
+
+def test_engine_admits_into_freed_rows_mid_run():
+    """Three rows, eight requests of mixed d with different step caps: rows
+    free up at different chunks and the queue's head takes them; every
+    result is still the single solve's."""
+    reqs = [serve.Request(id=k, arrival=0.0, n=20 + 7 * k, d=(3, 8, 16)[k % 3], seed=k, max_steps=40 + 24 * k)
+            for k in range(8)]
+    srv = serve.Server(pool_bytes=1 << 28, max_active=3, chunk=16, candidates=32, mode="bf16")
+    stats = srv.run(reqs)
+    assert stats["done"] == 8 and stats["errors"] == 0
+    assert srv.stats().pool_used == 0 and srv.stats().active == 0
+    for r in reqs:
+        F, mu, radius, step, flags = serve.solve_alone(r, candidates=32, mode="bf16", chunk=16)
+        assert mu == r.mu and step == r.steps, f"request {r.id}"
 
 
 def test_oversized_request_is_rejected_not_queued():
