@@ -162,6 +162,25 @@ trstmi_status trstmi_coherence(int64_t n, int64_t d, int32_t mode, const double*
                                hipStream_t stream);
 
 /*
+ * trstmi_coherence for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and result as trstmi_coherence, with the
+ * workspace taken from a fixed device array inside the library instead of
+ * the caller's buffer.  The array holds trstmi_coherence_noalloc_max_bytes()
+ * bytes (16 MiB + 256: an FP64 frame with n * (2d rounded up to 8) <= 2^21,
+ * e.g. N = 8192 at d = 128); larger frames return TRSTMI_E_UNSUPPORTED
+ * before anything is launched.  Each GPU holds its own array for the life of
+ * the process; the first call on a device looks up its address.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one device (different streams or threads without
+ * ordering) race and must be serialised by the caller.  Arguments, errors
+ * and stream ordering as trstmi_coherence.
+ */
+size_t trstmi_coherence_noalloc_max_bytes(void);
+trstmi_status trstmi_coherence_noalloc(int64_t n, int64_t d, int32_t mode, const double* frame,
+                                       double* mu_out, hipStream_t stream);
+
+/*
  * A pair attaining the coherence (section I definition, FP64): *mu_out
  * (device) <- mu as trstmi_coherence computes it in TRSTMI_MODE_FP64, and
  * pair_out[0..1] (device int64) <- (j, k), j < k, the first pair in the

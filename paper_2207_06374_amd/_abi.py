@@ -162,6 +162,8 @@ SIGNATURES = {
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_server_table_bytes": (_sz, [_i32]),
     "trstmi_welch_bound": (ctypes.c_double, [_i64, _i64]),
+    "trstmi_coherence_noalloc_max_bytes": (_sz, []),
+    "trstmi_coherence_noalloc": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp]),
     "trstmi_lse_hvp_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_lse_hvp": (_i32, [_i64, _i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_tr_workspace_bytes": (_sz, [_i64, _i64]),

@@ -1449,3 +1449,56 @@ int32_t trstmi_abi_version(void) { return 11; }
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Coherence without allocation: the workspace is a fixed device array of the
+// library (each GPU the library runs on holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocBytes = ((size_t)16 << 20) + 256;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+trstmi_status scratch_of_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(TRSTMI_E_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TRSTMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t trstmi_coherence_noalloc_max_bytes(void) { return kNoAllocBytes; }
+
+trstmi_status trstmi_coherence_noalloc(int64_t n, int64_t d, int32_t mode, const double* frame, double* mu_out,
+                                       hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if ((st = check_mode(mode))) return st;
+  const size_t need = trstmi_coherence_workspace_bytes(n, d, mode);
+  if (need > kNoAllocBytes)
+    return fail(TRSTMI_E_UNSUPPORTED, "frame too large for the fixed workspace: needs " + std::to_string(need) +
+                                          " bytes, the library holds " + std::to_string(kNoAllocBytes));
+  void* ws = nullptr;
+  if ((st = scratch_of_device(&ws))) return st;
+  return trstmi_coherence(n, d, mode, frame, mu_out, ws, kNoAllocBytes, stream);
+}
+
+}  // extern "C"

@@ -250,6 +250,20 @@ def test_lse_hvp_argument_checks(L):
     assert L.trstmi_abi_version() >= 11
 
 
+def test_coherence_noalloc_refuses_oversized_frames_on_the_host(L):
+    """The fixed workspace bounds the frame; a larger one is refused before
+    any device call (this runs without a GPU)."""
+    cap = L.trstmi_coherence_noalloc_max_bytes()
+    assert cap == (16 << 20) + 256
+    p = ctypes.c_void_p(4096)
+    n_big = cap // (1024 * 8) + 1
+    assert L.trstmi_coherence_noalloc(n_big, 512, 0, p, p, None) == abi.E_UNSUPPORTED
+    assert b"fixed workspace" in L.trstmi_last_error()
+    assert L.trstmi_coherence_workspace_bytes(n_big - 1, 512, 0) <= cap
+    assert L.trstmi_coherence_noalloc(1, 4, 0, p, p, None) == abi.E_INVALID_ARG
+    assert L.trstmi_coherence_noalloc(16, 4, 7, p, p, None) == abi.E_INVALID_ARG
+
+
 def test_optimize_argument_checks(L):
     need = L.trstmi_optimize_workspace_bytes(9, 3, 1)
     assert need > L.trstmi_tr_workspace_bytes(9, 3)
