@@ -392,21 +392,22 @@ def run_table2(lib, dims):
     return rows
 
 
-def run_serving(lib, count, max_steps, pool_gib):
+def run_serving(lib, count, max_steps, pool_gib, slots, chunk=32):
     """The serving workload: Poisson arrivals (mean gap 5 ms), d in
     {8, 16, 32, 64, 128}, N uniform in [2d, 8d], each solved to 1.10 x Welch or
     max_steps with BF16-screened / FP64-verified steps, admitted by device
-    footprint into a capped pool."""
+    footprint into a capped pool and advanced by the continuous-batching
+    engine."""
     import inputs
     from paper_2207_06374_amd import serve
     reqs = [serve.Request(id=r["id"], arrival=r["arrival"], n=r["n"], d=r["d"], seed=r["seed"], max_steps=max_steps)
             for r in inputs.serving_requests(count, seed=1)]
-    srv = serve.Server(pool_bytes=int(pool_gib * 2 ** 30), max_active=16, chunk=64, candidates=64, mode="bf16")
+    srv = serve.Server(pool_bytes=int(pool_gib * 2 ** 30), max_active=slots, chunk=chunk, candidates=64, mode="bf16")
     stats = srv.run(reqs, progress=log)
     srv.close()
-    stats["workload"] = (f"{count} requests, Poisson arrivals mean gap 5 ms, d in {{8,16,32,64,128}}, N in [2d, 8d], "
-                         f"target 1.10 x Welch or {max_steps} steps, 64 candidates, BF16 screen + FP64 recheck, "
-                         f"pool {pool_gib} GiB, native server with 16 slots (a thread and a stream each)")
+    stats["workload"] = (f"{count} requests, Poisson arrivals mean gap 5 ms (200 req/s), d in {{8,16,32,64,128}}, "
+                         f"N in [2d, 8d], target 1.10 x Welch or {max_steps} steps, 64 candidates, BF16 screen + "
+                         f"top-8 FP64 recheck, pool {pool_gib} GiB, engine with {slots} rows and {chunk}-step chunks")
     return stats
 
 
@@ -531,9 +532,10 @@ def main():
                     help="dimensions d for the optimiser at N = d^2 (Table II comparison; empty: skip)")
     ap.add_argument("--smooth-max-evals", type=int, default=10,
                     help="evaluations of the section IV smooth maximum at the throughput shape (0: skip)")
-    ap.add_argument("--serving-requests", type=int, default=16, help="requests of the serving run (0: skip)")
-    ap.add_argument("--serving-max-steps", type=int, default=5000)
-    ap.add_argument("--serving-pool-gib", type=float, default=8.0)
+    ap.add_argument("--serving-requests", type=int, default=96, help="requests of the serving run (0: skip)")
+    ap.add_argument("--serving-max-steps", type=int, default=20000)
+    ap.add_argument("--serving-pool-gib", type=float, default=1.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -583,8 +585,8 @@ def main():
     table2 = run_table2(lib, [int(x) for x in args.table2_dims.split(",") if x]) if args.table2_dims else None
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
-    serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib)
-               if args.serving_requests > 0 else None)
+    serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib,
+                           args.serving_slots) if args.serving_requests > 0 else None)
 
     g = main_res["gram"]
     traffic = load_traffic("gram_bf16")

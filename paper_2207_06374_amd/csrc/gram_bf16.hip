@@ -19,12 +19,13 @@
 // the next tile's columns are prefetched into registers while the current
 // tile is computed and stored into a second LDS buffer, so each tile costs
 // one barrier.  Per tile, the wave sweeps 8 column blocks of 16 columns:
-// 4 x 2 x K/32 MFMAs per block.  The accumulators of block cb are folded
-// (|G|^2 = Re^2 + Im^2, running max on the float bit patterns; the integer
-// max keeps NaN, which marks an invalid candidate, above every finite value)
-// row block by row block just before the first MFMAs of block cb + 1 reuse
-// them, and scheduling groups interleave that epilogue and the LDS reads of
-// block cb + 2 with the MFMAs.  Diagonal tiles skip the column blocks wholly
+// 4 x 2 x K/32 MFMAs per block, row block by row block (the 2 K/32 products
+// of one 16-row block back to back).  The accumulators of a row block are
+// folded (|G|^2 = Re^2 + Im^2, running max on the float bit patterns; the
+// integer max keeps NaN, which marks an invalid candidate, above every
+// finite value) under the products of the row block two places later, and
+// scheduling groups spread that epilogue and the LDS reads of the next
+// column block over the MFMAs.  Diagonal tiles skip the column blocks wholly
 // below the wave's rows and keep j > i; rows/columns past N are zero and
 // contribute 0.
 //
@@ -389,21 +390,45 @@ __device__ __forceinline__ void qblock(const QRows<KS>& A, const u32x4 b[KS], v4
     }
 }
 
-template <int KS>
-__device__ __forceinline__ void sched_qblock(bool reads) {
-  // rb-interleaved epilogue with the first K step, LDS reads of the next
-  // block spread over the following MFMAs
+// Row-block-major form of one column block: the 2 KS products of row block
+// rb run back to back, and the |G|^2 / max fold of row block rb - 2 (of the
+// previous column block for rb < 2) runs under them, so the fold of a row
+// block is spread over another row block's products instead of being packed
+// before the next column block.  Row block rb's accumulators are rewritten
+// only at row block rb of the next column block, after their fold.
+template <int KS, bool EPI>
+__device__ __forceinline__ void qblock_rm(const QRows<KS>& A, const u32x4 b[KS], v4f32 R[4], v4f32 I[4],
+                                          uint32_t& best) {
+  const v4f32 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
-    __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-  }
+    const int fr = (rb + 2) & 3;
+    if (EPI || rb >= 2) best = fold_rb(best, R[fr], I[fr]);
+    R[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.u[rb][0]), as_bf16x8(b[0]), z, 0, 0, 0);
+    I[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][0]), as_bf16x8(b[0]), z, 0, 0, 0);
 #pragma unroll
-  for (int i = 0; i < KS; ++i) {
-    if (reads) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+    for (int ks = 1; ks < KS; ++ks) {
+      R[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.u[rb][ks]), as_bf16x8(b[ks]), R[rb], 0, 0, 0);
+      I[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A.v[rb][ks]), as_bf16x8(b[ks]), I[rb], 0, 0, 0);
+    }
   }
-  __builtin_amdgcn_sched_group_barrier(0x008, 8 * KS, 0);
+}
+
+template <int KS>
+__device__ __forceinline__ void sched_qblock_rm(bool epi, bool reads) {
+  // per row block: its 2 KS products, the fold (10 VALU) in pairs after the
+  // first five, one LDS read of the next column block's fragments after the
+  // first product (KS reads over the first KS row blocks)
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const bool fold = epi || rb >= 2;
+#pragma unroll
+    for (int j = 0; j < 2 * KS; ++j) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      if (j == 0 && reads && rb < KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      if (fold && j < 5) __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+    }
+  }
 }
 
 // Max |G|^2 bits over this wave's 64 rows (tile offset roff) against the 128
@@ -417,22 +442,23 @@ __device__ __forceinline__ uint32_t tile_max_k(const QRows<KS>& A, const uint16_
   if (!diag) {
     read_frags<KS>(Bs, 0, b0);
     read_frags<KS>(Bs, 1, b1);
-    qblock<KS, false>(A, b0, R, I, best);
+    qblock_rm<KS, false>(A, b0, R, I, best);
+    sched_qblock_rm<KS>(false, false);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int cb = 1; cb < T / 16; ++cb) {
       if (cb & 1) {
         if (cb + 1 < T / 16) read_frags<KS>(Bs, cb + 1, b0);
-        qblock<KS, true>(A, b1, R, I, best);
+        qblock_rm<KS, true>(A, b1, R, I, best);
       } else {
         if (cb + 1 < T / 16) read_frags<KS>(Bs, cb + 1, b1);
-        qblock<KS, true>(A, b0, R, I, best);
+        qblock_rm<KS, true>(A, b0, R, I, best);
       }
-      sched_qblock<KS>(cb + 1 < T / 16);
+      sched_qblock_rm<KS>(true, cb + 1 < T / 16);
       __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) best = fold_rb(best, R[rb], I[rb]);
+    best = fold_rb(best, R[2], I[2]);
+    best = fold_rb(best, R[3], I[3]);
     return best;
   }
   // diagonal tile: column blocks wholly below this wave's rows are skipped

@@ -7,8 +7,9 @@
 // its step (frame, radius, step counter and workspace live in its range of
 // the caller's pool).  Per step the engine launches each kernel of the
 // BF16-screen step once per group of admitted requests with the same d (the
-// request is a grid dimension; each block reads its request's record), so
-// one launch sequence advances every request in flight, each with exactly
+// request is a grid dimension; each block reads its request's record; the
+// top-k and the selection, which do not depend on d, once for all of them),
+// so one launch sequence advances every request in flight, each with exactly
 // the arithmetic of its own single-search step.  After every `chunk` steps
 // one small kernel gathers every request's flags, step and coherence for a
 // single read-back; finished requests leave the table, and the queue's head
@@ -187,24 +188,38 @@ trstmi_status trstmi_server::rebuild() {
   return TRSTMI_OK;
 }
 
+// One step of every admitted request, in each request's own kernel order:
+// candidates and screen per group of d, the top-k of every request in one
+// launch (it does not depend on d), regeneration and recheck per group, the
+// selection of every request in one launch, the commit per group.
 trstmi_status trstmi_server::launch_steps(int steps) {
   const size_t S = sizeof(trstmi::StepArgs);
-  for (int i = 0; i < steps; ++i)
+  const int32_t nrun = (int32_t)running.size();
+  auto all = [&](size_t member) {
+    return trstmi::TabRef{tab_dev + member, S, list_dev + (list_host.size() - nrun), nrun};
+  };
+  for (int i = 0; i < steps; ++i) {
+    hipError_t e = hipSuccess;
     for (const Group& g : groups) {
-      auto ref = [&](size_t member) {
-        return trstmi::TabRef{tab_dev + member, S, list_dev + g.first, g.count};
-      };
-      hipError_t e = trstmi::launch_perturb_tab(ref(offsetof(trstmi::StepArgs, pa)), g.shape_pa, p.candidates, stream);
-      if (e == hipSuccess) e = trstmi::launch_gram_bf16_tab(ref(offsetof(trstmi::StepArgs, g)), g.ldk16, g.gram_grid, stream);
-      if (e == hipSuccess) e = trstmi::launch_topk_tab(ref(offsetof(trstmi::StepArgs, ta)), stream);
-      if (e == hipSuccess)
-        e = trstmi::launch_perturb_tab(ref(offsetof(trstmi::StepArgs, pr)), g.shape_pr, p.recheck_topk, stream);
-      if (e == hipSuccess)
-        e = trstmi::launch_recheck_tab(ref(offsetof(trstmi::StepArgs, ra)), g.ldk16, g.recheck_grid, stream);
-      if (e == hipSuccess) e = trstmi::launch_select_tab(ref(offsetof(trstmi::StepArgs, sa)), stream);
-      if (e == hipSuccess) e = trstmi::launch_perturb_tab(ref(offsetof(trstmi::StepArgs, pc)), g.shape_pc, 1, stream);
-      if (e != hipSuccess) return server_fail(TRSTMI_E_HIP, std::string("engine step: ") + hipGetErrorString(e));
+      const trstmi::TabRef pa{tab_dev + offsetof(trstmi::StepArgs, pa), S, list_dev + g.first, g.count};
+      const trstmi::TabRef gr{tab_dev + offsetof(trstmi::StepArgs, g), S, list_dev + g.first, g.count};
+      if (e == hipSuccess) e = trstmi::launch_perturb_tab(pa, g.shape_pa, p.candidates, stream);
+      if (e == hipSuccess) e = trstmi::launch_gram_bf16_tab(gr, g.ldk16, g.gram_grid, stream);
     }
+    if (e == hipSuccess) e = trstmi::launch_topk_tab(all(offsetof(trstmi::StepArgs, ta)), stream);
+    for (const Group& g : groups) {
+      const trstmi::TabRef pr{tab_dev + offsetof(trstmi::StepArgs, pr), S, list_dev + g.first, g.count};
+      const trstmi::TabRef ra{tab_dev + offsetof(trstmi::StepArgs, ra), S, list_dev + g.first, g.count};
+      if (e == hipSuccess) e = trstmi::launch_perturb_tab(pr, g.shape_pr, p.recheck_topk, stream);
+      if (e == hipSuccess) e = trstmi::launch_recheck_tab(ra, g.ldk16, g.recheck_grid, stream);
+    }
+    if (e == hipSuccess) e = trstmi::launch_select_tab(all(offsetof(trstmi::StepArgs, sa)), stream);
+    for (const Group& g : groups) {
+      const trstmi::TabRef pc{tab_dev + offsetof(trstmi::StepArgs, pc), S, list_dev + g.first, g.count};
+      if (e == hipSuccess) e = trstmi::launch_perturb_tab(pc, g.shape_pc, 1, stream);
+    }
+    if (e != hipSuccess) return server_fail(TRSTMI_E_HIP, std::string("engine step: ") + hipGetErrorString(e));
+  }
   return TRSTMI_OK;
 }
 

@@ -177,20 +177,35 @@ class Server:
         return summarize(reqs, wall, self.candidates, s.pool_peak, s.pool_capacity)
 
 
+def _pct(values, q):
+    return float(np.percentile(np.array(values), q)) if len(values) else math.nan
+
+
 def summarize(reqs, wall, candidates, peak_bytes, cap_bytes):
+    """Latency = finish - arrival: over every finished request (time to the
+    target or to the step cap) and over those that reached the target (time
+    to target); queue = admission - arrival; evals = steps x candidates, and
+    the screen's algorithmic flops 8 d N (N - 1) / 2 per eval."""
     done = [r for r in reqs if r.status == "done"]
-    lat = np.array([r.latency for r in done]) if done else np.array([math.nan])
+    reached = [r for r in done if r.reached]
     evals = sum(r.steps * candidates for r in done)
+    flops = sum(r.steps * candidates * 4.0 * r.d * r.n * (r.n - 1) for r in done)
+    queue = [r.admit - r.arrival for r in done]
     return {
         "requests": len(reqs),
         "done": len(done),
         "rejected": sum(r.status == "rejected" for r in reqs),
         "errors": sum(r.status == "error" for r in reqs),
-        "reached_target": sum(r.reached for r in done),
-        "p50_latency_s": float(np.percentile(lat, 50)),
-        "p99_latency_s": float(np.percentile(lat, 99)),
-        "mean_queue_s": float(np.mean([r.admit - r.arrival for r in done])) if done else math.nan,
+        "reached_target": len(reached),
+        "p50_latency_s": _pct([r.latency for r in done], 50),
+        "p99_latency_s": _pct([r.latency for r in done], 99),
+        "p50_time_to_target_s": _pct([r.latency for r in reached], 50),
+        "p99_time_to_target_s": _pct([r.latency for r in reached], 99),
+        "mean_queue_s": float(np.mean(queue)) if done else math.nan,
+        "p50_queue_s": _pct(queue, 50),
+        "p99_queue_s": _pct(queue, 99),
         "evals_per_s": evals / wall if wall > 0 else math.nan,
+        "screen_tflops": flops / wall / 1e12 if wall > 0 else math.nan,
         "wall_s": wall,
         "median_mu_over_welch": float(np.median([r.mu / welch_bound(r.n, r.d) for r in done])) if done else math.nan,
         "pool_peak_bytes": int(peak_bytes),
