@@ -213,6 +213,23 @@ size_t trstmi_lse_workspace_bytes(int64_t n, int64_t d);
 trstmi_status trstmi_lse(int64_t n, int64_t d, const double* frame, double delta, int32_t squared,
                          double* out, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Tile choice of the BF16 screen (speed only: every result is the same
+ * under any choice).  An entry applies to frames with ks = ceil(2d / 32) K
+ * steps of 32 and n <= n_max (the entry with the smallest such n_max):
+ * form 0 = blocks of 256 frame rows (64 per wavefront, ks <= 4), form 1 =
+ * blocks of 128 rows (32 per wavefront); seg = column tiles of 128 one block
+ * sweeps after loading its rows (1 .. 64).  Without an entry: form 0 with
+ * runs of 6 for ks <= 4, form 1 with runs of 8 above.  The table is
+ * process-wide and copied; it applies to steps, solves and server
+ * admissions prepared after the call (count 0 clears it).  Written by
+ * paper_2207_06374_amd.autotune from timings on the device.
+ */
+typedef struct {
+  int32_t ks, n_max, form, seg;
+} trstmi_screen_tile;
+trstmi_status trstmi_screen_tiles_set(const trstmi_screen_tile* entries, int32_t count);
+
 /* Bytes of workspace trstmi_lse_grad needs (0 if invalid or d > 64). */
 size_t trstmi_lse_grad_workspace_bytes(int64_t n, int64_t d);
 

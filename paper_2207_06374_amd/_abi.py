@@ -161,6 +161,7 @@ SIGNATURES = {
     "trstmi_lse_grad_workspace_bytes": (_sz, [_i64, _i64]),
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_server_table_bytes": (_sz, [_i32]),
+    "trstmi_screen_tiles_set": (_i32, [_vp, _i32]),
     "trstmi_welch_bound": (ctypes.c_double, [_i64, _i64]),
     "trstmi_coherence_noalloc_max_bytes": (_sz, []),
     "trstmi_coherence_noalloc": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp]),
@@ -219,7 +220,32 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        _install_screen_tiles(L)
     return _lib
+
+
+class ScreenTile(ctypes.Structure):
+    _fields_ = [("ks", _i32), ("n_max", _i32), ("form", _i32), ("seg", _i32)]
+
+
+SCREEN_TILES_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "screen_tiles.json")
+
+
+def set_screen_tiles(entries, L=None):
+    """Installs a BF16 screen tile table: a list of dicts with ks, n_max,
+    form and seg (an empty list restores the library's defaults)."""
+    L = L or lib()
+    arr = (ScreenTile * max(len(entries), 1))(*[ScreenTile(int(e["ks"]), int(e["n_max"]), int(e["form"]),
+                                                             int(e["seg"])) for e in entries])
+    check(L.trstmi_screen_tiles_set(arr, len(entries)), "trstmi_screen_tiles_set")
+
+
+def _install_screen_tiles(L):
+    """The tuned table shipped with the package (written by autotune), if any."""
+    import json
+    if os.path.exists(SCREEN_TILES_PATH):
+        with open(SCREEN_TILES_PATH) as f:
+            set_screen_tiles(json.load(f).get("entries", []), L)
 
 
 class TrstmiError(RuntimeError):

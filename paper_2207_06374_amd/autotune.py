@@ -1,13 +1,23 @@
-"""Tile autotuner for the batched form.
+"""Tile autotuners.
 
-The batched kernel processes each candidate with 1, 2 or 4 wavefronts
-(``waves_per_item``).  The choice changes only speed, never results (each
-pair is computed by the same code whatever the split).  This module times
-every feasible choice on homogeneous batches of one (d, N) class and keeps the
-fastest per class in a JSON table; ``Batch`` consults the table for instances
-that do not fix ``waves_per_item`` themselves.
+Batched form: the batched kernel processes each candidate with 1, 2 or 4
+wavefronts (``waves_per_item``).  The choice changes only speed, never
+results (each pair is computed by the same code whatever the split).  This
+module times every feasible choice on homogeneous batches of one (d, N) class
+and keeps the fastest per class in a JSON table; ``Batch`` consults the table
+for instances that do not fix ``waves_per_item`` themselves.
+
+BF16 screen (single searches, solves and the serving engine): the tile form
+(blocks of 256 frame rows, 64 per wavefront, for 2d <= 128; or of 128 rows,
+32 per wavefront) and the run length (column tiles of 128 a block sweeps
+after loading its rows) are timed per (K steps, N) class with whole steps of
+64 candidates, and the fastest go to ``screen_tiles.json``, which the binding
+installs in the library when it loads it.  Every choice gives the same
+screened values (each pair's product is the same MFMA sequence), so results
+never change.
 
 Run on the GPU:  python -m paper_2207_06374_amd.autotune [--out PATH]
+                 python -m paper_2207_06374_amd.autotune --screen [--screen-out PATH]
 """
 
 from __future__ import annotations
@@ -95,10 +105,75 @@ def autotune(out=TABLE_PATH, candidates=64, count=128, steps=6, verbose=True):
     return table
 
 
+SCREEN_TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "screen_tiles.json")
+# (d, n_max) classes: the serving mix (d in {8, 16, 32, 64, 128}, N in
+# [2d, 8d]) in N buckets, and the throughput shape N = 4096, d = 64
+SCREEN_CLASSES = ((16, 64), (16, 128), (32, 128), (32, 256), (64, 128), (64, 256), (64, 512), (64, 4096),
+                  (128, 256), (128, 512), (128, 1024))
+SCREEN_SEGS = (1, 2, 3, 4, 6, 8, 12, 16)
+
+
+def screen_options(d):
+    ks = (2 * d + 31) // 32
+    forms = (0, 1) if ks <= 4 else (1,)
+    return [(f, g) for f in forms for g in SCREEN_SEGS]
+
+
+def time_screen(lib, torch, n, d, form, seg, candidates=64, steps=20, reps=3):
+    """Microseconds per whole BF16-screen step (64 candidates) with this tile
+    choice installed for (ks, n)."""
+    from . import _abi
+    ks = (2 * d + 31) // 32
+    _abi.set_screen_tiles([{"ks": ks, "n_max": n, "form": form, "seg": seg}])
+    s = lib.Solver(n, d, candidates=candidates, mode="bf16", radius0=0.05, max_steps=10 ** 6, seed=0)
+    s.init_haar()
+    for _ in range(3):
+        s.step(with_report=False)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step(with_report=False)
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t0) / steps * 1e6)
+    return best
+
+
+def autotune_screen(out=SCREEN_TABLE_PATH, candidates=64, steps=20, verbose=True):
+    import torch
+
+    import paper_2207_06374_amd as lib
+    from . import _abi
+    entries = []
+    try:
+        for d, n in SCREEN_CLASSES:
+            times = {(f, g): time_screen(lib, torch, n, d, f, g, candidates, steps) for f, g in screen_options(d)}
+            f, g = min(times, key=times.get)
+            default = (0, 6) if (2 * d + 31) // 32 <= 4 else (1, 8)
+            entries.append({"ks": (2 * d + 31) // 32, "n_max": n, "d": d, "form": f, "seg": g,
+                            "us_per_step": round(times[(f, g)], 2), "default_us_per_step": round(times[default], 2)})
+            if verbose:
+                print(f"d={d:3d} n<={n:4d}: best form {f} seg {g:2d} {times[(f, g)]:9.1f} us/step "
+                      f"(default {times[default]:9.1f})", flush=True)
+    finally:
+        _abi.set_screen_tiles([])
+    table = {"version": 1, "candidates": candidates, "entries": entries}
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    _abi.set_screen_tiles(entries)
+    return table
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE_PATH)
     ap.add_argument("--count", type=int, default=128)
     ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--screen", action="store_true", help="tune the BF16 screen's tiles instead")
+    ap.add_argument("--screen-out", default=SCREEN_TABLE_PATH)
     args = ap.parse_args()
-    autotune(args.out, count=args.count, steps=args.steps)
+    if args.screen:
+        autotune_screen(args.screen_out)
+    else:
+        autotune(args.out, count=args.count, steps=args.steps)

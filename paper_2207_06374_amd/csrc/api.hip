@@ -859,6 +859,22 @@ trstmi_status trstmi_lse_grad(int64_t n, int64_t d, const double* frame, double 
   return TRSTMI_OK;
 }
 
+trstmi_status trstmi_screen_tiles_set(const trstmi_screen_tile* entries, int32_t count) {
+  if (count < 0 || count > 4096 || (count > 0 && !entries))
+    return fail(TRSTMI_E_INVALID_ARG, "count must be in [0, 4096] with a host array of that many entries");
+  std::vector<ScreenTile> t(count);
+  for (int32_t i = 0; i < count; ++i) {
+    const trstmi_screen_tile& e = entries[i];
+    if (e.ks < 1 || e.ks > 8 || e.n_max < 2 || (e.form != 0 && e.form != 1) || (e.form == 0 && e.ks > 4) ||
+        e.seg < 1 || e.seg > 64)
+      return fail(TRSTMI_E_INVALID_ARG, "screen tile entry " + std::to_string(i) +
+                                            ": need 1 <= ks <= 8, n_max >= 2, form 0 (ks <= 4) or 1, 1 <= seg <= 64");
+    t[i] = ScreenTile{e.ks, e.n_max, e.form, e.seg};
+  }
+  screen_tiles_set(t.data(), count);
+  return TRSTMI_OK;
+}
+
 size_t trstmi_lse_hvp_workspace_bytes(int64_t n, int64_t d) {
   if (check_size(n, d) || d > 64) return 0;
   return trstmi_lse_workspace_bytes(n, d) + 256 + hv_scratch_bytes(n, d);
@@ -1445,7 +1461,7 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 11; }
+int32_t trstmi_abi_version(void) { return 12; }
 
 }  // extern "C"
 

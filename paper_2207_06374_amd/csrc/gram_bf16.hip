@@ -47,6 +47,9 @@
 // Fallback kernel (2d > 256, coherence entry point only): 128 x 128 tiles, K
 // looped in LDS chunks of 128.
 
+#include <mutex>
+#include <vector>
+
 #include "device_common.h"
 #include "launch.h"
 
@@ -55,7 +58,6 @@ namespace trstmi {
 namespace {
 
 constexpr int T = kTileBF16;
-constexpr int kSeg = 8;  // column tiles per row segment
 
 __device__ __forceinline__ u32x4 swap_negate(u32x4 u) {
   u32x4 v;
@@ -257,19 +259,19 @@ __device__ __forceinline__ uint32_t tile_max_wave(const ARows<KS>& A, const uint
 }
 
 // Segment s of the row-segment enumeration: row block bi in order, each row
-// block split into ceil((nt - bi) / kSeg) runs of at most kSeg column tiles.
-__device__ __forceinline__ void seg_decode(int s, int nt, int& bi, int& bj0, int& bj1) {
+// block split into ceil((nt - bi) / seg) runs of at most seg column tiles.
+__device__ __forceinline__ void seg_decode(int s, int nt, int seg, int& bi, int& bj0, int& bj1) {
   int r = 0;
   int rem = s;
   for (;;) {
-    const int ns = (nt - r + kSeg - 1) / kSeg;
+    const int ns = (nt - r + seg - 1) / seg;
     if (rem < ns) break;
     rem -= ns;
     ++r;
   }
   bi = r;
-  bj0 = r + rem * kSeg;
-  bj1 = bj0 + kSeg < nt ? bj0 + kSeg : nt;
+  bj0 = r + rem * seg;
+  bj1 = bj0 + seg < nt ? bj0 + seg : nt;
 }
 
 // Narrow kernel.  Two blocks per CU while the whole-K rows fit (2d <= 160);
@@ -282,7 +284,7 @@ __device__ __forceinline__ void gram_bf16_narrow(const GramArgs& a, int b) {
   const int seg = local % a.nseg;
   if (slot >= a.slots) return;
   int bi, bj0, bj1;
-  seg_decode(seg, a.nt, bi, bj0, bj1);
+  seg_decode(seg, a.nt, a.segk, bi, bj0, bj1);
   const int tiles = a.nt * (a.nt + 1) / 2;
 
   // Two B tiles while two blocks still fit in LDS: tile bj + 1 is stored
@@ -483,21 +485,20 @@ __device__ __forceinline__ uint32_t tile_max_k(const QRows<KS>& A, const uint16_
 
 // Row segments of 256-row blocks: row block r (tile rows 2r, 2r + 1) against
 // runs of column tiles bj >= 2r; the nt - 2r tiles of row block r are split
-// into ceil((nt - 2r) / kSegK) runs of equal length (within one tile), so
+// into ceil((nt - 2r) / seg) runs of equal length (within one tile), so
 // every block does about the same work and the A rows are loaded once per
-// run of up to kSegK tiles.
-constexpr int kSegK = 6;
-__device__ __forceinline__ void seg_decode_k(int s, int nt, int& r, int& bj0, int& bj1) {
+// run of up to seg tiles (6 measured best at N = 4096, d = 64 among 3..16).
+__device__ __forceinline__ void seg_decode_k(int s, int nt, int seg, int& r, int& bj0, int& bj1) {
   r = 0;
   int rem = s;
   for (;;) {
-    const int ns = (nt - 2 * r + kSegK - 1) / kSegK;
+    const int ns = (nt - 2 * r + seg - 1) / seg;
     if (rem < ns) break;
     rem -= ns;
     ++r;
   }
   const int L = nt - 2 * r;
-  const int ns = (L + kSegK - 1) / kSegK;
+  const int ns = (L + seg - 1) / seg;
   bj0 = 2 * r + (rem * L) / ns;
   bj1 = 2 * r + ((rem + 1) * L) / ns;
 }
@@ -510,7 +511,7 @@ __device__ __forceinline__ void gram_bf16_wide(const GramArgs& a, int b) {
   const int seg = local % a.nseg;
   if (slot >= a.slots) return;
   int r, bj0, bj1;
-  seg_decode_k(seg, a.nt, r, bj0, bj1);
+  seg_decode_k(seg, a.nt, a.segk, r, bj0, bj1);
   const int tiles = a.nt * (a.nt + 1) / 2;
 
   constexpr int kBuf = T * (32 * KS + 8);
@@ -586,9 +587,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16_k_tab(TabRef t) {
   gram_bf16_wide<KS>(a, blockIdx.x);
 }
 
-int k_segments(int nt) {
+int k_segments(int nt, int seg) {
   int total = 0;
-  for (int r = 0; 2 * r < nt; ++r) total += (nt - 2 * r + kSegK - 1) / kSegK;
+  for (int r = 0; 2 * r < nt; ++r) total += (nt - 2 * r + seg - 1) / seg;
   return total;
 }
 
@@ -850,11 +851,15 @@ hipError_t launch_rp(const RecheckArgs& a, int grid, hipStream_t s, const TabRef
 // the group)
 template <int KS>
 hipError_t launch_ks(const GramArgs& a, int grid, hipStream_t s, const TabRef* tab) {
-  if constexpr (KS <= 4) {
-    if (tab)
-      hipLaunchKernelGGL(k_gram_bf16_k_tab<KS>, dim3(grid, tab->count), dim3(256), 0, s, *tab);
-    else
-      hipLaunchKernelGGL(k_gram_bf16_k<KS>, dim3(grid), dim3(256), 0, s, a);
+  bool wide = false;
+  if constexpr (KS <= 4) wide = a.form == 0;
+  if (wide) {
+    if constexpr (KS <= 4) {
+      if (tab)
+        hipLaunchKernelGGL(k_gram_bf16_k_tab<KS>, dim3(grid, tab->count), dim3(256), 0, s, *tab);
+      else
+        hipLaunchKernelGGL(k_gram_bf16_k<KS>, dim3(grid), dim3(256), 0, s, a);
+    }
   } else {
     if (tab)
       hipLaunchKernelGGL(k_gram_bf16_tab<KS>, dim3(grid, tab->count), dim3(256), 0, s, *tab);
@@ -900,25 +905,47 @@ hipError_t launch_rp_any(const RecheckArgs& a, int grid, hipStream_t s, const Ta
 
 }  // namespace
 
-int bf16_segments(int nt) {
+int bf16_segments(int nt, int seg) {
   int total = 0;
-  for (int r = 0; r < nt; ++r) total += (nt - r + kSeg - 1) / kSeg;
+  for (int r = 0; r < nt; ++r) total += (nt - r + seg - 1) / seg;
   return total;
+}
+
+namespace {
+std::mutex g_tiles_mu;
+std::vector<ScreenTile> g_tiles;
+}  // namespace
+
+void screen_tiles_set(const ScreenTile* e, int32_t count) {
+  std::lock_guard<std::mutex> g(g_tiles_mu);
+  g_tiles.assign(e, e + count);
+}
+
+void screen_tile_choose(int64_t n, int32_t ks, int32_t* form, int32_t* seg) {
+  *form = ks <= 4 ? 0 : 1;
+  *seg = ks <= 4 ? 6 : 8;
+  std::lock_guard<std::mutex> g(g_tiles_mu);
+  const ScreenTile* best = nullptr;
+  for (const ScreenTile& t : g_tiles)
+    if (t.ks == ks && t.n_max >= n && (!best || t.n_max < best->n_max)) best = &t;
+  if (best) {
+    *form = best->form;
+    *seg = best->seg;
+  }
 }
 
 int gram_bf16_prepare(GramArgs& a, int slots) {
   a.slots = slots;
   const long slots8 = (slots + 7) / 8 * 8;
   const int ks = a.ldk % 32 == 0 ? a.ldk / 32 : 0;
-  if (ks >= 1 && ks <= 4) {
-    a.nseg = k_segments(a.nt);
-  } else if (ks >= 5 && ks <= 8) {
-    a.nseg = bf16_segments(a.nt);
-  } else {
-    a.nseg = 0;
-    return (int)((long)a.nt * (a.nt + 1) / 2 * slots8);
+  if (ks >= 1 && ks <= 8) {
+    screen_tile_choose(a.n, ks, &a.form, &a.segk);
+    if (ks > 4) a.form = 1;  // 256-row blocks hold the whole K only up to 2d = 128
+    a.nseg = a.form == 0 ? k_segments(a.nt, a.segk) : bf16_segments(a.nt, a.segk);
+    return (int)((long)a.nseg * slots8);
   }
-  return (int)((long)a.nseg * slots8);
+  a.nseg = 0;
+  return (int)((long)a.nt * (a.nt + 1) / 2 * slots8);
 }
 
 hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
@@ -927,9 +954,10 @@ hipError_t launch_gram_bf16(const GramArgs& a_in, int slots, hipStream_t s) {
   return launch_gram_any(a, grid, s, nullptr);
 }
 
-hipError_t launch_gram_bf16_tab(const TabRef& t, int ldk, int grid, hipStream_t s) {
+hipError_t launch_gram_bf16_tab(const TabRef& t, int ldk, int form, int grid, hipStream_t s) {
   GramArgs shape{};
   shape.ldk = ldk;
+  shape.form = form;
   return launch_gram_any(shape, grid, s, &t);
 }
 

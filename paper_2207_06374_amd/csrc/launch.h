@@ -62,6 +62,8 @@ struct GramArgs {
   uint64_t* cand_max;        // [slot] running max (bits of the float type)
   const int32_t* flags;      // DONE gate (null: always run)
   uint32_t* tile_max;        // screen: [slot][ntiles][4] max bits per tile and wave (null: not kept)
+  int32_t form;              // BF16 screen: 0 = 256-row blocks (2d <= 128), 1 = 128-row blocks (set by the launcher)
+  int32_t segk;              // BF16 screen: column tiles per block run (set by the launcher from the tile table)
 };
 
 struct SelectArgs {
@@ -282,13 +284,23 @@ trstmi_status tr_step_impl(int64_t n, int64_t d, double* frame, const trstmi_tr_
                            char* ws, size_t lws_bytes, hipStream_t stream);
 hipError_t launch_gram_f32(const GramArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_bf16(const GramArgs& a, int slots, hipStream_t s);
-// Fills a.slots and a.nseg as launch_gram_bf16 does; returns that launch's grid.
+// Fills a.slots, a.form, a.segk and a.nseg as launch_gram_bf16 does (form
+// and run length from the screen tile table); returns that launch's grid.
 int gram_bf16_prepare(GramArgs& a, int slots);
+// The screen tile table (process-wide): form and run length by K steps
+// (ks = 2d / 32 rounded up) and the smallest n_max >= n; without an entry,
+// 256-row blocks with runs of 6 tiles for ks <= 4, 128-row blocks with runs of
+// 8 tiles above.  The choice changes speed only, never a result.
+struct ScreenTile {
+  int32_t ks, n_max, form, seg;
+};
+void screen_tiles_set(const ScreenTile* e, int32_t count);
+void screen_tile_choose(int64_t n, int32_t ks, int32_t* form, int32_t* seg);
 int recheck_grid(int list_cap);
 // Group launches over a table (see StepArgs).  shape: a record with the
 // group's d, output kind and largest n; grid: the largest grid of the group.
 hipError_t launch_perturb_tab(const TabRef& t, const PerturbArgs& shape, int slots, hipStream_t s);
-hipError_t launch_gram_bf16_tab(const TabRef& t, int ldk, int grid, hipStream_t s);
+hipError_t launch_gram_bf16_tab(const TabRef& t, int ldk, int form, int grid, hipStream_t s);
 hipError_t launch_topk_tab(const TabRef& t, hipStream_t s);
 hipError_t launch_recheck_tab(const TabRef& t, int ldk16, int grid, hipStream_t s);
 hipError_t launch_select_tab(const TabRef& t, hipStream_t s);

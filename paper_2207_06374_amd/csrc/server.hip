@@ -6,7 +6,8 @@
 // memory: each admitted request has a row holding every argument record of
 // its step (frame, radius, step counter and workspace live in its range of
 // the caller's pool).  Per step the engine launches each kernel of the
-// BF16-screen step once per group of admitted requests with the same d (the
+// BF16-screen step once per group of admitted requests with the same d and
+// screen tile form (the
 // request is a grid dimension; each block reads its request's record; the
 // top-k and the selection, which do not depend on d, once for all of them),
 // so one launch sequence advances every request in flight, each with exactly
@@ -83,9 +84,10 @@ struct Running {
   int32_t row;
 };
 
-// Admitted requests of one d, launched together.
+// Admitted requests of one d and one screen form, launched together.
 struct Group {
   int32_t d;
+  int32_t form;
   int32_t first, count;       // their rows in the list region
   trstmi::PerturbArgs shape_pa, shape_pr, shape_pc;  // launch shapes (largest n)
   int32_t ldk16;
@@ -148,12 +150,13 @@ trstmi_status trstmi_server::admit(Running& r) {
 trstmi_status trstmi_server::rebuild() {
   drop_graph();
   groups.clear();
-  std::map<int32_t, std::vector<int32_t>> by_d;
-  for (auto& kv : running) by_d[(int32_t)kv.second.params.d].push_back(kv.first);
+  std::map<std::pair<int32_t, int32_t>, std::vector<int32_t>> by_d;
+  for (auto& kv : running) by_d[{(int32_t)kv.second.params.d, tab_host[kv.first].g.form}].push_back(kv.first);
   list_host.clear();
   for (auto& kv : by_d) {
     Group g{};
-    g.d = kv.first;
+    g.d = kv.first.first;
+    g.form = kv.first.second;
     g.first = (int32_t)list_host.size();
     g.count = (int32_t)kv.second.size();
     int64_t n_max = 0;
@@ -204,7 +207,7 @@ trstmi_status trstmi_server::launch_steps(int steps) {
       const trstmi::TabRef pa{tab_dev + offsetof(trstmi::StepArgs, pa), S, list_dev + g.first, g.count};
       const trstmi::TabRef gr{tab_dev + offsetof(trstmi::StepArgs, g), S, list_dev + g.first, g.count};
       if (e == hipSuccess) e = trstmi::launch_perturb_tab(pa, g.shape_pa, p.candidates, stream);
-      if (e == hipSuccess) e = trstmi::launch_gram_bf16_tab(gr, g.ldk16, g.gram_grid, stream);
+      if (e == hipSuccess) e = trstmi::launch_gram_bf16_tab(gr, g.ldk16, g.form, g.gram_grid, stream);
     }
     if (e == hipSuccess) e = trstmi::launch_topk_tab(all(offsetof(trstmi::StepArgs, ta)), stream);
     for (const Group& g : groups) {

@@ -264,6 +264,21 @@ def test_coherence_noalloc_refuses_oversized_frames_on_the_host(L):
     assert L.trstmi_coherence_noalloc(16, 4, 7, p, p, None) == abi.E_INVALID_ARG
 
 
+def test_screen_tiles_argument_checks(L):
+    T = abi.ScreenTile
+    good = (T * 2)(T(4, 512, 0, 6), T(8, 1024, 1, 64))
+    assert L.trstmi_screen_tiles_set(good, 2) == abi.OK
+    for bad in (T(0, 512, 0, 6), T(9, 512, 1, 6), T(4, 1, 0, 6), T(4, 512, 2, 6), T(5, 512, 0, 6),
+                T(4, 512, 0, 0), T(4, 512, 1, 65)):
+        one = (T * 1)(bad)
+        assert L.trstmi_screen_tiles_set(one, 1) == abi.E_INVALID_ARG
+    assert L.trstmi_screen_tiles_set(None, 1) == abi.E_INVALID_ARG
+    assert L.trstmi_screen_tiles_set(None, -1) == abi.E_INVALID_ARG
+    assert L.trstmi_screen_tiles_set(None, 0) == abi.OK
+    abi._install_screen_tiles(L)
+    assert L.trstmi_abi_version() >= 12
+
+
 def test_optimize_argument_checks(L):
     need = L.trstmi_optimize_workspace_bytes(9, 3, 1)
     assert need > L.trstmi_tr_workspace_bytes(9, 3)
