@@ -367,6 +367,29 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* par
                               double* best_mu, int32_t* best_restart, void* workspace,
                               size_t workspace_bytes, hipStream_t stream);
 
+/* Bytes of workspace trstmi_optimize_batched needs for `restarts` starts (0
+ * if n > 128, d > 16 or an argument is invalid). */
+size_t trstmi_optimize_batched_workspace_bytes(int64_t n, int64_t d, int32_t restarts);
+
+/*
+ * The same procedure as trstmi_optimize (Alg. 2 around Alg. 1 steps with
+ * exact Hessian products; the same parameters, starts and result) with every
+ * start advanced by one block of a single launch: each block draws its
+ * start, runs every delta's trust-region steps (Steihaug CG, ratio test,
+ * radius rule) with all vector work and every scalar decision on the device,
+ * and ends with the exact FP64 coherence of its frame; the host then picks
+ * the least coherence (lowest start index among equal values) and copies
+ * that frame to best_frame.  No host synchronisation inside the procedure,
+ * one launch for all starts.  For n <= 128, d <= 16 (the frame and its
+ * normalisation sit in one block's LDS); larger sizes and fd_step != 0 give
+ * TRSTMI_E_UNSUPPORTED.  params->concurrency is ignored.  Every start
+ * follows the oracle's step (rounding aside), so results match
+ * trstmi_optimize's to rounding, not bit for bit.  Synchronises the stream.
+ */
+trstmi_status trstmi_optimize_batched(int64_t n, int64_t d, const trstmi_opt_params* params, double* best_frame,
+                                      double* best_mu, int32_t* best_restart, void* workspace,
+                                      size_t workspace_bytes, hipStream_t stream);
+
 /* Bytes of workspace trstmi_miso_quantize needs (0 if a size is invalid). */
 size_t trstmi_miso_workspace_bytes(int64_t n, int64_t d, int64_t m);
 

@@ -210,21 +210,38 @@ def tr_step(frame, n, d, delta, radius, radius_max=1.0, eta=0.1, cg_tol=1e-8, cg
 
 def optimize(n, d, restarts=None, deltas=(1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4), steps_per_delta=40, seed=0,
              radius0=0.1, radius_min=1e-10, radius_max=1.0, eta=0.1, cg_tol=1e-10, cg_max_iter=0, fd_step=0.0,
-             concurrency=None, first_restart=0, device="cuda", workspace=None, stream=None):
+             concurrency=None, first_restart=0, device="cuda", workspace=None, stream=None, engine=None):
     """The outer procedure of Alg. 2 (delta continuation and random restarts
     around trust-region steps).  Returns (best frame as a device tensor,
-    best coherence, best restart index).  restarts defaults to 2 d^2;
-    concurrency (starts in flight, one host thread and stream each)
-    defaults to min(restarts, 16).  The starts are first_restart ..
-    first_restart + restarts - 1, so one run may be split into calls."""
+    best coherence, best restart index).  restarts defaults to 2 d^2.  The
+    starts are first_restart .. first_restart + restarts - 1, so one run may
+    be split into calls.  engine "batched": every start in one block of a
+    single launch (n <= 128, d <= 16, exact Hessian products); "threads":
+    concurrency starts in flight on host threads with a stream each
+    (default min(restarts, 16)), host-driven steps; None: "batched" where it
+    applies."""
     torch = _torch()
     L = int(restarts) if restarts is not None else 2 * int(d) * int(d)
     P = int(concurrency) if concurrency is not None else min(L, 16)
+    if engine is None:
+        engine = "batched" if int(n) <= 128 and int(d) <= 16 and float(fd_step) == 0.0 else "threads"
     dl = (ctypes.c_double * len(deltas))(*[float(x) for x in deltas])
     p = _abi.OptParams(int(seed), L, len(deltas), dl, int(steps_per_delta), float(radius0), float(radius_min),
                        float(radius_max), float(eta), float(cg_tol), int(cg_max_iter), float(fd_step), P,
                        int(first_restart))
     out = torch.empty(2 * int(d) * int(n), dtype=torch.float64, device=device)
+    if engine == "batched":
+        if workspace is None:
+            need = _abi.lib().trstmi_optimize_batched_workspace_bytes(int(n), int(d), L)
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+        mu = ctypes.c_double()
+        best = ctypes.c_int32()
+        _abi.check(_abi.lib().trstmi_optimize_batched(int(n), int(d), ctypes.byref(p), _ptr(out), ctypes.byref(mu),
+                                                      ctypes.byref(best), _ptr(workspace), workspace.numel(),
+                                                      _stream(stream)), "trstmi_optimize_batched")
+        return out, mu.value, best.value
+    if engine != "threads":
+        raise ValueError("engine must be None, 'batched' or 'threads'")
     if workspace is None:
         need = _abi.lib().trstmi_optimize_workspace_bytes(int(n), int(d), P)
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)

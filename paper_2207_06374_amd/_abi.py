@@ -162,6 +162,9 @@ SIGNATURES = {
     "trstmi_lse_grad": (_i32, [_i64, _i64, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "trstmi_server_table_bytes": (_sz, [_i32]),
     "trstmi_screen_tiles_set": (_i32, [_vp, _i32]),
+    "trstmi_optimize_batched_workspace_bytes": (_sz, [_i64, _i64, _i32]),
+    "trstmi_optimize_batched": (_i32, [_i64, _i64, _P(OptParams), _vp, _P(ctypes.c_double), _P(ctypes.c_int32), _vp,
+                                       _sz, _vp]),
     "trstmi_welch_bound": (ctypes.c_double, [_i64, _i64]),
     "trstmi_coherence_noalloc_max_bytes": (_sz, []),
     "trstmi_coherence_noalloc": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp]),

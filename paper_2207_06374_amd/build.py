@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtrstmi.so")
 
-SOURCES = ["perturb.hip", "gram_f64.hip", "gram_f32.hip", "gram_bf16.hip", "select.hip", "batch.hip", "lse_grad.hip", "lse_hv.hip",
+SOURCES = ["perturb.hip", "gram_f64.hip", "gram_f32.hip", "gram_bf16.hip", "select.hip", "batch.hip", "lse_grad.hip", "lse_hv.hip", "opt_batch.hip",
            "miso.hip", "server.hip",
            "trust_region.hip", "api.hip"]
 

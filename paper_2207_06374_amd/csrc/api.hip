@@ -1128,6 +1128,71 @@ trstmi_status trstmi_optimize(int64_t n, int64_t d, const trstmi_opt_params* op,
   return TRSTMI_OK;
 }
 
+size_t trstmi_optimize_batched_workspace_bytes(int64_t n, int64_t d, int32_t restarts) {
+  if (n < 2 || n > kOptMaxN || d < 1 || d > kOptMaxD || restarts < 1) return 0;
+  return align256((size_t)restarts * opt_batch_stride(n, d) * 8) + align256((size_t)restarts * 8) + 256 * 8;
+}
+
+trstmi_status trstmi_optimize_batched(int64_t n, int64_t d, const trstmi_opt_params* op, double* best_frame,
+                                      double* best_mu, int32_t* best_restart, void* workspace,
+                                      size_t workspace_bytes, hipStream_t stream) {
+  trstmi_status st = check_size(n, d);
+  if (st) return st;
+  if (n > kOptMaxN || d > kOptMaxD)
+    return fail(TRSTMI_E_UNSUPPORTED, "the batched optimiser holds a start in one block: n <= 128, d <= 16");
+  if (!op || !best_mu || !best_restart) return fail(TRSTMI_E_INVALID_ARG, "params, best_mu and best_restart are host pointers");
+  auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
+  bool ok = op->restarts >= 1 && op->n_deltas >= 1 && op->n_deltas <= 256 && op->deltas && op->steps_per_delta >= 1 &&
+            pos(op->radius0) && op->radius_min >= 0.0 && op->radius_max >= op->radius0 &&
+            std::isfinite(op->radius_max) && op->eta >= 0.0 && op->eta < 0.25 && pos(op->cg_tol) &&
+            op->cg_max_iter >= 0 && op->first_restart >= 0 && (int64_t)op->first_restart + op->restarts <= INT32_MAX;
+  for (int32_t k = 0; ok && k < op->n_deltas; ++k) ok = pos(op->deltas[k]);
+  if (!ok) return fail(TRSTMI_E_INVALID_ARG, "invalid optimiser parameters");
+  if (op->fd_step != 0.0) return fail(TRSTMI_E_UNSUPPORTED, "the batched optimiser uses exact Hessian products (fd_step 0)");
+  if (!best_frame || ((uintptr_t)best_frame & 15)) return fail(TRSTMI_E_INVALID_ARG, "best_frame: null or misaligned");
+  const size_t need = trstmi_optimize_batched_workspace_bytes(n, d, op->restarts);
+  if ((st = check_ws(workspace, workspace_bytes, need))) return st;
+  char* ws = (char*)workspace;
+  const size_t stride = opt_batch_stride(n, d);
+  const size_t work_bytes = align256((size_t)op->restarts * stride * 8);
+  double* mu = (double*)(ws + work_bytes);
+  double* deltas = (double*)(ws + work_bytes + align256((size_t)op->restarts * 8));
+  OptBatchArgs a{};
+  a.n = (int32_t)n;
+  a.d = (int32_t)d;
+  a.starts = op->restarts;
+  a.first = op->first_restart;
+  a.seed = (uint32_t)op->seed;
+  a.n_deltas = op->n_deltas;
+  a.steps_per_delta = op->steps_per_delta;
+  a.cg_max_iter = op->cg_max_iter ? op->cg_max_iter : (int32_t)(2 * d * n);
+  a.deltas = deltas;
+  a.radius0 = op->radius0;
+  a.radius_min = op->radius_min;
+  a.radius_max = op->radius_max;
+  a.eta = op->eta;
+  a.cg_tol = op->cg_tol;
+  a.work = (double*)ws;
+  a.stride = (int64_t)stride;
+  a.mu = mu;
+  TRY_HIP(hipMemcpyAsync(deltas, op->deltas, (size_t)op->n_deltas * 8, hipMemcpyHostToDevice, stream), "deltas");
+  TRY_HIP(TIMED("opt_batch", stream, launch_opt_batch(a, stream)), "optimise (batched)");
+  std::vector<double> host_mu(op->restarts);
+  TRY_HIP(hipMemcpyAsync(host_mu.data(), mu, (size_t)op->restarts * 8, hipMemcpyDeviceToHost, stream), "read mu");
+  TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+  int32_t best = -1;
+  for (int32_t l = 0; l < op->restarts; ++l)
+    if (host_mu[l] == host_mu[l] && (best < 0 || host_mu[l] < host_mu[best])) best = l;
+  *best_mu = best >= 0 ? host_mu[best] : __builtin_inf();
+  *best_restart = best >= 0 ? op->first_restart + best : -1;
+  if (best >= 0) {
+    TRY_HIP(hipMemcpyAsync(best_frame, a.work + (size_t)best * stride, (size_t)2 * d * n * 8, hipMemcpyDeviceToDevice,
+                           stream), "optimise: copy");
+    TRY_HIP(hipStreamSynchronize(stream), "optimise: sync");
+  }
+  return TRSTMI_OK;
+}
+
 trstmi_status trstmi_init_haar(const trstmi_params* p, const trstmi_state* state, void* workspace,
                                size_t workspace_bytes, hipStream_t stream) {
   trstmi_status st = check_params(p);
@@ -1461,7 +1526,7 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 12; }
+int32_t trstmi_abi_version(void) { return 13; }
 
 }  // extern "C"
 

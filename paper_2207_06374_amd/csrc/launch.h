@@ -249,6 +249,23 @@ struct HvArgs {
 size_t hv_scratch_bytes(int64_t n, int64_t d);
 void hv_layout(HvArgs& a, char* scratch, int64_t n, int64_t d);
 hipError_t launch_lse_hv(const HvArgs& a, hipStream_t s);
+// Alg. 2 with one block per random start (opt_batch.hip): n <= kOptMaxN,
+// d <= kOptMaxD, exact Hessian products.
+constexpr int kOptMaxN = 128;
+constexpr int kOptMaxD = 16;
+struct OptBatchArgs {
+  int32_t n, d, starts, first;  // starts l = 0 .. starts - 1 use stream first + l
+  uint32_t seed;
+  int32_t n_deltas, steps_per_delta, cg_max_iter;
+  const double* deltas;         // device [n_deltas]
+  double radius0, radius_min, radius_max, eta, cg_tol;
+  double* work;                 // [starts][stride]: the frame, then nine CG vectors of 2dn doubles
+  int64_t stride;               // doubles per start (opt_batch_stride)
+  double* mu;                   // [starts] exact FP64 coherence of each final frame
+};
+size_t opt_batch_stride(int64_t n, int64_t d);
+hipError_t launch_opt_batch(const OptBatchArgs& a, hipStream_t s);
+
 // Where trstmi_lse_grad leaves s (max |G|^2 bits) and log S in its workspace.
 void lse_grad_scalars(int64_t n, int64_t d, char* ws, const uint64_t** s_bits, const double** log_sum);
 

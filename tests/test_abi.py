@@ -279,6 +279,31 @@ def test_screen_tiles_argument_checks(L):
     assert L.trstmi_abi_version() >= 12
 
 
+def test_optimize_batched_argument_checks(L):
+    assert L.trstmi_optimize_batched_workspace_bytes(129, 4, 8) == 0
+    assert L.trstmi_optimize_batched_workspace_bytes(64, 17, 8) == 0
+    assert L.trstmi_optimize_batched_workspace_bytes(64, 4, 0) == 0
+    need = L.trstmi_optimize_batched_workspace_bytes(16, 4, 8)
+    assert need >= 8 * 10 * 2 * 4 * 16 * 8
+    dl = (ctypes.c_double * 2)(0.1, 0.01)
+    mu = ctypes.c_double()
+    best = ctypes.c_int32()
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    good = abi.OptParams(0, 8, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 0.0, 1, 0)
+    assert L.trstmi_optimize_batched(200, 4, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
+                                     None) == abi.E_UNSUPPORTED
+    fd = abi.OptParams(0, 8, 2, dl, 10, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 1e-6, 1, 0)
+    assert L.trstmi_optimize_batched(16, 4, ctypes.byref(fd), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
+                                     None) == abi.E_UNSUPPORTED
+    bad = abi.OptParams(0, 8, 2, dl, 0, 0.1, 1e-10, 1.0, 0.1, 1e-10, 0, 0.0, 1, 0)
+    assert L.trstmi_optimize_batched(16, 4, ctypes.byref(bad), p, ctypes.byref(mu), ctypes.byref(best), ws, need,
+                                     None) == abi.E_INVALID_ARG
+    assert L.trstmi_optimize_batched(16, 4, ctypes.byref(good), p, ctypes.byref(mu), ctypes.byref(best), ws,
+                                     need - 1, None) == abi.E_WORKSPACE
+    assert L.trstmi_abi_version() >= 13
+
+
 def test_optimize_argument_checks(L):
     need = L.trstmi_optimize_workspace_bytes(9, 3, 1)
     assert need > L.trstmi_tr_workspace_bytes(9, 3)

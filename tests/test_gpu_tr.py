@@ -167,27 +167,30 @@ def _table2():
     return rows
 
 
+@pytest.mark.parametrize("engine", ["threads", "batched"])
 @pytest.mark.parametrize("d,restarts", [(2, 8), (3, 18), (4, 32), (5, 50), (6, 72)])
-def test_optimize_reaches_table2(d, restarts):
+def test_optimize_reaches_table2(d, restarts, engine):
     """Alg. 2 on the GPU reaches the printed Table II coherence at N = d^2
-    (the Welch bound there, so optimal)."""
+    (the Welch bound there, so optimal), with host-driven steps and with
+    every start in one block of one launch."""
     n, printed = _table2()[d]
-    frame, mu, l = lib.optimize(n, d, restarts=restarts)
-    print(f"d={d} n={n} mu={mu!r} restart={l} printed={printed}", flush=True)
+    frame, mu, l = lib.optimize(n, d, restarts=restarts, engine=engine)
+    print(f"{engine} d={d} n={n} mu={mu!r} restart={l} printed={printed}", flush=True)
     assert oracle.welch_bound(n, d) - 1e-12 <= mu <= printed
     F = lib.frame_from_device(frame, n, d)
     assert abs(oracle.coherence(F) - mu) <= 1e-12
 
 
-@pytest.mark.parametrize("n,d,seed", [(9, 3, 0), (20, 4, 1), (50, 7, 2)])
-def test_optimize_matches_oracle_short_run(n, d, seed):
+@pytest.mark.parametrize("engine", ["threads", "batched"])
+@pytest.mark.parametrize("n,d,seed", [(9, 3, 0), (20, 4, 1), (50, 7, 2), (100, 12, 3)])
+def test_optimize_matches_oracle_short_run(n, d, seed, engine):
     """A short Alg. 2 run (three starts, two deltas, six steps each) against
     the oracle's: same starts, same accept decisions, so the same best start
     and a coherence and frame that differ by rounding only."""
     deltas = (1e-1, 1e-2)
     op = oracle.OptParams(restarts=3, deltas=deltas, steps_per_delta=6, seed=seed)
     mu_ref, l_ref, F_ref = oracle.optimize(n, d, op)
-    frame, mu, l = lib.optimize(n, d, restarts=3, deltas=deltas, steps_per_delta=6, seed=seed)
+    frame, mu, l = lib.optimize(n, d, restarts=3, deltas=deltas, steps_per_delta=6, seed=seed, engine=engine)
     F = lib.frame_from_device(frame, n, d)
     print(f"n={n} d={d} mu={mu!r} ref={mu_ref!r} restart={l} ref_restart={l_ref}", flush=True)
     assert l == l_ref
@@ -206,22 +209,45 @@ def test_optimize_concurrency_does_not_change_the_result():
     frame."""
     n, d = 16, 4
     kw = dict(restarts=6, deltas=(1e-1, 1e-2), steps_per_delta=10, seed=3)
-    f1, mu1, l1 = lib.optimize(n, d, concurrency=1, **kw)
-    f4, mu4, l4 = lib.optimize(n, d, concurrency=4, **kw)
-    f6, mu6, l6 = lib.optimize(n, d, concurrency=6, **kw)
+    f1, mu1, l1 = lib.optimize(n, d, concurrency=1, engine="threads", **kw)
+    f4, mu4, l4 = lib.optimize(n, d, concurrency=4, engine="threads", **kw)
+    f6, mu6, l6 = lib.optimize(n, d, concurrency=6, engine="threads", **kw)
     print(f"mu={mu1!r} {mu4!r} {mu6!r} restart={l1} {l4} {l6}", flush=True)
     assert mu1 == mu4 == mu6 and l1 == l4 == l6
     assert torch.equal(f1, f4) and torch.equal(f1, f6)
 
 
-def test_optimize_split_into_calls_equals_one_run():
+@pytest.mark.parametrize("engine", ["threads", "batched"])
+def test_optimize_split_into_calls_equals_one_run(engine):
     """Starts l = 0..5 in one call, or as l = 0..2 and l = 3..5 in two calls
     (first_restart): the best of the two calls is the one call's result."""
     n, d = 16, 4
-    kw = dict(deltas=(1e-1, 1e-2), steps_per_delta=10, seed=5, concurrency=3)
+    kw = dict(deltas=(1e-1, 1e-2), steps_per_delta=10, seed=5, concurrency=3, engine=engine)
     f, mu, l = lib.optimize(n, d, restarts=6, **kw)
     fa, mua, la = lib.optimize(n, d, restarts=3, first_restart=0, **kw)
     fb, mub, lb = lib.optimize(n, d, restarts=3, first_restart=3, **kw)
     best = (mua, la, fa) if mua <= mub else (mub, lb, fb)
     assert 0 <= la < 3 <= lb < 6
     assert best[0] == mu and best[1] == l and torch.equal(best[2], f)
+
+
+def test_optimize_batched_repeatable_and_equal_to_host_driven():
+    """The one-launch form gives the same bits on a second run, and the same
+    best start as the host-driven form with a coherence equal to rounding."""
+    n, d = 25, 5
+    kw = dict(restarts=12, deltas=(1e-1, 1e-2, 1e-3), steps_per_delta=15, seed=7)
+    fa, mua, la = lib.optimize(n, d, engine="batched", **kw)
+    fb, mub, lb = lib.optimize(n, d, engine="batched", **kw)
+    ft, mut, lt = lib.optimize(n, d, engine="threads", **kw)
+    print(f"batched mu={mua!r} restart={la}; threads mu={mut!r} restart={lt}", flush=True)
+    assert mua == mub and la == lb and torch.equal(fa, fb)
+    assert la == lt and abs(mua - mut) <= 1e-10
+
+
+def test_optimize_batched_table2_d7():
+    """d = 7 (N = 49, L = 98 starts in one launch) at the printed 0.3536 (the
+    Welch bound 1/sqrt(8))."""
+    n, printed = _table2()[7]
+    frame, mu, l = lib.optimize(n, 7, restarts=98, engine="batched")
+    print(f"d=7 mu={mu!r} restart={l}", flush=True)
+    assert oracle.welch_bound(n, 7) - 1e-12 <= mu <= printed
