@@ -9,7 +9,9 @@
 //
 // Work: a unit is 1, 2 or 4 candidates of one instance, processed by one
 // block of 4 wavefronts split into groups of `wpi` waves per candidate (the
-// per-instance tile choice).  The step kernel is launched with at most as
+// per-instance tile choice).  With one wave per candidate the phases below
+// are separated by wave-level synchronisation only, so the block's waves
+// run out of phase.  The step kernel is launched with at most as
 // many blocks as the device holds at once; block b takes units b, b + grid,
 // ... of the list (largest instances first), so no work counter is shared.
 // Per candidate the group
@@ -282,6 +284,22 @@ __global__ __launch_bounds__(kThreads) void k_batch_finalize(BatchArgs a) {
   }
 }
 
+// Synchronisation of a candidate's group of waves: with one wave per
+// candidate (wpi = 1) the group is the wave itself and its LDS region,
+// maxima and scratch are its own, so completing its LDS and memory
+// operations suffices and the block's waves drift out of phase (one wave's
+// FP64 generation overlaps another's matrix products); with more waves per
+// candidate, the whole block.  wpi is the same for every wave of a unit.
+__device__ __forceinline__ void group_sync(bool solo) {
+  if (solo) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int KSt>
 __device__ void screen_phase(const BInst& I, const float* L, const double* c64, int nbk, int nblk, int wg, int wpi,
                              bool work, uint32_t* blkmax, uint32_t* smax, unsigned long long* umax) {
@@ -310,7 +328,7 @@ __device__ void screen_phase(const BInst& I, const float* L, const double* c64, 
     }
     if (lane == 0) atomicMax(smax, wmax);
   }
-  __syncthreads();
+  group_sync(wpi == 1);
   if (work) {
     const uint32_t sb = *smax;
     if (sb >= kInfBits32) {
@@ -341,7 +359,7 @@ __device__ void screen_phase(const BInst& I, const float* L, const double* c64, 
       if (lane == 0) atomicMax(umax, (unsigned long long)best);
     }
   }
-  __syncthreads();
+  group_sync(wpi == 1);
 }
 
 // K = 2d <= 32: ceil(d / 2) steps of 4.
@@ -392,14 +410,25 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
     const int nblk = nbk * (nbk + 1) / 2;
 
     // 1. candidate (FP64 scratch + FP32 LDS copy; entries past 2d are never read)
-    if (tid < 4) {
-      smax[tid] = 0;
-      umax[tid] = 0;
+    const bool solo = wpi == 1;
+    if (solo) {
+      if (lane == 0) {
+        smax[g] = 0;
+        umax[g] = 0;
+      }
+    } else {
+      // a wave may still be in a previous one-wave unit, on its own part of
+      // the LDS regions that these groups share differently
+      __syncthreads();
+      if (tid < 4) {
+        smax[tid] = 0;
+        umax[tid] = 0;
+      }
     }
-    __syncthreads();
+    group_sync(solo);
     if (work) gen_dispatch(I, a.frames + I.frame_off, S0.radius, c, S0.step, c64, L, gtab, wg * 64 + lane, wpi * 64);
     __threadfence_block();
-    __syncthreads();
+    group_sync(solo);
 
     // 2. FP32 screen: block maxima and the candidate maximum;
     // 3. certified FP64 recheck of the pairs that can attain the maximum
@@ -407,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
 
     // 4. publish (read by the finalizing launch)
     if (work && wg == 0 && lane == 0) a.cand_max[(size_t)i * a.C + c] = umax[g];
-    __syncthreads();
+    group_sync(solo);
   }
 }
 
