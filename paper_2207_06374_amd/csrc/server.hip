@@ -7,11 +7,11 @@
 // its step (frame, radius, step counter and workspace live in its range of
 // the caller's pool).  Per step the engine launches each kernel of the
 // BF16-screen step once per group of admitted requests with the same d and
-// screen tile form (the
-// request is a grid dimension; each block reads its request's record; the
-// top-k and the selection, which do not depend on d, once for all of them),
-// so one launch sequence advances every request in flight, each with exactly
-// the arithmetic of its own single-search step.  After every `chunk` steps
+// screen tile form (the request is a grid dimension; each block reads its
+// request's record), so one launch sequence advances every request in
+// flight, each with exactly the arithmetic of its own single-search step;
+// the groups run on streams of their own (forked from the engine's stream
+// and joined back), so their launches overlap.  After every `chunk` steps
 // one small kernel gathers every request's flags, step and coherence for a
 // single read-back; finished requests leave the table, and the queue's head
 // requests are admitted into the free rows as long as their footprint
@@ -84,10 +84,14 @@ struct Running {
   int32_t row;
 };
 
+constexpr int kGroupStreams = 4;  // streams the groups' launches are spread over
+
 // Admitted requests of one d and one screen form, launched together.
 struct Group {
   int32_t d;
   int32_t form;
+  int32_t lane;               // group stream it runs on
+  double work;                // algorithmic screen flops per step (for the stream assignment)
   int32_t first, count;       // their rows in the list region
   trstmi::PerturbArgs shape_pa, shape_pr, shape_pc;  // launch shapes (largest n)
   int32_t ldk16;
@@ -112,6 +116,9 @@ struct trstmi_server {
 
   // engine thread only
   hipStream_t stream = nullptr;
+  hipStream_t gstream[kGroupStreams] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kGroupStreams] = {};
   char* tab_dev = nullptr;
   int32_t* list_dev = nullptr;
   trstmi::PollRecord* poll_dev = nullptr;
@@ -177,7 +184,23 @@ trstmi_status trstmi_server::rebuild() {
     // one step's recheck items of a request are few (its listed tiles); the
     // grid-stride loop covers them with fewer blocks per request in a group
     g.recheck_grid = std::min(g.recheck_grid, std::max(256, 8192 / g.count));
+    for (int32_t row : kv.second) {
+      const double n = (double)tab_host[row].pa.n;
+      g.work += 4.0 * g.d * n * (n - 1.0) * p.candidates;
+    }
     groups.push_back(g);
+  }
+  // largest groups first, each to the stream with the least work so far
+  std::vector<int> order(groups.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return groups[x].work > groups[y].work; });
+  double load[kGroupStreams] = {};
+  for (int i : order) {
+    int best = 0;
+    for (int q = 1; q < kGroupStreams; ++q)
+      if (load[q] < load[best]) best = q;
+    groups[i].lane = best;
+    load[best] += groups[i].work;
   }
   const int32_t nall = (int32_t)list_host.size();
   for (auto& kv : running) list_host.push_back(kv.first);  // every admitted row, for the poll
@@ -191,38 +214,40 @@ trstmi_status trstmi_server::rebuild() {
   return TRSTMI_OK;
 }
 
-// One step of every admitted request, in each request's own kernel order:
-// candidates and screen per group of d, the top-k of every request in one
-// launch (it does not depend on d), regeneration and recheck per group, the
-// selection of every request in one launch, the commit per group.
+// One chunk of steps of every admitted request.  Each group of requests runs
+// on one of the group streams (forked from the engine stream and joined back
+// to it), its steps in each request's own kernel order: candidates, screen,
+// top-k, regeneration, recheck, selection, commit.  Groups are independent,
+// so the small groups' launches overlap the large ones' instead of waiting
+// behind them.
 trstmi_status trstmi_server::launch_steps(int steps) {
   const size_t S = sizeof(trstmi::StepArgs);
-  const int32_t nrun = (int32_t)running.size();
-  auto all = [&](size_t member) {
-    return trstmi::TabRef{tab_dev + member, S, list_dev + (list_host.size() - nrun), nrun};
-  };
-  for (int i = 0; i < steps; ++i) {
-    hipError_t e = hipSuccess;
+  bool used[kGroupStreams] = {};
+  for (const Group& g : groups) used[g.lane] = true;
+  hipError_t e = hipEventRecord(fork_ev, stream);
+  for (int q = 0; q < kGroupStreams && e == hipSuccess; ++q)
+    if (used[q]) e = hipStreamWaitEvent(gstream[q], fork_ev, 0);
+  for (int i = 0; i < steps && e == hipSuccess; ++i)
     for (const Group& g : groups) {
-      const trstmi::TabRef pa{tab_dev + offsetof(trstmi::StepArgs, pa), S, list_dev + g.first, g.count};
-      const trstmi::TabRef gr{tab_dev + offsetof(trstmi::StepArgs, g), S, list_dev + g.first, g.count};
-      if (e == hipSuccess) e = trstmi::launch_perturb_tab(pa, g.shape_pa, p.candidates, stream);
-      if (e == hipSuccess) e = trstmi::launch_gram_bf16_tab(gr, g.ldk16, g.form, g.gram_grid, stream);
+      hipStream_t gs = gstream[g.lane];
+      auto ref = [&](size_t member) {
+        return trstmi::TabRef{tab_dev + member, S, list_dev + g.first, g.count};
+      };
+      if (e == hipSuccess) e = trstmi::launch_perturb_tab(ref(offsetof(trstmi::StepArgs, pa)), g.shape_pa, p.candidates, gs);
+      if (e == hipSuccess)
+        e = trstmi::launch_gram_bf16_tab(ref(offsetof(trstmi::StepArgs, g)), g.ldk16, g.form, g.gram_grid, gs);
+      if (e == hipSuccess) e = trstmi::launch_topk_tab(ref(offsetof(trstmi::StepArgs, ta)), gs);
+      if (e == hipSuccess) e = trstmi::launch_perturb_tab(ref(offsetof(trstmi::StepArgs, pr)), g.shape_pr, p.recheck_topk, gs);
+      if (e == hipSuccess) e = trstmi::launch_recheck_tab(ref(offsetof(trstmi::StepArgs, ra)), g.ldk16, g.recheck_grid, gs);
+      if (e == hipSuccess) e = trstmi::launch_select_tab(ref(offsetof(trstmi::StepArgs, sa)), gs);
+      if (e == hipSuccess) e = trstmi::launch_perturb_tab(ref(offsetof(trstmi::StepArgs, pc)), g.shape_pc, 1, gs);
     }
-    if (e == hipSuccess) e = trstmi::launch_topk_tab(all(offsetof(trstmi::StepArgs, ta)), stream);
-    for (const Group& g : groups) {
-      const trstmi::TabRef pr{tab_dev + offsetof(trstmi::StepArgs, pr), S, list_dev + g.first, g.count};
-      const trstmi::TabRef ra{tab_dev + offsetof(trstmi::StepArgs, ra), S, list_dev + g.first, g.count};
-      if (e == hipSuccess) e = trstmi::launch_perturb_tab(pr, g.shape_pr, p.recheck_topk, stream);
-      if (e == hipSuccess) e = trstmi::launch_recheck_tab(ra, g.ldk16, g.recheck_grid, stream);
+  for (int q = 0; q < kGroupStreams && e == hipSuccess; ++q)
+    if (used[q]) {
+      e = hipEventRecord(join_ev[q], gstream[q]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, join_ev[q], 0);
     }
-    if (e == hipSuccess) e = trstmi::launch_select_tab(all(offsetof(trstmi::StepArgs, sa)), stream);
-    for (const Group& g : groups) {
-      const trstmi::TabRef pc{tab_dev + offsetof(trstmi::StepArgs, pc), S, list_dev + g.first, g.count};
-      if (e == hipSuccess) e = trstmi::launch_perturb_tab(pc, g.shape_pc, 1, stream);
-    }
-    if (e != hipSuccess) return server_fail(TRSTMI_E_HIP, std::string("engine step: ") + hipGetErrorString(e));
-  }
+  if (e != hipSuccess) return server_fail(TRSTMI_E_HIP, std::string("engine step: ") + hipGetErrorString(e));
   return TRSTMI_OK;
 }
 
@@ -255,6 +280,11 @@ trstmi_status trstmi_server::run_chunk() {
 void trstmi_server::work() {
   hipError_t he = hipSetDevice(device);
   if (he == hipSuccess) he = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+  for (int q = 0; q < kGroupStreams && he == hipSuccess; ++q) {
+    he = hipStreamCreateWithFlags(&gstream[q], hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&join_ev[q], hipEventDisableTiming);
+  }
+  if (he == hipSuccess) he = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
   std::string engine_error = he == hipSuccess ? "" : std::string("engine stream: ") + hipGetErrorString(he);
   for (;;) {
     // admission: the queue's head while a row is free and its footprint fits
@@ -369,6 +399,11 @@ void trstmi_server::work() {
     if (!failed.empty() || !leaving.empty()) cv.notify_all();
   }
   drop_graph();
+  for (int q = 0; q < kGroupStreams; ++q) {
+    if (gstream[q]) (void)hipStreamDestroy(gstream[q]);
+    if (join_ev[q]) (void)hipEventDestroy(join_ev[q]);
+  }
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
