@@ -29,8 +29,11 @@
 // below the wave's rows and keep j > i; rows/columns past N are zero and
 // contribute 0.
 //
-// Narrow kernel (128 < 2d <= 256): one tile row (128 frame columns) per
-// segment, 32 rows per wave, the same pipelining with two accumulator sets.
+// Narrow kernel (any 2d <= 256; the form for 128 < 2d): one tile row (128
+// frame columns) per segment, 32 rows per wave, the same pipelining with two
+// accumulator sets.  For 2d > 160 a lean variant without the register
+// prefetch of the next tile and with fragments read per column block keeps
+// two blocks per CU (about 244 registers per lane instead of 300).
 //
 // Blocks are mapped XCD-aware: the dispatcher deals consecutive block ids to
 // the 8 XCDs in turn, so block b runs on XCD b mod 8; all segments of
@@ -258,6 +261,40 @@ __device__ __forceinline__ uint32_t tile_max_wave(const ARows<KS>& A, const uint
   return best;
 }
 
+// The same for the lean form (K >= 192): fragments read per column block
+// just before its products, no register double buffering; latency is
+// covered by the second wavefront on the SIMD that the saved registers allow.
+template <int KS>
+__device__ __forceinline__ uint32_t tile_max_wave_lean(const ARows<KS>& A, const uint16_t* Bs, bool diag) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  uint32_t best = 0;
+  uint32_t m[8];
+  for (int cb = diag ? 2 * w : 0; cb < T / 16; ++cb) {
+    v4f32 xR[2], xI[2];
+    mma_block<KS>(A, Bs, cb, xR, xI);
+    sq_mag(xR, xI, m);
+    if (diag) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = w * 32 + (q >> 2) * 16 + 4 * (lane >> 4) + (q & 3);
+        const int j = cb * 16 + (lane & 15);
+        if (i >= j) m[q] = 0u;
+      }
+    }
+    best = max_of(best, m);
+  }
+  return best;
+}
+
+// Column tile bj from global memory into LDS in one pass (zero past n).
+template <int KS>
+__device__ __forceinline__ void copy_cols(const uint16_t* base, int n, int bj, uint16_t* Bs) {
+  u32x4 pf[2 * KS];
+  fetch_cols<KS>(base, n, bj, pf);
+  store_cols<KS>(pf, Bs);
+}
+
 // Segment s of the row-segment enumeration: row block bi in order, each row
 // block split into ceil((nt - bi) / seg) runs of at most seg column tiles.
 __device__ __forceinline__ void seg_decode(int s, int nt, int seg, int& bi, int& bj0, int& bj1) {
@@ -274,8 +311,9 @@ __device__ __forceinline__ void seg_decode(int s, int nt, int seg, int& bi, int&
   bj1 = bj0 + seg < nt ? bj0 + seg : nt;
 }
 
-// Narrow kernel.  Two blocks per CU while the whole-K rows fit (2d <= 160);
-// one block with the full register file (VGPRs and AGPRs) beyond that.
+// Narrow kernel, two blocks per CU: double-buffered tiles and the register
+// prefetch while the whole-K rows leave room (2d <= 160), the lean variant
+// (one tile buffer, one copy pass per tile) beyond that.
 template <int KS>
 __device__ __forceinline__ void gram_bf16_narrow(const GramArgs& a, int b) {
   if (a.flags && (*a.flags & kFlagDone)) return;
@@ -298,31 +336,51 @@ __device__ __forceinline__ void gram_bf16_narrow(const GramArgs& a, int b) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
 
-  u32x4 pf[2 * KS];
-  fetch_cols<KS>(base, a.n, bj0, pf);
-  ARows<KS> A;
-  load_rows<KS>(base, a.ldk, a.n, bi, A);
-  store_cols<KS>(pf, Bs);
-  __syncthreads();
-  if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.n, bj0 + 1, pf);
-
   uint32_t cmax = 0;
   uint32_t tile_lane = 0;
-  for (int bj = bj0; bj < bj1; ++bj) {
-    const int buf = kNB == 2 ? (bj - bj0) & 1 : 0;
-    const uint32_t tmax = tile_max_wave<KS>(A, Bs + buf * kBuf, bj == bi);
-    cmax = tmax > cmax ? tmax : cmax;
-    if (a.tile_max) {
-      // lane k keeps the wave maximum of tile bj0 + k; stored after the
-      // segment, so no tile waits on a global store
-      const uint32_t wm = wave_max_u32_dpp(tmax);
-      if (lane == bj - bj0) tile_lane = wm;
+  ARows<KS> A;
+  if constexpr (KS >= 6) {
+    // lean form: two blocks per CU (the registers of one block's waves fit
+    // twice), each tile copied in one pass between two barriers
+    copy_cols<KS>(base, a.n, bj0, Bs);
+    load_rows<KS>(base, a.ldk, a.n, bi, A);
+    __syncthreads();
+    for (int bj = bj0; bj < bj1; ++bj) {
+      const uint32_t tmax = tile_max_wave_lean<KS>(A, Bs, bj == bi);
+      cmax = tmax > cmax ? tmax : cmax;
+      if (a.tile_max) {
+        const uint32_t wm = wave_max_u32_dpp(tmax);
+        if (lane == bj - bj0) tile_lane = wm;
+      }
+      if (bj + 1 < bj1) {
+        __syncthreads();  // every wave is done with this tile's columns
+        copy_cols<KS>(base, a.n, bj + 1, Bs);
+        __syncthreads();
+      }
     }
-    if (bj + 1 < bj1) {
-      if (kNB == 1) __syncthreads();  // every wave is done with this tile's columns
-      store_cols<KS>(pf, Bs + (kNB == 2 ? buf ^ 1 : 0) * kBuf);
-      __syncthreads();  // tile bj + 1 is in LDS; every wave is past tile bj
-      if (bj + 2 < bj1) fetch_cols<KS>(base, a.n, bj + 2, pf);
+  } else {
+    u32x4 pf[2 * KS];
+    fetch_cols<KS>(base, a.n, bj0, pf);
+    load_rows<KS>(base, a.ldk, a.n, bi, A);
+    store_cols<KS>(pf, Bs);
+    __syncthreads();
+    if (bj0 + 1 < bj1) fetch_cols<KS>(base, a.n, bj0 + 1, pf);
+    for (int bj = bj0; bj < bj1; ++bj) {
+      const int buf = kNB == 2 ? (bj - bj0) & 1 : 0;
+      const uint32_t tmax = tile_max_wave<KS>(A, Bs + buf * kBuf, bj == bi);
+      cmax = tmax > cmax ? tmax : cmax;
+      if (a.tile_max) {
+        // lane k keeps the wave maximum of tile bj0 + k; stored after the
+        // segment, so no tile waits on a global store
+        const uint32_t wm = wave_max_u32_dpp(tmax);
+        if (lane == bj - bj0) tile_lane = wm;
+      }
+      if (bj + 1 < bj1) {
+        if (kNB == 1) __syncthreads();  // every wave is done with this tile's columns
+        store_cols<KS>(pf, Bs + (kNB == 2 ? buf ^ 1 : 0) * kBuf);
+        __syncthreads();  // tile bj + 1 is in LDS; every wave is past tile bj
+        if (bj + 2 < bj1) fetch_cols<KS>(base, a.n, bj + 2, pf);
+      }
     }
   }
 
@@ -564,7 +622,7 @@ __device__ __forceinline__ void gram_bf16_wide(const GramArgs& a, int b) {
 }
 
 template <int KS>
-__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16(GramArgs a) {
+__global__ __launch_bounds__(256, 2) void k_gram_bf16(GramArgs a) {
   gram_bf16_narrow<KS>(a, blockIdx.x);
 }
 
@@ -576,7 +634,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf16_k(GramArgs a) {
 // Group launches: search blockIdx.y of the table (each record with its own
 // slots and nseg; blocks past a search's own grid return at once).
 template <int KS>
-__global__ __launch_bounds__(256, KS <= 5 ? 2 : 1) void k_gram_bf16_tab(TabRef t) {
+__global__ __launch_bounds__(256, 2) void k_gram_bf16_tab(TabRef t) {
   const GramArgs a = *(const GramArgs*)(t.base + (size_t)t.list[blockIdx.y] * t.stride);
   gram_bf16_narrow<KS>(a, blockIdx.x);
 }
