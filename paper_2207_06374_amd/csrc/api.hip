@@ -478,7 +478,7 @@ constexpr int kBatchMaxD = 16;
 constexpr int kBatchMaxC = 256;
 
 struct BatchLayout {
-  size_t hdr = 0, inst = 0, state = 0, units = 0, frames = 0, cand = 0, scratch = 0, total = 0;
+  size_t hdr = 0, tab = 0, inst = 0, state = 0, units = 0, frames = 0, cand = 0, scratch = 0, total = 0;
   int nunits = 0;
   int grid = 0;
   int64_t scratch_stride = 0;
@@ -537,6 +537,8 @@ trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_inst
   size_t o = 0;
   L.hdr = o;
   o = align256(o + 256);
+  L.tab = o;
+  o = align256(o + batch_tab_bytes());
   L.inst = o;
   o = align256(o + (size_t)p->count * batch_inst_bytes());
   L.state = o;
@@ -578,6 +580,7 @@ BatchArgs batch_args(const trstmi_batch_params* p, const BatchLayout& L, char* w
   b.scratch_stride = L.scratch_stride;
   b.count = p->count;
   b.done_instances = (int32_t*)(ws + L.hdr) + 2;
+  b.tab = ws + L.tab;
   b.tau = p->near_tie > 0 ? p->near_tie : 2e-12;
   b.grow = p->grow;
   b.shrink = p->shrink;

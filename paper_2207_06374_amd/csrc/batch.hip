@@ -379,17 +379,18 @@ __device__ __forceinline__ void screen_dispatch(const BInst& I, const float* L, 
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch_step(BatchArgs a) {
+// Four blocks per CU (the LDS and register use of one block fit four times):
+// the Gaussian tables are read from the workspace copy the init launch
+// filled (8 KiB, held in the CU's cache) rather than kept in LDS.
+__global__ __launch_bounds__(kThreads, 4) void k_batch_step(BatchArgs a) {
   __shared__ float lds[kLdsFloats];
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
   __shared__ uint32_t smax[4];
   __shared__ unsigned long long umax[4];
-  __shared__ GaussTab gtab;
+  const GaussTab& gtab = *(const GaussTab*)a.tab;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  fill_gauss_tab(&gtab);
-  __syncthreads();
 
   for (int u = blockIdx.x; u < a.nunits; u += gridDim.x) {
     const int2 unit = a.units[u];
@@ -447,6 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_init(BatchArgs a, int count,
   __shared__ GaussTab gtab;
   const int tid = threadIdx.x;
   fill_gauss_tab(&gtab);
+  if (blockIdx.x == 0) fill_gauss_tab((GaussTab*)a.tab);  // the step launches' copy
   __syncthreads();
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const BInst I = ((const BInst*)a.inst)[i];
@@ -563,5 +565,7 @@ void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed
 }
 
 int batch_lds_floats() { return kLdsFloats; }
+
+size_t batch_tab_bytes() { return sizeof(GaussTab); }
 
 }  // namespace trstmi

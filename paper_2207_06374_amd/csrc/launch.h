@@ -186,6 +186,7 @@ struct BatchArgs {
   double tau, grow, shrink, radius_min, radius_max;
   double* rep_mu;            // [count][C] or null
   int32_t* rep_best;         // [count] or null
+  void* tab;                 // the Gaussian draw tables (a GaussTab, filled by the init launch)
 };
 
 hipError_t launch_batch_step(const BatchArgs& a, int grid, hipStream_t s);
@@ -196,6 +197,7 @@ size_t batch_state_bytes();
 void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed, uint32_t stream_id,
                      int64_t frame_off, double target_mu, int64_t max_steps);
 int batch_lds_floats();
+size_t batch_tab_bytes();
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
