@@ -449,7 +449,17 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
     TRY_HIP(TIMED("perturb_recheck", s, launch_perturb(A.pr, L.k, s)), "perturb_recheck");
     TRY_HIP(TIMED("recheck", s, launch_recheck_pairs(A.ra, s)), "recheck");
     TRY_HIP(TIMED("select", s, launch_select(A.sa, s)), "select");
-    TRY_HIP(TIMED("commit", s, launch_perturb(A.pc, 1, s)), "commit");
+    CommitCopyArgs cc{};
+    cc.dec = (const Decision*)(ws + L.dec);
+    cc.slot_cand = (const int32_t*)(ws + L.rechecked);
+    cc.k = L.k;
+    cc.src = (const double*)(ws + L.recheck);
+    cc.src_slot_stride = L.n * L.ld;
+    cc.src_ld = L.ld;
+    cc.frame = st->frame;
+    cc.n = L.n;
+    cc.d = (int32_t)L.d;
+    TRY_HIP(TIMED("commit", s, launch_commit_copy(cc, s)), "commit");
     return TRSTMI_OK;
   }
   const PerturbArgs pa = candidate_args(p, st, L, ws, z);
@@ -464,7 +474,19 @@ trstmi_status enqueue_step(const trstmi_params* p, const trstmi_state* st, char*
   sa.is_f32 = f32 ? 1 : 0;
   sa.rep_cand_mu = rep ? rep->cand_mu : nullptr;
   TRY_HIP(TIMED("select", s, launch_select(sa, s)), "select");
-  TRY_HIP(TIMED("commit", s, launch_perturb(commit_args(p, st, L, ws, z), 1, s)), "commit");
+  if (f32) {
+    TRY_HIP(TIMED("commit", s, launch_perturb(commit_args(p, st, L, ws, z), 1, s)), "commit");
+  } else {
+    CommitCopyArgs cc{};
+    cc.dec = (const Decision*)(ws + L.dec);
+    cc.src = (const double*)(ws + L.cand);
+    cc.src_slot_stride = L.n * L.ldc;
+    cc.src_ld = L.ldc;
+    cc.frame = st->frame;
+    cc.n = L.n;
+    cc.d = (int32_t)L.d;
+    TRY_HIP(TIMED("commit", s, launch_commit_copy(cc, s)), "commit");
+  }
   return TRSTMI_OK;
 }
 

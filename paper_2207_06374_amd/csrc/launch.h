@@ -200,6 +200,22 @@ int batch_lds_floats();
 size_t batch_tab_bytes();
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);
+
+// Commit by copy: when dec->commit is set, the accepted candidate's FP64
+// columns, already written earlier in the step (the FP64 candidates, or the
+// FP64 copies of the rechecked ones), are copied into the frame.
+struct CommitCopyArgs {
+  const Decision* dec;
+  const int32_t* slot_cand;  // slot -> candidate (k entries), or null: slot = candidate
+  int32_t k;
+  const double* src;         // slot s at src + s * src_slot_stride, column stride src_ld
+  int64_t src_slot_stride;
+  int32_t src_ld;
+  double* frame;             // column stride 2d
+  int64_t n;
+  int32_t d;
+};
+hipError_t launch_commit_copy(const CommitCopyArgs& a, hipStream_t s);
 hipError_t launch_gram_f64(const GramArgs& a, int slots, hipStream_t s);
 // After launch_gram_f64 on one frame (slot 0): the first pair j < k in the
 // order j * n + k whose |G|^2 has the maximum's bits, into *pair (scratch),

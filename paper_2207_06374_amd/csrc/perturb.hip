@@ -200,6 +200,30 @@ __global__ __launch_bounds__(kThreads) void k_perturb_tab(TabRef t) {
   perturb_body<LPC, Q, OUT, DRAW, FULL>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
+// Commit by copy.  Every output kind of a candidate comes from the same
+// column split for a given d, so the FP64 columns written earlier in the step
+// have the bits the regeneration would write; copying them replaces drawing
+// the accepted candidate again.
+__global__ __launch_bounds__(kThreads) void k_commit_copy(CommitCopyArgs a) {
+  if (a.dec->commit != 1) return;
+  const int best = a.dec->best;
+  int slot = best;
+  if (a.slot_cand) {
+    slot = -1;
+    for (int s = 0; s < a.k; ++s)
+      if (a.slot_cand[s] == best) slot = s;
+    if (slot < 0) return;  // the selection only picks listed candidates
+  }
+  const double* src = a.src + (size_t)slot * a.src_slot_stride;
+  const int h = a.d;  // double2 per column
+  const int64_t total = a.n * h;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThreads) {
+    const int64_t col = e / h;
+    const int m = (int)(e - col * h);
+    ((double2*)(a.frame + (size_t)col * 2 * a.d))[m] = ((const double2*)(src + (size_t)col * a.src_ld))[m];
+  }
+}
+
 // FP64 frame -> FP32 copy with zero padding (no renormalisation).
 __global__ __launch_bounds__(kThreads) void k_convert_f32(const double* frame, int64_t n, int d, float* out,
                                                           int out_ld, uint64_t* zero_max) {
@@ -290,6 +314,14 @@ hipError_t launch_perturb_any(const PerturbArgs& a, int slots, hipStream_t s, co
   }
 }
 }  // namespace
+
+hipError_t launch_commit_copy(const CommitCopyArgs& a, hipStream_t s) {
+  const int64_t total = a.n * a.d;
+  int64_t g = (total + kThreads - 1) / kThreads;
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_commit_copy, dim3((int)(g > 0 ? g : 1)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s) {
   return launch_perturb_any(a, slots, s, nullptr);
