@@ -943,7 +943,6 @@ trstmi_status trstmi_lse_hvp(int64_t n, int64_t d, const double* frame, const do
   h.raw = frame;
   h.v = v;
   h.s_bits = mx;
-  h.log_sum = log_sum;
   h.inv_delta = 1.0 / delta;
   h.out = hv;
   TRY_HIP(TIMED("lse_hv", stream, launch_lse_hv(h, stream)), "lse_hv");

@@ -251,7 +251,6 @@ struct HvArgs {
   const double* raw;        // the frame Y (column stride 2d)
   const double* v;          // the direction V (same layout)
   const uint64_t* s_bits;   // max |G|^2 bits of Y
-  const double* log_sum;    // log of sum exp((x - s) / delta) over j < k
   double inv_delta;
   double* out;              // Hv (same layout)
   // scratch, laid out by hv_layout
@@ -259,9 +258,10 @@ struct HvArgs {
   double* dphi;             // their derivative along V
   double* r;                // [n] column norms
   double* dr;               // [n] their derivative
-  double* partial;          // [chunks][n][2][2d] D and E partial sums
-  double* sigpart;          // [blocks] partial sums of sigma
-  double* sigma;            // [1]
+  double* partial;          // [chunks][n][4][2d] partial sums of U Re B, U Im B, dU Re B + U Re B1, dU Im B + U Im B1
+  double* sigpart;          // [blocks] partial sums of sum e dx (e = exp((x - s) / delta), unnormalised)
+  double* esumpart;         // [blocks] partial sums of e
+  double* sigma;            // [2]: sigma and 1 / S (S = sum of e over j < k)
   int32_t n, d;
 };
 size_t hv_scratch_bytes(int64_t n, int64_t d);

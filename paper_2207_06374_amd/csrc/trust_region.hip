@@ -134,7 +134,8 @@ trstmi_status tr_step_impl(int64_t n, int64_t d, double* frame, const trstmi_tr_
   HvArgs hv{};
   if (exact) {
     hv_layout(hv, q + 256 + 3 * kDotBlocks * 8, n, d);
-    lse_grad_scalars(n, d, ws, &hv.s_bits, &hv.log_sum);
+    const double* unused_log_sum = nullptr;  // the product normalises with its own sum
+    lse_grad_scalars(n, d, ws, &hv.s_bits, &unused_log_sum);
     hv.raw = frame;
     hv.inv_delta = 1.0 / tp->delta;
   }

@@ -233,7 +233,11 @@ def test_optimize_split_into_calls_equals_one_run(engine):
 
 def test_optimize_batched_repeatable_and_equal_to_host_driven():
     """The one-launch form gives the same bits on a second run, and the same
-    best start as the host-driven form with a coherence equal to rounding."""
+    best coherence as the host-driven form to rounding.  Several starts end
+    within about 1e-10 of the optimum (here the Welch bound) after these 45
+    steps, an amount that the two forms' different rounding moves, so they
+    may name different best starts: each form's pick must then be within
+    1e-9 of the best in the other form too."""
     n, d = 25, 5
     kw = dict(restarts=12, deltas=(1e-1, 1e-2, 1e-3), steps_per_delta=15, seed=7)
     fa, mua, la = lib.optimize(n, d, engine="batched", **kw)
@@ -241,7 +245,13 @@ def test_optimize_batched_repeatable_and_equal_to_host_driven():
     ft, mut, lt = lib.optimize(n, d, engine="threads", **kw)
     print(f"batched mu={mua!r} restart={la}; threads mu={mut!r} restart={lt}", flush=True)
     assert mua == mub and la == lb and torch.equal(fa, fb)
-    assert la == lt and abs(mua - mut) <= 1e-10
+    assert abs(mua - mut) <= 1e-10
+    if la != lt:
+        one = dict(kw, restarts=1)
+        _, mu_la_t, _ = lib.optimize(n, d, engine="threads", **dict(one, first_restart=la))
+        _, mu_lt_b, _ = lib.optimize(n, d, engine="batched", **dict(one, first_restart=lt))
+        print(f"start {la} host-driven mu={mu_la_t!r}; start {lt} batched mu={mu_lt_b!r}", flush=True)
+        assert abs(mu_la_t - mut) <= 1e-9 and abs(mu_lt_b - mua) <= 1e-9
 
 
 def test_optimize_batched_table2_d7():
