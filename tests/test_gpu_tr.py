@@ -93,7 +93,10 @@ def test_hessian_vector_product_matches_oracle(n, d, delta):
     s_ref, F_ref = oracle.smooth_max(Y, delta)
     err = np.max(np.abs(H - ref)) / np.max(np.abs(ref))
     print(f"n={n} d={d} delta={delta} rel={err:.3e}", flush=True)
-    assert err <= 1e-11
+    # both sides normalise the weights with their own sum, so what remains is
+    # the rounding of |G|^2 (about 2^-52 relative) moving each weight by
+    # about 2^-52 / delta: a few 1e-14 at delta = 1e-3
+    assert err <= 1e-12
     o = out.cpu().numpy()
     assert abs(o[0] - s_ref) <= 1e-14 and abs(o[1] - F_ref) <= 1e-13
     # repeatable bits
@@ -113,7 +116,7 @@ def test_hessian_vector_product_full_size():
     ref = oracle.smooth_max_hess_vec(Y, V, delta)
     err = np.max(np.abs(H - ref)) / np.max(np.abs(ref))
     print(f"n={n} d={d} rel={err:.3e}", flush=True)
-    assert err <= 1e-11
+    assert err <= 1e-12
 
 
 def test_hessian_vector_product_invalid_column_is_nan():
