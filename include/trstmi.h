@@ -263,7 +263,9 @@ size_t trstmi_lse_hvp_workspace_bytes(int64_t n, int64_t d);
  * derivative of F along u and v.  Forward differentiation of the gradient's
  * chain (column norms, Gram, |G|^2, the weights exp((x - s)/delta) / S, the
  * product Phi (W o G) and the projection through the normalisation), in FP64
- * with a fixed summation order (repeatable bits).  A zero or non-finite
+ * with a fixed summation order (repeatable bits); S is summed in the same
+ * pass from the same x as the weights, so they add up to one.  The
+ * workspace size depends on n and d only.  A zero or non-finite
  * column gives out = (+inf, +inf) and a NaN product.  Requires n >= 2,
  * 1 <= d <= 64 (TRSTMI_E_UNSUPPORTED above), delta finite and > 0; workspace
  * of trstmi_lse_hvp_workspace_bytes(n, d) bytes.  Stream-ordered.
