@@ -252,6 +252,7 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     frame, N=4096, d=64): FP64 normalisation, one FP64 MFMA pass over the
     upper-triangle tiles (block maxima and rescaled sums) and the fixed-order
     finish; then the value with its gradient with respect to the frame."""
+    import numpy as np
     s = lib.Solver(wl.n, wl.d, candidates=8, mode="fp64", seed=wl.seed, stream_id=wl.stream_id)
     s.init_haar()
     frame = s.state.frame
@@ -290,8 +291,28 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
     lib.timing_enable(False)
     ms, cnt = lib.timing_read("lse_grad")
     grad_us = 1e3 * ms / cnt
-    # trust-region steps (Steihaug CG with finite-difference Hessian products)
-    # from the same frame; each CG iteration costs two value-and-gradient calls
+    # exact Hessian-vector product along a seeded direction (one more tile
+    # pass on FP64 MFMA after the value)
+    V = lib.frame_to_device(np.random.default_rng(1).standard_normal((wl.d, wl.n))
+                            + 1j * np.random.default_rng(2).standard_normal((wl.d, wl.n)))
+    hv = torch.empty_like(frame)
+    hws = torch.empty(lib.lse_hvp_workspace_bytes(wl.n, wl.d), dtype=torch.uint8, device=frame.device)
+    for _ in range(2):
+        lib.lse_hvp(frame, V, wl.n, wl.d, delta, out, hv, hws)
+    torch.cuda.synchronize()
+    lib.timing_reset()
+    lib.timing_enable(True)
+    t6 = time.perf_counter()
+    for _ in range(evals):
+        lib.lse_hvp(frame, V, wl.n, wl.d, delta, out, hv, hws)
+    torch.cuda.synchronize()
+    t7 = time.perf_counter()
+    lib.timing_enable(False)
+    ms, cnt = lib.timing_read("lse_hv")
+    hv_us = 1e3 * ms / cnt
+    hv_flop = 48 * wl.d * wl.n * (wl.n - 1)  # per ordered pair: six real products of length 2d forward, six back
+    # trust-region steps (Steihaug CG with exact Hessian products) from the
+    # same frame; each CG iteration costs one Hessian-vector product
     Y = frame.clone()
     tws = torch.empty(lib.tr_workspace_bytes(wl.n, wl.d), dtype=torch.uint8, device=frame.device)
     radius, tr_reps = 0.05, []
@@ -321,6 +342,10 @@ def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
         "grad_issued_flop": grad_issued,
         "grad_pass_frac_fp64_peak": grad_alg / (grad_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
         "grad_pass_issued_frac_fp64_peak": grad_issued / (grad_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
+        "hvp_ms_per_call": 1e3 * (t7 - t6) / evals,
+        "hv_pass_us": hv_us,
+        "hv_flop": hv_flop,
+        "hv_pass_frac_fp64_peak": hv_flop / (hv_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"],
         "tr_steps": len(tr_reps),
         "tr_ms_per_step": 1e3 * (t5 - t4) / len(tr_reps),
         "tr_ms_per_gradient_call": 1e3 * (t5 - t4) / grad_calls,
