@@ -139,14 +139,17 @@ __device__ __forceinline__ void put_rows(const double pre[kPreH], int ldp, doubl
 // Forward product(s) of one 16 x 16 pair block: rows j of the tile (A
 // operand: lane l holds row l % 16 at real index 4 ks + l / 16), columns
 // kcol of the k tile (B operand).  Q: 0 Re G, 1 Im G, 2 Re dG, 3 Im dG.
-template <int Q>
+template <int Q, int LDP>
 __device__ __forceinline__ v4f64 fwd_block(const double* Uj, const double* dUj, const double* Uk, const double* dUk,
-                                           int ldp, int kcol, int K4) {
+                                           int kcol) {
+  constexpr int ldp = LDP;
   const int lane = threadIdx.x & 63;
   const int l16 = lane & 15, kl = lane >> 4;
   const bool odd = kl & 1;
   v4f64 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int ks = 0; ks < K4 / 4; ++ks) {
+  // the whole staged width (entries past 2d are zero), a compile-time count
+#pragma unroll
+  for (int ks = 0; ks < (LDP - 1) / 4; ++ks) {
     const int m = 4 * ks + kl;
     const double au = Uj[l16 * ldp + m];
     if constexpr (Q == 0) {
@@ -180,7 +183,6 @@ __global__ __launch_bounds__(kThreadsH, 1) void k_lse_hv(HvArgs a) {
   __shared__ double red[2 * (kThreadsH / 64)];
   const int kb = blockIdx.x, ch = blockIdx.y, nch = gridDim.y;
   const int n = a.n, L = 2 * a.d;
-  const int K4 = (L + 3) & ~3;
   const int njt = (n + kTJ - 1) / kTJ;
   const int jt0 = (int)(((int64_t)ch * njt) / nch), jt1 = (int)(((int64_t)(ch + 1) * njt) / nch);
   const int tid = threadIdx.x;
@@ -213,13 +215,13 @@ __global__ __launch_bounds__(kThreadsH, 1) void k_lse_hv(HvArgs a) {
       const int kcol = 16 * cbf + l16;
       v4f64 r;
       if (qf == 0)
-        r = fwd_block<0>(Uj, dUj, Uk, dUk, LDP, kcol, K4);
+        r = fwd_block<0, LDP>(Uj, dUj, Uk, dUk, kcol);
       else if (qf == 1)
-        r = fwd_block<1>(Uj, dUj, Uk, dUk, LDP, kcol, K4);
+        r = fwd_block<1, LDP>(Uj, dUj, Uk, dUk, kcol);
       else if (qf == 2)
-        r = fwd_block<2>(Uj, dUj, Uk, dUk, LDP, kcol, K4);
+        r = fwd_block<2, LDP>(Uj, dUj, Uk, dUk, kcol);
       else
-        r = fwd_block<3>(Uj, dUj, Uk, dUk, LDP, kcol, K4);
+        r = fwd_block<3, LDP>(Uj, dUj, Uk, dUk, kcol);
 #pragma unroll
       for (int v = 0; v < 4; ++v) F[qf][(4 * v + kl) * kFS + kcol] = r[v];
     }
