@@ -101,7 +101,6 @@ __global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
   const int cg = w & 3;   // column group: columns 16 cg .. 16 cg + 15 of tile kb
   const int rh = w >> 2;  // row half: rows 32 rh .. 32 rh + 31 of tile jb
   constexpr int ldp = LDP;
-  const int K4 = (2 * a.d + 3) & ~3;
   const uint64_t sb = *a.s_bits;
   const bool valid = sb < kInfBits64;
   const double s = __longlong_as_double((int64_t)sb);
@@ -134,7 +133,9 @@ __global__ __launch_bounds__(kThreadsG, 1) void k_lse_grad(GradArgs a) {
       R[jl] = v4f64{0.0, 0.0, 0.0, 0.0};
       I[jl] = v4f64{0.0, 0.0, 0.0, 0.0};
     }
-    for (int kk = 0; kk < K4 / 4; ++kk) {
+    // the whole staged width (entries past 2d are zero), a compile-time count
+#pragma unroll
+    for (int kk = 0; kk < (LDP - 1) / 4; ++kk) {
       const int k = 4 * kk + kl;
       const double bu = Uk[kcol * ldp + k];
       const double x = Uk[kcol * ldp + (k ^ 1)];
