@@ -534,7 +534,7 @@ def copy_calibration(torch, mib):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--other-modes", default="fp64,fp32",
                     help="also time these plain forms on the same workload (comma list, '' for none)")
