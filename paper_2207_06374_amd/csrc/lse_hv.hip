@@ -42,8 +42,8 @@
 //     outputs P1 = U_j Re B, P2 = U_j Im B, Q1 = dU_j Re B + U_j Re B1,
 //     Q2 = dU_j Im B + U_j Im B1 for both column blocks, accumulated over all
 //     of the block's tiles in registers.
-// Each block writes P1, P2, Q1, Q2 of its columns and its sigma share to
-// slots of its own; the finishing kernels add them in a fixed order (so
+// Each block writes P1, P2, Q1, Q2 of its columns and its shares of S and
+// sigma to slots of its own; the finishing kernels add them in a fixed order (so
 // repeated calls give the same bits) and combine D_re[i] = P1[2i] - P2[2i+1],
 // D_im[i] = P2[2i] + P1[2i+1] (E likewise from Q1, Q2).
 
