@@ -436,6 +436,26 @@ def run_serving(lib, count, max_steps, pool_gib, slots, chunk=32):
     return stats
 
 
+def serving_in_child(args):
+    """The serving leg in a child process of its own (the same script with
+    --serving-child): the engine's native thread and its device state live
+    and end there, and a failure of that process is reported in the result
+    instead of ending the benchmark."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serving-child",
+           "--serving-requests", str(args.serving_requests), "--serving-max-steps", str(args.serving_max_steps),
+           "--serving-pool-gib", str(args.serving_pool_gib), "--serving-slots", str(args.serving_slots)]
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=1800)
+    except subprocess.TimeoutExpired:
+        return {"requests": args.serving_requests, "error": "the serving leg's process did not finish in 1800 s"}
+    lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"requests": args.serving_requests,
+                "error": f"the serving leg's process exited with status {r.returncode}"}
+    return json.loads(lines[-1])
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -561,6 +581,9 @@ def main():
     ap.add_argument("--serving-max-steps", type=int, default=20000)
     ap.add_argument("--serving-pool-gib", type=float, default=1.0)
     ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-child", action="store_true",
+                    help="only run the serving leg and print its statistics as one JSON line (the bench runs the "
+                         "serving leg this way in a child process of its own)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -580,6 +603,12 @@ def main():
 
     import inputs
     import paper_2207_06374_amd as lib
+
+    if args.serving_child:
+        stats = run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib,
+                            args.serving_slots)
+        print(json.dumps(stats), flush=True)
+        return
 
     wl = inputs.LARGE
     main_res = run_mode(lib, torch, wl, "bf16", args.steps, args.warmup, min_warm_s=args.min_warmup_s)
@@ -610,8 +639,7 @@ def main():
     table2 = run_table2(lib, [int(x) for x in args.table2_dims.split(",") if x]) if args.table2_dims else None
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
-    serving = (run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib,
-                           args.serving_slots) if args.serving_requests > 0 else None)
+    serving = serving_in_child(args) if args.serving_requests > 0 else None
 
     g = main_res["gram"]
     traffic = load_traffic("gram_bf16")
