@@ -417,26 +417,28 @@ def run_table2(lib, dims):
     return rows
 
 
-def run_serving(lib, count, max_steps, pool_gib, slots, chunk=32):
+def run_serving(lib, count, max_steps, pool_gib, slots, target_factor=1.10, warmup=0, chunk=32):
     """The serving workload: Poisson arrivals (mean gap 5 ms), d in
-    {8, 16, 32, 64, 128}, N uniform in [2d, 8d], each solved to 1.10 x Welch or
-    max_steps with BF16-screened / FP64-verified steps, admitted by device
-    footprint into a capped pool and advanced by the continuous-batching
-    engine."""
+    {8, 16, 32, 64, 128}, N uniform in [2d, 8d], each solved to
+    target_factor x Welch or max_steps with BF16-screened / FP64-verified
+    steps, admitted by device footprint into a capped pool and advanced by the
+    continuous-batching engine."""
     import inputs
     from paper_2207_06374_amd import serve
     reqs = [serve.Request(id=r["id"], arrival=r["arrival"], n=r["n"], d=r["d"], seed=r["seed"], max_steps=max_steps)
             for r in inputs.serving_requests(count, seed=1)]
-    srv = serve.Server(pool_bytes=int(pool_gib * 2 ** 30), max_active=slots, chunk=chunk, candidates=64, mode="bf16")
-    stats = srv.run(reqs, progress=log)
+    srv = serve.Server(pool_bytes=int(pool_gib * 2 ** 30), max_active=slots, chunk=chunk, candidates=64, mode="bf16",
+                       target_factor=target_factor)
+    stats = srv.run(reqs, progress=log, warmup=warmup)
     srv.close()
-    stats["workload"] = (f"{count} requests, Poisson arrivals mean gap 5 ms (200 req/s), d in {{8,16,32,64,128}}, "
-                         f"N in [2d, 8d], target 1.10 x Welch or {max_steps} steps, 64 candidates, BF16 screen + "
+    stats["target_factor"] = target_factor
+    stats["workload"] = (f"{count} requests ({warmup} warm-up), Poisson arrivals mean gap 5 ms (200 req/s), d in {{8,16,32,64,128}}, "
+                         f"N in [2d, 8d], target {target_factor} x Welch or {max_steps} steps, 64 candidates, BF16 screen + "
                          f"top-8 FP64 recheck, pool {pool_gib} GiB, engine with {slots} rows and {chunk}-step chunks")
     return stats
 
 
-def serving_in_child(args):
+def serving_in_child(args, target_factor):
     """The serving leg in a child process of its own (the same script with
     --serving-child): the engine's native thread and its device state live
     and end there, and a failure of that process is reported in the result
@@ -444,7 +446,8 @@ def serving_in_child(args):
     import subprocess
     cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serving-child",
            "--serving-requests", str(args.serving_requests), "--serving-max-steps", str(args.serving_max_steps),
-           "--serving-pool-gib", str(args.serving_pool_gib), "--serving-slots", str(args.serving_slots)]
+           "--serving-pool-gib", str(args.serving_pool_gib), "--serving-slots", str(args.serving_slots),
+           "--serving-target-factor", repr(target_factor), "--serving-warmup", str(args.serving_warmup)]
     try:
         r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=1800)
     except subprocess.TimeoutExpired:
@@ -581,6 +584,13 @@ def main():
     ap.add_argument("--serving-max-steps", type=int, default=20000)
     ap.add_argument("--serving-pool-gib", type=float, default=1.0)
     ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-target-factor", type=float, default=1.10,
+                    help="each request stops at this multiple of its Welch bound (or the step cap)")
+    ap.add_argument("--serving-warmup", type=int, default=0,
+                    help="the first arrivals left out of the serving latency statistics (throughput counts them)")
+    ap.add_argument("--serving-reachable-factor", type=float, default=2.6,
+                    help="a second serving run with this looser target, which part of the stream reaches within "
+                         "the cap, so that time-to-target percentiles are measured (0: skip)")
     ap.add_argument("--serving-child", action="store_true",
                     help="only run the serving leg and print its statistics as one JSON line (the bench runs the "
                          "serving leg this way in a child process of its own)")
@@ -606,7 +616,7 @@ def main():
 
     if args.serving_child:
         stats = run_serving(lib, args.serving_requests, args.serving_max_steps, args.serving_pool_gib,
-                            args.serving_slots)
+                            args.serving_slots, args.serving_target_factor, args.serving_warmup)
         print(json.dumps(stats), flush=True)
         return
 
@@ -639,7 +649,9 @@ def main():
     table2 = run_table2(lib, [int(x) for x in args.table2_dims.split(",") if x]) if args.table2_dims else None
     batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
     log("batched done")
-    serving = serving_in_child(args) if args.serving_requests > 0 else None
+    serving = serving_in_child(args, args.serving_target_factor) if args.serving_requests > 0 else None
+    serving_reachable = (serving_in_child(args, args.serving_reachable_factor)
+                         if args.serving_requests > 0 and args.serving_reachable_factor > 0 else None)
 
     g = main_res["gram"]
     traffic = load_traffic("gram_bf16")
@@ -683,6 +695,7 @@ def main():
         "equal_mu": equal,
         "batched": batched,
         "serving": serving,
+        "serving_reachable_target": serving_reachable,
         "smooth_max": smooth,
         "optimiser_table2": table2,
         "miso_codebook": miso,

@@ -137,9 +137,10 @@ class Server:
         _abi.check(_abi.lib().trstmi_server_get_stats(self.handle, ctypes.byref(s)), "trstmi_server_get_stats")
         return s
 
-    def run(self, requests: List[Request], progress=None, progress_every_s=10.0):
+    def run(self, requests: List[Request], progress=None, progress_every_s=10.0, warmup=0):
         """Serve `requests`, each submitted at its arrival time (relative to
-        now).  Returns a dict of statistics; per-request results are written
+        now).  Returns a dict of statistics (the first `warmup` arrivals are
+        left out of the latency statistics); per-request results are written
         into the requests.  `progress(text)`, if given, is called about every
         progress_every_s while requests are outstanding."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
@@ -174,40 +175,52 @@ class Server:
                 r.finish = r.admit + out.run_s
         wall = time.perf_counter() - t0
         s = self.stats()
-        return summarize(reqs, wall, self.candidates, s.pool_peak, s.pool_capacity)
+        return summarize(reqs, wall, self.candidates, s.pool_peak, s.pool_capacity, warmup)
 
 
 def _pct(values, q):
-    return float(np.percentile(np.array(values), q)) if len(values) else math.nan
+    return float(np.percentile(np.array(values), q)) if len(values) else None
 
 
-def summarize(reqs, wall, candidates, peak_bytes, cap_bytes):
+def summarize(reqs, wall, candidates, peak_bytes, cap_bytes, warmup=0):
     """Latency = finish - arrival: over every finished request (time to the
     target or to the step cap) and over those that reached the target (time
     to target); queue = admission - arrival; evals = steps x candidates, and
-    the screen's algorithmic flops 8 d N (N - 1) / 2 per eval."""
-    done = [r for r in reqs if r.status == "done"]
+    the screen's algorithmic flops 8 d N (N - 1) / 2 per eval.  The first
+    `warmup` requests by arrival count towards throughput but not towards the
+    latency, queue and target statistics.  An empty statistic is None."""
+    done_all = [r for r in reqs if r.status == "done"]
+    measured = set(id(r) for r in sorted(reqs, key=lambda r: (r.arrival, r.id))[warmup:])
+    done = [r for r in done_all if id(r) in measured]
     reached = [r for r in done if r.reached]
-    evals = sum(r.steps * candidates for r in done)
-    flops = sum(r.steps * candidates * 4.0 * r.d * r.n * (r.n - 1) for r in done)
+    evals = sum(r.steps * candidates for r in done_all)
+    flops = sum(r.steps * candidates * 4.0 * r.d * r.n * (r.n - 1) for r in done_all)
     queue = [r.admit - r.arrival for r in done]
+    by_d = {}
+    for r in done:
+        e = by_d.setdefault(str(r.d), {"done": 0, "reached_target": 0})
+        e["done"] += 1
+        e["reached_target"] += int(r.reached)
     return {
         "requests": len(reqs),
-        "done": len(done),
+        "warmup_requests": int(warmup),
+        "done": len(done_all),
         "rejected": sum(r.status == "rejected" for r in reqs),
         "errors": sum(r.status == "error" for r in reqs),
+        "measured": len(done),
         "reached_target": len(reached),
+        "reached_by_d": by_d,
         "p50_latency_s": _pct([r.latency for r in done], 50),
         "p99_latency_s": _pct([r.latency for r in done], 99),
         "p50_time_to_target_s": _pct([r.latency for r in reached], 50),
         "p99_time_to_target_s": _pct([r.latency for r in reached], 99),
-        "mean_queue_s": float(np.mean(queue)) if done else math.nan,
+        "mean_queue_s": float(np.mean(queue)) if done else None,
         "p50_queue_s": _pct(queue, 50),
         "p99_queue_s": _pct(queue, 99),
-        "evals_per_s": evals / wall if wall > 0 else math.nan,
-        "screen_tflops": flops / wall / 1e12 if wall > 0 else math.nan,
+        "evals_per_s": evals / wall if wall > 0 else None,
+        "screen_tflops": flops / wall / 1e12 if wall > 0 else None,
         "wall_s": wall,
-        "median_mu_over_welch": float(np.median([r.mu / welch_bound(r.n, r.d) for r in done])) if done else math.nan,
+        "median_mu_over_welch": float(np.median([r.mu / welch_bound(r.n, r.d) for r in done])) if done else None,
         "pool_peak_bytes": int(peak_bytes),
         "pool_cap_bytes": int(cap_bytes),
         "first_error": next((r.error for r in reqs if r.status == "error"), ""),

@@ -62,3 +62,27 @@ def test_footprint_and_server_argument_checks_without_device():
     assert L.trstmi_server_submit(None, None, None) == _abi.E_INVALID_ARG
     assert L.trstmi_server_destroy(None) == _abi.OK
     assert L.trstmi_server_forget(None, 0) == _abi.E_INVALID_ARG
+
+
+def test_summary_statistics_warmup_and_empty_fields():
+    """Latency = finish - arrival over finished requests, time to target over
+    those that reached it; warm-up arrivals count in throughput only; an
+    empty statistic is None (JSON null), never NaN."""
+    R = serve.Request
+    reqs = [R(id=0, arrival=0.0, n=16, d=8), R(id=1, arrival=0.1, n=16, d=8), R(id=2, arrival=0.2, n=40, d=4),
+            R(id=3, arrival=0.3, n=40, d=4)]
+    for r, (admit, finish, steps, reached) in zip(reqs, ((0.0, 1.0, 10, True), (0.1, 2.1, 20, False),
+                                                          (0.5, 0.7, 5, True), (0.3, 4.3, 30, False))):
+        r.status, r.admit, r.finish, r.steps, r.reached = "done", admit, finish, steps, reached
+        r.mu = 2.0 * serve.welch_bound(r.n, r.d)
+    s = serve.summarize(reqs, 10.0, 4, 0, 1, warmup=1)
+    assert s["done"] == 4 and s["measured"] == 3 and s["warmup_requests"] == 1
+    assert s["evals_per_s"] == (10 + 20 + 5 + 30) * 4 / 10.0            # warm-up included
+    assert s["screen_tflops"] == sum(r.steps * 4 * 4.0 * r.d * r.n * (r.n - 1) for r in reqs) / 10.0 / 1e12
+    assert s["reached_target"] == 1 and s["p50_time_to_target_s"] == pytest.approx(0.5)   # request 2 only
+    assert s["p50_latency_s"] == pytest.approx(2.0)                       # latencies 2.0, 0.5, 4.0
+    assert s["reached_by_d"] == {"8": {"done": 1, "reached_target": 0}, "4": {"done": 2, "reached_target": 1}}
+    assert s["median_mu_over_welch"] == pytest.approx(2.0)
+    none = serve.summarize(reqs[:1], 1.0, 4, 0, 1, warmup=1)
+    assert none["p50_latency_s"] is None and none["p99_time_to_target_s"] is None and none["mean_queue_s"] is None
+    assert "NaN" not in __import__("json").dumps(none)
