@@ -91,7 +91,7 @@ __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, 
 // Lanes [0, nl) of the calling wave group regenerate candidate c (FP64, unit
 // columns) into `out` (column stride 2d) and, when lds != null, into the FP32
 // LDS copy.  Lanes of one column are LPC consecutive lanes; the norm is
-// reduced with xor-shuffles inside the column's lanes.
+// reduced with DPP row permutes inside the column's lanes.
 template <int LPC>
 __device__ void gen_candidate(const BInst& I, const double* frame, double radius, int c, int64_t t, double* out,
                               float* lds, const GaussTab& tab, int lane_g, int nl) {
@@ -107,12 +107,11 @@ __device__ void gen_candidate(const BInst& I, const double* frame, double radius
     bool two = false;
     if (active) draw_block(I, frame, s, c, t, col, lq, tab, y, two);
     double nrm2 = (y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]);
-#pragma unroll
-    for (int off = LPC / 2; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
+    nrm2 = group_sum<LPC>(nrm2);  // DPP inside the column's lanes (every lane of the wave takes part)
     if (!active) continue;
-    const double nrm = sqrt(nrm2);
-    const bool bad = !(nrm > 0.0 && nrm < __builtin_inf());
-    const double inv = bad ? __builtin_nan("") : 1.0 / nrm;
+    // 1 / ||y||; NaN for a zero or non-finite norm, which makes the column
+    // (and so the candidate) invalid
+    const double inv = rsqrt_pos(nrm2);
     const int i0 = 2 * lq;
     double* o = out + 2 * ((size_t)col * d + i0);
     o[0] = y[0] * inv;

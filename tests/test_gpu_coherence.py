@@ -104,7 +104,10 @@ def test_haar_start_parity(n, d, seed, stream):
     assert radius == 0.1 and t == 0 and flags == 0
 
 
-@pytest.mark.parametrize("n,d,C,t", [(16, 4, 64, 0), (37, 7, 9, 5), (1024, 32, 4, 123), (70, 130, 3, 2)])
+# every column split of the candidate kernel: d = 4 and 7 (partial), 16, 32,
+# 64, 128 and 256 (full splits), 130 (wide partial)
+@pytest.mark.parametrize("n,d,C,t", [(16, 4, 64, 0), (37, 7, 9, 5), (1024, 32, 4, 123), (70, 130, 3, 2),
+                                     (90, 16, 5, 1), (200, 64, 3, 7), (129, 128, 2, 1), (40, 256, 2, 3)])
 def test_candidates_parity(n, d, C, t):
     p = oracle.Params(n=n, d=d, candidates=C, seed=1, stream_id=2)
     st = oracle.haar_init(p)
