@@ -87,4 +87,5 @@ from .trstmi import (  # noqa: F401
     step,
     solve,
     screen_error_bound,
+    split_screen_error_bound,
 )

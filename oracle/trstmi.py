@@ -204,6 +204,46 @@ def screen_error_bound(d):
     return (2 * u + u * u) + math.sqrt(2.0) * gamma * (1 + u) ** 2 + 8 * v + 1e-12
 
 
+def split_screen_error_bound(d):
+    """Largest possible |screened - exact| coherence for unit columns in C^d
+    under the batched form's split screen.
+
+    Input: each real component x of a unit column is rounded to binary32
+    (f, relative error at most 2^-24) and held as hi + lo, hi the bfloat16
+    rounding of f and lo the bfloat16 rounding of the exact remainder f - hi.
+    |f - hi| <= u |f| and |lo - (f - hi)| <= u |f - hi| with u = 2^-8, so
+    hi + lo is within delta = 2^-16 (1 + 2^-24) + 2^-24 of x, relative; a
+    complex entry moves by at most delta times its modulus and the inner
+    product of two unit columns by at most 2 delta + delta^2.
+
+    Products: Re and Im are each formed from the three products
+    hi hi' + hi lo' + lo hi' of every real pair (each exact in binary32);
+    the dropped lo lo' add up to at most 2^-16 (1 + u)^2 (1 + 2^-24)^2.
+
+    Accumulation: 3 x 32 products per part (the K = 2d <= 32 reals padded with
+    zeros), every binary32 addition faithful (error below one ulp, w =
+    2^-23): gamma_96 times the sum of |products|, which is at most
+    (1 + u)^2 (1 + 2u) (1 + 2^-24)^2.  Re and Im together give the factor
+    sqrt(2) on the product and accumulation terms.
+
+    Epilogue: the binary32 |G|^2 and the FP64 square root and threshold
+    (16 v, v = 2^-24), and the FP64 value's own rounding (1e-12).
+    """
+    if d > 16:
+        raise ValueError("the split screen serves d <= 16 (one 32-real MFMA step)")
+    u = 2.0 ** -8
+    v = 2.0 ** -24
+    w = 2.0 ** -23
+    delta = 2.0 ** -16 * (1 + v) + v
+    inputs = 2 * delta + delta * delta
+    unit = (1 + v) ** 2
+    dropped = 2.0 ** -16 * (1 + u) ** 2 * unit
+    n = 96
+    gamma = n * w / (1.0 - n * w)
+    accumulation = gamma * (1 + u) ** 2 * (1 + 2 * u) * unit
+    return inputs + math.sqrt(2.0) * (dropped + accumulation) + 16 * v + 1e-12
+
+
 def _is_done(p, mu, t):
     return (p.target_mu > 0 and mu <= p.target_mu) or t >= p.max_steps
 
