@@ -29,11 +29,13 @@ import time
 
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch_tiles.json")
 N_BUCKETS = (16, 32, 64, 128, 256)
-LDS_FLOATS = 8448
+LDS_FLOATS = 9216   # LDS words of a step block's candidate copies
 
 
 def ldk(d):
-    return (2 * d + 3) // 4 * 4 + 1
+    """LDS words per column of a candidate's split copy: hi and lo planes of
+    2d reals padded to a multiple of 8, plus 16 bytes."""
+    return (2 * d + 7) // 8 * 8 + 4
 
 
 def feasible(n, d):

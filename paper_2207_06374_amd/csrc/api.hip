@@ -509,8 +509,6 @@ struct BatchLayout {
   std::vector<int2> unit_list;
 };
 
-int32_t batch_ldk(int32_t d) { return (2 * d + 3) / 4 * 4 + 1; }
-
 trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_instance* inst, BatchLayout& L) {
   if (!p || !inst) return fail(TRSTMI_E_INVALID_ARG, "batch params or instances NULL");
   if (p->count < 1 || p->count > (1 << 20)) return fail(TRSTMI_E_INVALID_ARG, "batch count must be in [1, 2^20]");
@@ -532,7 +530,7 @@ trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_inst
       return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": need 2 <= n <= 256, 1 <= d <= 16");
     if (I.max_steps < 0 || I.max_steps > kMaxSteps || std::isnan(I.target_mu))
       return fail(TRSTMI_E_INVALID_ARG, "batch instance " + std::to_string(i) + ": bad max_steps or target");
-    const int64_t need = (int64_t)I.n * batch_ldk(I.d);
+    const int64_t need = (int64_t)I.n * batch_row_words(I.d);
     int32_t w = I.waves_per_item;
     if (w == 0) w = need * 4 <= lds ? 1 : (need * 2 <= lds ? 2 : 4);
     if (w != 1 && w != 2 && w != 4)

@@ -16,13 +16,17 @@
 // ... of the list (largest instances first), so no work counter is shared.
 // Per candidate the group
 //   1. draws and renormalises the candidate in FP64 (FP64 copy to global
-//      scratch, FP32 copy to LDS);
-//   2. screens every pair j < k with v_mfma_f32_16x16x4_f32 on the FP32 copy,
-//      keeping the maximum of every 16 x 16 pair block;
+//      scratch; to LDS, every real rounded to FP32 and held as two bfloat16
+//      parts hi + lo);
+//   2. screens every pair j < k with v_mfma_f32_16x16x32_bf16: Re and Im are
+//      each the three products hi hi' + hi lo' + lo hi' of the split copies
+//      (an FP32-class screen at three bfloat16 products instead of the FP32
+//      matrix rate, which is no faster than the FP32 vector rate), keeping
+//      the maximum of every 16 x 16 pair block;
 //   3. re-evaluates exactly in FP64 the pairs whose screened |G| is within
-//      2 eps32 of the screened maximum (eps32 bounds |screened - exact| for
-//      unit columns, so the exact maximiser is among them): every candidate
-//      ends with its exact FP64 coherence, stored with a plain write.
+//      2 eps of the screened maximum (eps bounds |screened - exact| for unit
+//      columns, so the exact maximiser is among them): every candidate ends
+//      with its exact FP64 coherence, stored with a plain write.
 // The finalizing kernel (one block per instance) then selects, accepts,
 // updates the radius and regenerates the accepted candidate in FP64 into the
 // frame.  Handing the candidates' values over at the kernel boundary replaces
@@ -37,10 +41,12 @@ namespace trstmi {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsFloats = 8192 + 256;  // FP32 candidate(s): N * (ldk + 1) per group, summed over groups
+// LDS words for the split copies of the candidates of one unit: N * ldk per
+// group, summed over groups (ldk = split_row_words(d) <= 36 at d <= 16).
+constexpr int kLdsFloats = 9216;
 
 struct alignas(16) BInst {
-  int32_t n, d, wpi, ldk;  // ldk: FP32 column stride in LDS (2d rounded up to 4, +1 padding)
+  int32_t n, d, wpi, ldk;  // ldk: words per column of the LDS split copy (split_row_words)
   uint32_t seed, stream_id;
   int64_t frame_off;       // doubles into the frame arena
   double target_mu;
@@ -55,16 +61,43 @@ struct alignas(16) BState {
   int32_t pad;
 };
 
-__device__ __forceinline__ double eps32(int d) {
-  // |screened - exact| for unit columns: FP32 inputs (relative 2^-24 in each
-  // real part, so at most u times each complex entry's modulus) move the
-  // complex inner product by at most 2u + u^2; FP32 accumulation of 2d
-  // products moves Re and Im each by gamma_{2d} (1 + u)^2, sqrt 2 for the
-  // two; the tail covers the epilogue.
-  const double u = 0x1p-24;
-  const double nu = 2.0 * d * u;
-  const double g = nu / (1.0 - nu);
-  return (2 * u + u * u) + 1.4142135623730951 * g * (1 + u) * (1 + u) + 16 * u + 1e-12;
+// Words per column of a candidate's LDS split copy: the hi parts of its 2d
+// reals padded with zeros to kp = 2d rounded up to 8, then the lo parts
+// likewise, then 16 bytes of padding (rows stay 16-byte aligned and the
+// column-strided fragment reads spread over the banks).
+__host__ __device__ constexpr int split_kp(int d) { return (2 * d + 7) / 8 * 8; }
+__host__ __device__ constexpr int split_row_words(int d) { return split_kp(d) + 4; }
+
+__device__ __forceinline__ double eps_split(int d) {
+  // |screened - exact| for unit columns, d <= 16.  Inputs: each real is
+  // rounded to FP32 (relative 2^-24) and held as hi + lo (hi = bf16 of it,
+  // lo = bf16 of the exact remainder): within delta = 2^-16 (1 + 2^-24) +
+  // 2^-24 of it, so the inner product of two unit columns moves by at most
+  // 2 delta + delta^2.  Products: the dropped lo lo' add up to at most
+  // 2^-16 (1 + u)^2 (1 + 2^-24)^2 (u = 2^-8) in each of Re and Im.
+  // Accumulation: 96 products (32 reals, zero padded, three products each)
+  // summed in FP32 with faithful additions, gamma_96 (unit 2^-23) times at
+  // most (1 + u)^2 (1 + 2u) (1 + 2^-24)^2.  Re and Im together give sqrt 2;
+  // the tail covers the epilogue.
+  (void)d;
+  const double u = 0x1p-8, v = 0x1p-24, w = 0x1p-23;
+  const double delta = 0x1p-16 * (1 + v) + v;
+  const double unit = (1 + v) * (1 + v);
+  const double dropped = 0x1p-16 * (1 + u) * (1 + u) * unit;
+  const double g = 96 * w / (1.0 - 96 * w);
+  const double acc = g * (1 + u) * (1 + u) * (1 + 2 * u) * unit;
+  return (2 * delta + delta * delta) + 1.4142135623730951 * (dropped + acc) + 16 * v + 1e-12;
+}
+
+// x = hi + lo for two FP32 values: hi = bf16(x), lo = bf16(x - hi), both
+// round to nearest even (x - hi is exact in FP32); packed with x[0] in the
+// low half.
+__device__ __forceinline__ void split_bf16x2(f32x2 x, uint32_t& hi, uint32_t& lo) {
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2));
+  const float h0 = __uint_as_float(h << 16), h1 = __uint_as_float(h & 0xFFFF0000u);
+  const f32x2 r = {x[0] - h0, x[1] - h1};
+  hi = h;
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
 }
 
 // Candidate c of instance I at step t, column col, Philox block q (entries 2q, 2q+1).
@@ -89,12 +122,12 @@ __device__ __forceinline__ void draw_block(const BInst& I, const double* frame, 
 }
 
 // Lanes [0, nl) of the calling wave group regenerate candidate c (FP64, unit
-// columns) into `out` (column stride 2d) and, when lds != null, into the FP32
-// LDS copy.  Lanes of one column are LPC consecutive lanes; the norm is
+// columns) into `out` (column stride 2d) and, when lds != null, into the LDS
+// split copy.  Lanes of one column are LPC consecutive lanes; the norm is
 // reduced with DPP row permutes inside the column's lanes.
 template <int LPC>
 __device__ void gen_candidate(const BInst& I, const double* frame, double radius, int c, int64_t t, double* out,
-                              float* lds, const GaussTab& tab, int lane_g, int nl) {
+                              uint32_t* lds, const GaussTab& tab, int lane_g, int nl) {
   const int d = I.d;
   const int nb = (d + 1) >> 1;
   const double s = radius / sqrt((double)d);
@@ -121,19 +154,27 @@ __device__ void gen_candidate(const BInst& I, const double* frame, double radius
       o[3] = y[3] * inv;
     }
     if (lds) {
-      float* l = lds + (size_t)col * I.ldk + 2 * i0;  // reals 2 i0 .. 2 i0 + 3 of the column
-      l[0] = (float)(y[0] * inv);
-      l[1] = (float)(y[1] * inv);
-      if (two) {
-        l[2] = (float)(y[2] * inv);
-        l[3] = (float)(y[3] * inv);
-      }
+      // reals 2 i0 .. 2 i0 + 3 of the column: words i0, i0 + 1 of each plane
+      // (zero past 2d); the last lane of the column also zeroes the planes'
+      // padding [4 nb, kp)
+      const int kp2 = (I.ldk - 4) / 2;  // words per plane
+      uint32_t h01, l01, h23 = 0, l23 = 0;
+      split_bf16x2(f32x2{(float)(y[0] * inv), (float)(y[1] * inv)}, h01, l01);
+      if (two) split_bf16x2(f32x2{(float)(y[2] * inv), (float)(y[3] * inv)}, h23, l23);
+      uint32_t* row = lds + (size_t)col * I.ldk;
+      *(uint2*)(row + i0) = make_uint2(h01, h23);
+      *(uint2*)(row + kp2 + i0) = make_uint2(l01, l23);
+      if (lq == nb - 1)
+        for (int k = 2 * nb; k < kp2; k += 2) {
+          *(uint2*)(row + k) = make_uint2(0u, 0u);
+          *(uint2*)(row + kp2 + k) = make_uint2(0u, 0u);
+        }
     }
   }
 }
 
 __device__ __forceinline__ void gen_dispatch(const BInst& I, const double* frame, double radius, int c, int64_t t,
-                                             double* out, float* lds, const GaussTab& tab, int lane_g, int nl) {
+                                             double* out, uint32_t* lds, const GaussTab& tab, int lane_g, int nl) {
   // d <= 16: at most 8 blocks per column
   const int nb = (I.d + 1) >> 1;
   if (nb <= 1) gen_candidate<1>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
@@ -142,52 +183,54 @@ __device__ __forceinline__ void gen_dispatch(const BInst& I, const double* frame
   else gen_candidate<8>(I, frame, radius, c, t, out, lds, tab, lane_g, nl);
 }
 
-// FP32 fragments from the LDS copy for v_mfma_f32_16x16x4_f32, KSt steps of
-// 4 over K = 2d: lane l holds row / column 16 blk + l % 16 at k = 4 s + l / 16.
-// The A side is u (row block bi); the B side is u and v = (b, -a) of column
-// block bj, so that Re = u_i . u_j and Im = u_i . v_j.
-template <int KSt>
-__device__ __forceinline__ void frag_a(const float* L, int ldk, int n, int K, int bi, float a[KSt]) {
+// Fragments of the split copy for v_mfma_f32_16x16x32_bf16: lane l holds
+// row / column 16 blk + l % 16, reals 8 (l / 16) .. + 7 of the hi and of the
+// lo plane (zero past the row's kp reals or past n).
+__device__ __forceinline__ void frag_split(const uint32_t* L, int ldk, int n, int blk, u32x4& hi, u32x4& lo) {
   const int lane = threadIdx.x & 63;
-  const int row = bi * 16 + (lane & 15);
-#pragma unroll
-  for (int st = 0; st < KSt; ++st) {
-    const int k = 4 * st + (lane >> 4);
-    a[st] = (row < n && k < K) ? L[(size_t)row * ldk + k] : 0.f;
+  const int r = blk * 16 + (lane & 15);
+  const int w0 = 4 * (lane >> 4);  // first word of the lane's 8 reals
+  const int kp2 = (ldk - 4) / 2;
+  hi = u32x4{0u, 0u, 0u, 0u};
+  lo = u32x4{0u, 0u, 0u, 0u};
+  if (r < n && w0 < kp2) {
+    const uint32_t* p = L + (size_t)r * ldk + w0;
+    hi = *(const u32x4*)p;
+    lo = *(const u32x4*)(p + kp2);
   }
 }
 
-template <int KSt>
-__device__ __forceinline__ void frag_b(const float* L, int ldk, int n, int K, int bj, float bu[KSt], float bv[KSt]) {
-  const int lane = threadIdx.x & 63;
-  const int col = bj * 16 + (lane & 15);
-  const bool odd = (lane >> 4) & 1;
+// v = (b, -a) per complex entry (a + ib) of a packed word pair (a low, b
+// high), so that Im = u_i . v_j: swap the halves, negate the new high half.
+__device__ __forceinline__ u32x4 rot_entries(u32x4 u) {
+  u32x4 v;
 #pragma unroll
-  for (int st = 0; st < KSt; ++st) {
-    const int k = 4 * st + (lane >> 4);
-    bu[st] = (col < n && k < K) ? L[(size_t)col * ldk + k] : 0.f;
-    const float x = (col < n && (k ^ 1) < K) ? L[(size_t)col * ldk + (k ^ 1)] : 0.f;
-    bv[st] = odd ? -x : x;
-  }
+  for (int e = 0; e < 4; ++e) v[e] = __builtin_amdgcn_alignbit(u[e], u[e], 16) ^ 0x80000000u;
+  return v;
 }
 
-// |G|^2 of the 16 x 16 pair block (bi, bj): m[v] = output (row 4 (lane/16) + v,
-// column lane % 16), 0 where the pair is not (j > i, j < n).
-template <int KSt>
-__device__ __forceinline__ void screen_frags(const float a[KSt], const float bu[KSt], const float bv[KSt], int n,
-                                             int bi, int bj, float m[4]) {
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+// |G|^2 of the 16 x 16 pair block (bi, bj) from the split fragments of row
+// block bi (a) and column block bj (b): Re and Im each accumulate
+// hi lo', lo hi' and hi hi'.  m[v] = output (row 4 (lane/16) + v, column
+// lane % 16), 0 where the pair is not (j > i, j < n).
+__device__ __forceinline__ void screen_split(u32x4 ah, u32x4 al, u32x4 bh, u32x4 bl, int n, int bi, int bj,
+                                             float m[4]) {
   const int lane = threadIdx.x & 63;
-  v4f32 accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int st = 0; st < KSt; ++st) {
-    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], bu[st], accR, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], bv[st], accI, 0, 0, 0);
-  }
+  const u32x4 vh = rot_entries(bh), vl = rot_entries(bl);
+  const v4f32 z = {0.f, 0.f, 0.f, 0.f};
+  v4f32 R = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bl), z, 0, 0, 0);
+  v4f32 I = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(vl), z, 0, 0, 0);
+  R = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(bh), R, 0, 0, 0);
+  I = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(vh), I, 0, 0, 0);
+  R = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh), R, 0, 0, 0);
+  I = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(vh), I, 0, 0, 0);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = bi * 16 + 4 * (lane >> 4) + v;
     const int j = bj * 16 + (lane & 15);
-    m[v] = (i < j && j < n) ? fmaf(accR[v], accR[v], accI[v] * accI[v]) : 0.f;
+    m[v] = (i < j && j < n) ? fmaf(R[v], R[v], I[v] * I[v]) : 0.f;
   }
 }
 
@@ -299,12 +342,11 @@ __device__ __forceinline__ void group_sync(bool solo) {
   }
 }
 
-template <int KSt>
-__device__ void screen_phase(const BInst& I, const float* L, const double* c64, int nbk, int nblk, int wg, int wpi,
-                             bool work, uint32_t* blkmax, uint32_t* smax, unsigned long long* umax) {
+__device__ void screen_phase(const BInst& I, const uint32_t* L, const double* c64, int nbk, int nblk, int wg,
+                             int wpi, bool work, uint32_t* blkmax, uint32_t* smax, unsigned long long* umax) {
   const int lane = threadIdx.x & 63;
-  const int n = I.n, K = 2 * I.d;
-  float a[KSt], bu[KSt], bv[KSt];
+  const int n = I.n;
+  u32x4 ah, al, bh, bl;
   if (work) {
     uint32_t wmax = 0;
     int cur = -1;
@@ -312,12 +354,12 @@ __device__ void screen_phase(const BInst& I, const float* L, const double* c64, 
       int bi, bj;
       tile_decode(b, nbk, bi, bj);
       if (bi != cur) {  // the A fragments serve the whole row of blocks
-        frag_a<KSt>(L, I.ldk, n, K, bi, a);
+        frag_split(L, I.ldk, n, bi, ah, al);
         cur = bi;
       }
-      frag_b<KSt>(L, I.ldk, n, K, bj, bu, bv);
+      frag_split(L, I.ldk, n, bj, bh, bl);
       float m[4];
-      screen_frags<KSt>(a, bu, bv, n, bi, bj, m);
+      screen_split(ah, al, bh, bl, n, bi, bj, m);
       uint32_t bm = __float_as_uint(m[0]);
 #pragma unroll
       for (int v = 1; v < 4; ++v) bm = __float_as_uint(m[v]) > bm ? __float_as_uint(m[v]) : bm;
@@ -333,17 +375,17 @@ __device__ void screen_phase(const BInst& I, const float* L, const double* c64, 
     if (sb >= kInfBits32) {
       if (wg == 0 && lane == 0) *umax = ~0ull;  // non-finite column: invalid candidate
     } else {
-      const double thr = sqrt((double)__uint_as_float(sb)) - 2.0 * eps32(I.d);
+      const double thr = sqrt((double)__uint_as_float(sb)) - 2.0 * eps_split(I.d);
       const float thr_sq = thr > 0.0 ? (float)(thr * thr * (1.0 - 1e-6)) : 0.0f;
       uint64_t best = 0;
       for (int b = wg; b < nblk; b += wpi) {
         if (__uint_as_float(blkmax[b]) < thr_sq) continue;
         int bi, bj;
         tile_decode(b, nbk, bi, bj);
-        frag_a<KSt>(L, I.ldk, n, K, bi, a);
-        frag_b<KSt>(L, I.ldk, n, K, bj, bu, bv);
+        frag_split(L, I.ldk, n, bi, ah, al);
+        frag_split(L, I.ldk, n, bj, bh, bl);
         float m[4];
-        screen_frags<KSt>(a, bu, bv, n, bi, bj, m);
+        screen_split(ah, al, bh, bl, n, bi, bj, m);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int ii = bi * 16 + 4 * (lane >> 4) + v;
@@ -361,28 +403,11 @@ __device__ void screen_phase(const BInst& I, const float* L, const double* c64, 
   group_sync(wpi == 1);
 }
 
-// K = 2d <= 32: ceil(d / 2) steps of 4.
-__device__ __forceinline__ void screen_dispatch(const BInst& I, const float* L, const double* c64, int nbk, int nblk,
-                                                int wg, int wpi, int g, bool work, uint32_t* blkmax, uint32_t* smax,
-                                                unsigned long long* umax) {
-  (void)g;
-  switch ((I.d + 1) >> 1) {
-    case 1: screen_phase<1>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    case 2: screen_phase<2>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    case 3: screen_phase<3>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    case 4: screen_phase<4>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    case 5: screen_phase<5>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    case 6: screen_phase<6>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    case 7: screen_phase<7>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-    default: screen_phase<8>(I, L, c64, nbk, nblk, wg, wpi, work, blkmax, smax, umax); break;
-  }
-}
-
 // Four blocks per CU (the LDS and register use of one block fit four times):
 // the Gaussian tables are read from the workspace copy the init launch
 // filled (8 KiB, held in the CU's cache) rather than kept in LDS.
 __global__ __launch_bounds__(kThreads, 4) void k_batch_step(BatchArgs a) {
-  __shared__ float lds[kLdsFloats];
+  __shared__ __align__(16) uint32_t lds[kLdsFloats];
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
   __shared__ uint32_t smax[4];
   __shared__ unsigned long long umax[4];
@@ -403,13 +428,13 @@ __global__ __launch_bounds__(kThreads, 4) void k_batch_step(BatchArgs a) {
     const int c = unit.y + g;
     const bool work = !skip_inst && c < a.C;
     const int groups = 4 / wpi;
-    float* L = lds + (size_t)g * (kLdsFloats / groups);
+    uint32_t* L = lds + (size_t)g * (kLdsFloats / groups);
     double* c64 = a.scratch + ((size_t)blockIdx.x * 4 + g) * a.scratch_stride;
     const int n = I.n;
     const int nbk = (n + 15) / 16;
     const int nblk = nbk * (nbk + 1) / 2;
 
-    // 1. candidate (FP64 scratch + FP32 LDS copy; entries past 2d are never read)
+    // 1. candidate (FP64 scratch + LDS split copy, zero padded to kp reals)
     const bool solo = wpi == 1;
     if (solo) {
       if (lane == 0) {
@@ -430,9 +455,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_batch_step(BatchArgs a) {
     __threadfence_block();
     group_sync(solo);
 
-    // 2. FP32 screen: block maxima and the candidate maximum;
+    // 2. split screen: block maxima and the candidate maximum;
     // 3. certified FP64 recheck of the pairs that can attain the maximum
-    screen_dispatch(I, L, c64, nbk, nblk, wg, wpi, g, work, blkmax[g], &smax[g], &umax[g]);
+    screen_phase(I, L, c64, nbk, nblk, wg, wpi, work, blkmax[g], &smax[g], &umax[g]);
 
     // 4. publish (read by the finalizing launch)
     if (work && wg == 0 && lane == 0) a.cand_max[(size_t)i * a.C + c] = umax[g];
@@ -554,7 +579,7 @@ void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed
   I.n = n;
   I.d = d;
   I.wpi = wpi;
-  I.ldk = (2 * d + 3) / 4 * 4 + 1;
+  I.ldk = split_row_words(d);
   I.seed = seed;
   I.stream_id = stream_id;
   I.frame_off = frame_off;
@@ -564,6 +589,8 @@ void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed
 }
 
 int batch_lds_floats() { return kLdsFloats; }
+
+int32_t batch_row_words(int32_t d) { return split_row_words(d); }
 
 size_t batch_tab_bytes() { return sizeof(GaussTab); }
 

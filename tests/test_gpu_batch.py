@@ -12,6 +12,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 lib = pytest.importorskip("paper_2207_06374_amd")
+autotune = pytest.importorskip("paper_2207_06374_amd.autotune")
 
 
 def _specs(count, seed, d_hi=8, max_steps=1000, wpi=0):
@@ -80,8 +81,8 @@ def test_batch_result_independent_of_mix_and_tile():
         assert np.array_equal(alone[3][0], full[3][k])
     for wpi in (1, 2, 4):
         ok = [dict(s, waves_per_item=wpi) for s in specs
-              if s["n"] * ((2 * s["d"] + 3) // 4 * 4 + 1) * (4 // wpi) <= 8448]
-        idx = [k for k, s in enumerate(specs) if s["n"] * ((2 * s["d"] + 3) // 4 * 4 + 1) * (4 // wpi) <= 8448]
+              if s["n"] * autotune.ldk(s["d"]) * (4 // wpi) <= autotune.LDS_FLOATS]
+        idx = [k for k, s in enumerate(specs) if s["n"] * autotune.ldk(s["d"]) * (4 // wpi) <= autotune.LDS_FLOATS]
         res = _final(lib.Batch(ok, candidates=C).init(), steps)
         for j, k in enumerate(idx):
             assert res[0][j] == full[0][k] and res[1][j] == full[1][k]
