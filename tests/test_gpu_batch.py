@@ -15,9 +15,9 @@ lib = pytest.importorskip("paper_2207_06374_amd")
 autotune = pytest.importorskip("paper_2207_06374_amd.autotune")
 
 
-def _specs(count, seed, d_hi=8, max_steps=1000, wpi=0):
+def _specs(count, seed, d_hi=8, max_steps=1000, wpi=0, d_lo=3):
     out = []
-    for k, (d, n) in enumerate(inputs.batched_instances(count, seed=seed, d_hi=d_hi)):
+    for k, (d, n) in enumerate(inputs.batched_instances(count, seed=seed, d_lo=d_lo, d_hi=d_hi)):
         out.append({"n": n, "d": d, "seed": 7, "stream_id": 100 + k, "max_steps": max_steps, "waves_per_item": wpi})
     return out
 
@@ -25,6 +25,57 @@ def _specs(count, seed, d_hi=8, max_steps=1000, wpi=0):
 def _oracle_params(spec, C, radius0=0.1):
     return oracle.Params(n=spec["n"], d=spec["d"], candidates=C, mode="fp64", seed=spec["seed"],
                          stream_id=spec["stream_id"], radius0=radius0, max_steps=spec["max_steps"])
+
+
+def _follow_oracle(specs, C, steps):
+    """Step the batch and every instance's oracle search side by side: each
+    candidate's FP64 mu within 1e-12, then selection, acceptance, radius and
+    step while no near tie; returns the instances stopped at a near tie."""
+    b = lib.Batch(specs, candidates=C, radius0=0.1).init()
+    mu = b.query()[0]
+    states = []
+    for k, sp in enumerate(specs):
+        p = _oracle_params(sp, C)
+        st = oracle.haar_init(p)
+        assert abs(mu[k] - st.mu) <= 1e-12
+        states.append((p, st))
+    stopped = set()
+    for t in range(steps):
+        b.step(1, report=True)
+        rep_mu = b.rep_mu.cpu().numpy().reshape(len(specs), C)
+        rep_best = b.rep_best.cpu().numpy()
+        mu, radius, step, flags, done = b.query()
+        for k, (p, st) in enumerate(states):
+            if k in stopped:
+                continue
+            new, rep = oracle.step(p, st)
+            assert np.max(np.abs(rep_mu[k] - rep.cand_mu)) <= 1e-12, f"instance {k} step {t}"
+            if rep.near_tie or flags[k] & lib.FLAG_NEAR_TIE:
+                stopped.add(k)
+                continue
+            assert rep_best[k] == rep.best and bool(flags[k] & lib.FLAG_ACCEPTED) == rep.accepted
+            assert radius[k] == new.radius and step[k] == new.t and abs(mu[k] - new.mu) <= 1e-12
+            states[k] = (p, new)
+    return stopped
+
+
+def test_batch_large_d_matches_oracle():
+    """d = 9..16 (the reals fill the whole 32-wide screen step; N up to d^2):
+    every candidate's exact mu through the split screen and its recheck."""
+    specs = _specs(10, seed=13, d_lo=9, d_hi=16)
+    stopped = _follow_oracle(specs, 16, 5)
+    assert len(stopped) < len(specs)
+
+
+def test_batch_long_run_on_small_instances_matches_oracle():
+    """300 steps at d = 3, 4 (N up to d^2): the search evens out the largest
+    pairs (6 to 13 pairs of each final frame lie within twice the screen's
+    bound of its maximum), so the recheck re-evaluates several pairs per
+    candidate; every candidate's exact mu still matches."""
+    specs = [{"n": n, "d": d, "seed": 7, "stream_id": 500 + k, "max_steps": 10 ** 6, "waves_per_item": 0}
+             for k, (d, n) in enumerate([(3, 9), (3, 7), (4, 16), (4, 12)])]
+    stopped = _follow_oracle(specs, 16, 300)
+    assert len(stopped) < len(specs)
 
 
 def test_batch_matches_oracle_per_instance():
