@@ -226,11 +226,16 @@ __device__ __forceinline__ void screen_split(u32x4 ah, u32x4 al, u32x4 bh, u32x4
   I = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(vh), I, 0, 0, 0);
   R = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh), R, 0, 0, 0);
   I = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(vh), I, 0, 0, 0);
+  if (bi < bj && (bj + 1) * 16 <= n) {  // every pair of the block is j > i, j < n
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = bi * 16 + 4 * (lane >> 4) + v;
-    const int j = bj * 16 + (lane & 15);
-    m[v] = (i < j && j < n) ? fmaf(R[v], R[v], I[v] * I[v]) : 0.f;
+    for (int v = 0; v < 4; ++v) m[v] = fmaf(R[v], R[v], I[v] * I[v]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = bi * 16 + 4 * (lane >> 4) + v;
+      const int j = bj * 16 + (lane & 15);
+      m[v] = (i < j && j < n) ? fmaf(R[v], R[v], I[v] * I[v]) : 0.f;
+    }
   }
 }
 
@@ -342,6 +347,17 @@ __device__ __forceinline__ void group_sync(bool solo) {
   }
 }
 
+// (bi, bj) of the pair block `step` places after (bi, bj) in row-by-row
+// upper-triangle order (row bi holds bj = bi .. nbk - 1); step <= 4 and every
+// row holds at least one block, so the loop runs at most four times.
+__device__ __forceinline__ void tile_advance(int step, int nbk, int& bi, int& bj) {
+  bj += step;
+  while (bj >= nbk && bi < nbk) {
+    bj -= nbk - (bi + 1);
+    ++bi;
+  }
+}
+
 __device__ void screen_phase(const BInst& I, const uint32_t* L, const double* c64, int nbk, int nblk, int wg,
                              int wpi, bool work, uint32_t* blkmax, uint32_t* smax, unsigned long long* umax) {
   const int lane = threadIdx.x & 63;
@@ -350,9 +366,9 @@ __device__ void screen_phase(const BInst& I, const uint32_t* L, const double* c6
   if (work) {
     uint32_t wmax = 0;
     int cur = -1;
-    for (int b = wg; b < nblk; b += wpi) {
-      int bi, bj;
-      tile_decode(b, nbk, bi, bj);
+    int bi = 0, bj = 0;
+    tile_advance(wg, nbk, bi, bj);
+    for (int b = wg; b < nblk; b += wpi, tile_advance(wpi, nbk, bi, bj)) {
       if (bi != cur) {  // the A fragments serve the whole row of blocks
         frag_split(L, I.ldk, n, bi, ah, al);
         cur = bi;
