@@ -495,13 +495,17 @@ trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, vo
  * N_i, d_i, seed and stream (its draws are those of a single search with the
  * same seed and stream_id), its own frame, radius, step and flags, and its own
  * target / step limit; the candidate count, radius rule and near-tie threshold
- * are shared.  Every candidate is screened in FP32 on MFMA and the pairs that
- * can attain its maximum are re-evaluated in FP64, so each candidate's
- * coherence, the selection and the accept test are exact FP64 (each instance
- * follows the FP64 single search; its result does not depend on the other
- * instances in the batch or on its waves_per_item).
- * Limits: 2 <= n <= 256, 1 <= d <= 16, n * (ceil(2d/4)*4 + 1) <= 8448 * wpi / 4,
- * 1 <= candidates <= 256.  All state lives in the caller's workspace.
+ * are shared.  Every candidate is screened to FP32-class accuracy on the
+ * BF16 matrix cores (each real rounded to FP32 and held as two bfloat16
+ * parts hi + lo; Re and Im from hi hi' + hi lo' + lo hi'; certified error
+ * below 7e-5 for unit columns) and the pairs that can attain its maximum are
+ * re-evaluated in FP64, so each candidate's coherence, the selection and the
+ * accept test are exact FP64 (each instance follows the FP64 single search;
+ * its result does not depend on the other instances in the batch or on its
+ * waves_per_item).
+ * Limits: 2 <= n <= 256, 1 <= d <= 16, n * (ceil(2d/8)*8 + 4) <= 9216 * wpi / 4
+ * (LDS words of a candidate's split copy), 1 <= candidates <= 256.  All state
+ * lives in the caller's workspace.
  */
 typedef struct trstmi_batch_instance {
   int32_t n;
