@@ -29,7 +29,7 @@ import time
 
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch_tiles.json")
 N_BUCKETS = (16, 32, 64, 128, 256)
-LDS_FLOATS = 9216   # LDS words of a step block's candidate copies
+LDS_WORDS = 9216   # LDS words of a step block's candidate copies
 
 
 def ldk(d):
@@ -39,7 +39,7 @@ def ldk(d):
 
 
 def feasible(n, d):
-    return [w for w in (1, 2, 4) if n * ldk(d) * (4 // w) <= LDS_FLOATS]
+    return [w for w in (1, 2, 4) if n * ldk(d) * (4 // w) <= LDS_WORDS]
 
 
 def classes(d_lo=3, d_hi=16):

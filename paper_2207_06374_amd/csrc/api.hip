@@ -519,7 +519,7 @@ trstmi_status batch_layout(const trstmi_batch_params* p, const trstmi_batch_inst
   if (!ok_r) return fail(TRSTMI_E_INVALID_ARG, "need finite 0 < radius_min <= radius0 <= radius_max");
   if (!(std::isfinite(p->grow) && p->grow >= 1.0) || !(std::isfinite(p->shrink) && p->shrink > 0 && p->shrink <= 1.0))
     return fail(TRSTMI_E_INVALID_ARG, "need grow >= 1 and 0 < shrink <= 1");
-  const int lds = batch_lds_floats();
+  const int lds = batch_lds_words();
   L.frame_off.resize(p->count);
   L.wpi.resize(p->count);
   int64_t off = 0, max_frame = 0;

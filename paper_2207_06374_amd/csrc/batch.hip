@@ -43,7 +43,7 @@ namespace {
 constexpr int kThreads = 256;
 // LDS words for the split copies of the candidates of one unit: N * ldk per
 // group, summed over groups (ldk = split_row_words(d) <= 36 at d <= 16).
-constexpr int kLdsFloats = 9216;
+constexpr int kLdsWords = 9216;
 
 struct alignas(16) BInst {
   int32_t n, d, wpi, ldk;  // ldk: words per column of the LDS split copy (split_row_words)
@@ -423,7 +423,7 @@ __device__ void screen_phase(const BInst& I, const uint32_t* L, const double* c6
 // the Gaussian tables are read from the workspace copy the init launch
 // filled (8 KiB, held in the CU's cache) rather than kept in LDS.
 __global__ __launch_bounds__(kThreads, 4) void k_batch_step(BatchArgs a) {
-  __shared__ __align__(16) uint32_t lds[kLdsFloats];
+  __shared__ __align__(16) uint32_t lds[kLdsWords];
   __shared__ uint32_t blkmax[4][136];       // per group: max |G|^2 bits of each 16 x 16 pair block (N <= 256)
   __shared__ uint32_t smax[4];
   __shared__ unsigned long long umax[4];
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_batch_step(BatchArgs a) {
     const int c = unit.y + g;
     const bool work = !skip_inst && c < a.C;
     const int groups = 4 / wpi;
-    uint32_t* L = lds + (size_t)g * (kLdsFloats / groups);
+    uint32_t* L = lds + (size_t)g * (kLdsWords / groups);
     double* c64 = a.scratch + ((size_t)blockIdx.x * 4 + g) * a.scratch_stride;
     const int n = I.n;
     const int nbk = (n + 15) / 16;
@@ -604,7 +604,7 @@ void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed
   *(BInst*)dst = I;
 }
 
-int batch_lds_floats() { return kLdsFloats; }
+int batch_lds_words() { return kLdsWords; }
 
 int32_t batch_row_words(int32_t d) { return split_row_words(d); }
 

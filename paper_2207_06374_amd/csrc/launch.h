@@ -196,7 +196,7 @@ size_t batch_inst_bytes();
 size_t batch_state_bytes();
 void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed, uint32_t stream_id,
                      int64_t frame_off, double target_mu, int64_t max_steps);
-int batch_lds_floats();
+int batch_lds_words();
 int32_t batch_row_words(int32_t d);  // LDS words per column of a candidate's split copy
 size_t batch_tab_bytes();
 

@@ -132,8 +132,8 @@ def test_batch_result_independent_of_mix_and_tile():
         assert np.array_equal(alone[3][0], full[3][k])
     for wpi in (1, 2, 4):
         ok = [dict(s, waves_per_item=wpi) for s in specs
-              if s["n"] * autotune.ldk(s["d"]) * (4 // wpi) <= autotune.LDS_FLOATS]
-        idx = [k for k, s in enumerate(specs) if s["n"] * autotune.ldk(s["d"]) * (4 // wpi) <= autotune.LDS_FLOATS]
+              if s["n"] * autotune.ldk(s["d"]) * (4 // wpi) <= autotune.LDS_WORDS]
+        idx = [k for k, s in enumerate(specs) if s["n"] * autotune.ldk(s["d"]) * (4 // wpi) <= autotune.LDS_WORDS]
         res = _final(lib.Batch(ok, candidates=C).init(), steps)
         for j, k in enumerate(idx):
             assert res[0][j] == full[0][k] and res[1][j] == full[1][k]
