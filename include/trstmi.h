@@ -660,6 +660,17 @@ size_t trstmi_request_footprint(const trstmi_params* p);
  * rows (0 if slots is out of range). */
 size_t trstmi_server_table_bytes(int32_t slots);
 
+/* Certified bounds on |screened - exact| coherence for unit columns in C^d
+ * (section I's mu), used to prune the FP64 rechecks of the two
+ * reduced-precision screens; host functions, no device is touched, NaN for
+ * d out of range:
+ *  - trstmi_bf16_screen_bound: the BF16-screen form (TRSTMI_MODE_BF16_SCREEN
+ *    of trstmi_step and trstmi_solve, and the serving engine), d >= 1;
+ *  - trstmi_batch_screen_bound: the batched form's split screen (FP32 values
+ *    as hi + lo bfloat16 parts, three products), 1 <= d <= 16. */
+double trstmi_bf16_screen_bound(int64_t d);
+double trstmi_batch_screen_bound(int32_t d);
+
 /* The Welch bound sqrt((n - d) / (d (n - 1))) (0 for n <= d; section II),
  * the default target of a request is target_factor times it.  NaN for
  * n < 2 or d < 1. */

@@ -166,6 +166,8 @@ SIGNATURES = {
     "trstmi_optimize_batched": (_i32, [_i64, _i64, _P(OptParams), _vp, _P(ctypes.c_double), _P(ctypes.c_int32), _vp,
                                        _sz, _vp]),
     "trstmi_welch_bound": (ctypes.c_double, [_i64, _i64]),
+    "trstmi_bf16_screen_bound": (ctypes.c_double, [_i64]),
+    "trstmi_batch_screen_bound": (ctypes.c_double, [ctypes.c_int32]),
     "trstmi_coherence_noalloc_max_bytes": (_sz, []),
     "trstmi_coherence_noalloc": (_i32, [_i64, _i64, _i32, _vp, _vp, _vp]),
     "trstmi_lse_hvp_workspace_bytes": (_sz, [_i64, _i64]),

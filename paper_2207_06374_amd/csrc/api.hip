@@ -1531,6 +1531,10 @@ trstmi_status trstmi_batch_frame(const trstmi_batch_params* p, const trstmi_batc
 
 const char* trstmi_last_error(void) { return g_last_error.c_str(); }
 
+double trstmi_bf16_screen_bound(int64_t d) { return d >= 1 ? screen_eps(d) : NAN; }
+
+double trstmi_batch_screen_bound(int32_t d) { return d >= 1 && d <= 16 ? batch_screen_eps(d) : NAN; }
+
 trstmi_status trstmi_shutdown(void) {
   Timing& T = timing();
   std::lock_guard<std::mutex> g(T.mu);

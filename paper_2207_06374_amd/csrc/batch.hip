@@ -68,7 +68,7 @@ struct alignas(16) BState {
 __host__ __device__ constexpr int split_kp(int d) { return (2 * d + 7) / 8 * 8; }
 __host__ __device__ constexpr int split_row_words(int d) { return split_kp(d) + 4; }
 
-__device__ __forceinline__ double eps_split(int d) {
+__host__ __device__ inline double eps_split(int d) {
   // |screened - exact| for unit columns, d <= 16.  Inputs: each real is
   // rounded to FP32 (relative 2^-24) and held as hi + lo (hi = bf16 of it,
   // lo = bf16 of the exact remainder): within delta = 2^-16 (1 + 2^-24) +
@@ -607,6 +607,8 @@ void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed
 int batch_lds_words() { return kLdsWords; }
 
 int32_t batch_row_words(int32_t d) { return split_row_words(d); }
+
+double batch_screen_eps(int32_t d) { return eps_split(d); }
 
 size_t batch_tab_bytes() { return sizeof(GaussTab); }
 

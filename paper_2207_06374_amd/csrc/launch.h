@@ -198,6 +198,7 @@ void batch_fill_inst(void* dst, int32_t n, int32_t d, int32_t wpi, uint32_t seed
                      int64_t frame_off, double target_mu, int64_t max_steps);
 int batch_lds_words();
 int32_t batch_row_words(int32_t d);  // LDS words per column of a candidate's split copy
+double batch_screen_eps(int32_t d);    // the split screen's certified bound (d <= 16)
 size_t batch_tab_bytes();
 
 hipError_t launch_perturb(const PerturbArgs& a, int slots, hipStream_t s);

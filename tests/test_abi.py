@@ -400,3 +400,17 @@ def test_c_abi_from_plain_c():
                         "-L", pkg, "-ltrstmi", "-Wl,-rpath," + pkg], check=True, capture_output=True)
         r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
         assert r.returncode == 0 and r.stdout.strip() == "ok", (r.returncode, r.stdout, r.stderr)
+
+
+def test_screen_bounds_equal_the_oracle(L):
+    """The bounds the library prunes its FP64 rechecks with are the oracle's
+    pinned ones (two independent writings of the same formulas)."""
+    import math
+
+    import oracle
+    for d in (1, 2, 3, 7, 16, 33, 64, 128, 512):
+        assert L.trstmi_bf16_screen_bound(d) == pytest.approx(oracle.screen_error_bound(d), rel=1e-14, abs=0)
+    for d in range(1, 17):
+        assert L.trstmi_batch_screen_bound(d) == pytest.approx(oracle.split_screen_error_bound(d), rel=1e-14, abs=0)
+    assert math.isnan(L.trstmi_bf16_screen_bound(0))
+    assert math.isnan(L.trstmi_batch_screen_bound(0)) and math.isnan(L.trstmi_batch_screen_bound(17))
