@@ -498,7 +498,7 @@ trstmi_status trstmi_solve(const trstmi_params* p, const trstmi_state* state, vo
  * are shared.  Every candidate is screened to FP32-class accuracy on the
  * BF16 matrix cores (each real rounded to FP32 and held as two bfloat16
  * parts hi + lo; Re and Im from hi hi' + hi lo' + lo hi'; certified error
- * below 7e-5 for unit columns) and the pairs that can attain its maximum are
+ * below 5.5e-5 for unit columns) and the pairs that can attain its maximum are
  * re-evaluated in FP64, so each candidate's coherence, the selection and the
  * accept test are exact FP64 (each instance follows the FP64 single search;
  * its result does not depend on the other instances in the batch or on its

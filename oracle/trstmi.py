@@ -210,15 +210,19 @@ def split_screen_error_bound(d):
 
     Input: each real component x of a unit column is rounded to binary32
     (f, relative error at most 2^-24) and held as hi + lo, hi the bfloat16
-    rounding of f and lo the bfloat16 rounding of the exact remainder f - hi.
-    |f - hi| <= u |f| and |lo - (f - hi)| <= u |f - hi| with u = 2^-8, so
-    hi + lo is within delta = 2^-16 (1 + 2^-24) + 2^-24 of x, relative; a
-    complex entry moves by at most delta times its modulus and the inner
-    product of two unit columns by at most 2 delta + delta^2.
+    rounding of f and lo the bfloat16 rounding of the exact remainder
+    r = f - hi.  With 2^e <= |f| < 2^(e+1), |r| is at most half the bfloat16
+    spacing of that binade, 2^(e-8); at equality r is a power of two and lo =
+    r; otherwise |r| < 2^(e-8), so r lies in a binade at or below 2^(e-9) and
+    |lo - r| <= 2^(e-9-8) <= 2^-17 |f|.  hi + lo is therefore within delta =
+    2^-17 (1 + 2^-24) + 2^-24 of x, relative; a complex entry moves by at
+    most delta times its modulus and the inner product of two unit columns by
+    at most 2 delta + delta^2.
 
     Products: Re and Im are each formed from the three products
     hi hi' + hi lo' + lo hi' of every real pair (each exact in binary32);
-    the dropped lo lo' add up to at most 2^-16 (1 + u)^2 (1 + 2^-24)^2.
+    |r| <= u |f| and |lo| <= (1 + u) |r| with u = 2^-8, so the dropped lo lo'
+    add up to at most 2^-16 (1 + u)^2 (1 + 2^-24)^2.
 
     Accumulation: 3 x 32 products per part (the K = 2d <= 32 reals padded with
     zeros), every binary32 addition faithful (error below one ulp, w =
@@ -234,7 +238,7 @@ def split_screen_error_bound(d):
     u = 2.0 ** -8
     v = 2.0 ** -24
     w = 2.0 ** -23
-    delta = 2.0 ** -16 * (1 + v) + v
+    delta = 2.0 ** -17 * (1 + v) + v
     inputs = 2 * delta + delta * delta
     unit = (1 + v) ** 2
     dropped = 2.0 ** -16 * (1 + u) ** 2 * unit

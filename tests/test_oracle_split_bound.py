@@ -9,10 +9,9 @@ maximum.  That recheck finds the exact maximum only if |screened - exact|
 never exceeds the bound.  These tests check the pieces of the bound and the
 bound itself against inputs built to make the errors add up:
 
-* the representation: hi + lo is within 2^-16 of the binary32 value, the
-  remainder f - hi is exact, and random values reach about half of 2^-16
-  (the two roundings cannot both be maximal, so the term is conservative by
-  about 2);
+* the representation: hi + lo is within 2^-17 of the binary32 value (the
+  remainder lies at least nine binades below it), the remainder f - hi is
+  exact, and random values come close to 2^-17 (the term is nearly tight);
 * an adversarial pair whose components all carry a near-largest
   representation error, arranged so that every such error raises
   Re<phi, psi>: it reaches a clear part of the input term, exceeds the bound
@@ -89,17 +88,19 @@ def screened(phi, psi, direction="nearest"):
     return math.sqrt(float(g2))
 
 
-def test_representation_is_exact_remainder_and_within_2_pow_minus_16():
+def test_representation_is_exact_remainder_and_within_2_pow_minus_17():
     rng = np.random.default_rng(3)
     f = np.float32(rng.standard_normal(200000) * np.exp2(rng.integers(-20, 4, 200000))).astype(np.float64)
     hi, lo = split(f)
     r = f - hi
     assert np.array_equal(np.float32(r).astype(np.float64), r)          # the remainder is binary32-exact
     rel = np.abs(hi + lo - f) / np.abs(f)
-    assert rel.max() <= 2.0 ** -16
-    assert np.all(np.abs(lo) <= U * (1 + U) * np.abs(f))
-    # random values reach about half of 2^-16
-    assert rel.max() >= 0.45 * 2.0 ** -16
+    assert rel.max() <= 2.0 ** -17
+    assert np.all(np.abs(r) <= U * np.abs(f)) and np.all(np.abs(lo) <= U * (1 + U) * np.abs(f))
+    # random values come close to 2^-17 ...
+    assert rel.max() >= 0.9 * 2.0 ** -17
+    # ... and a bound of half of it would be wrong
+    assert rel.max() > 0.5 * 2.0 ** -17
 
 
 def _extreme_pools(seed=0):
@@ -172,9 +173,9 @@ def test_adversarial_pair_reaches_the_input_term_and_stays_within_bound(d):
     for dirn, err in errs.items():
         assert abs(err) <= eps, dirn
     err = errs["nearest"]
-    # a clear part of the input term 2 delta (about 3.06e-5) is attained (the
-    # dropped lo lo' of the majority group take some of it back) ...
-    assert err >= 0.25 * 2 * 2.0 ** -16
+    # most of the input term 2 delta (about 1.54e-5) is attained (the dropped
+    # lo lo' of the majority group take some of it back) ...
+    assert err >= 0.5 * 2 * 2.0 ** -17
     # ... which the binary32 screen's own bound (inputs rounded to binary32,
     # 2d products per part) does not cover
     w = 2.0 ** -23
@@ -196,15 +197,15 @@ def test_random_frames_with_directed_accumulation_within_bound(direction):
 
 
 def test_bound_value():
-    """About 7e-5: the input term 2 delta = 3.06e-5, sqrt 2 times the dropped
-    products 1.54e-5 and the accumulation 1.16e-5, and the epilogue; the same
-    for every d <= 16 (the reals are padded to 32); refused above."""
+    """About 5.45e-5: the input term 2 delta = 1.54e-5, sqrt 2 times the
+    dropped products 1.54e-5 and the accumulation 1.16e-5, and the epilogue;
+    the same for every d <= 16 (the reals are padded to 32); refused above."""
     e = oracle.split_screen_error_bound(16)
-    delta = 2.0 ** -16 * (1 + V) + V
-    assert 3.06e-5 < 2 * delta < 3.07e-5
-    assert 6.9e-5 < e < 7.1e-5
+    delta = 2.0 ** -17 * (1 + V) + V
+    assert 1.53e-5 < 2 * delta < 1.55e-5
+    assert 5.4e-5 < e < 5.5e-5
     assert oracle.split_screen_error_bound(3) == e
-    # an order of magnitude above the binary32 screen's, far below the bfloat16 one's
-    assert 10 * (2 * V + math.sqrt(2) * 32 * 2.0 ** -23) < e < oracle.screen_error_bound(16) / 100
+    # about ten times the binary32 screen's, far below the bfloat16 one's
+    assert 8 * (2 * V + math.sqrt(2) * 32 * 2.0 ** -23) < e < oracle.screen_error_bound(16) / 100
     with pytest.raises(ValueError):
         oracle.split_screen_error_bound(17)
