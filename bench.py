@@ -214,40 +214,64 @@ def run_equal_mu(lib, torch, wl, probe_steps=300, cap_factor=4, chunk=16):
     return out, frames
 
 
-def run_batched(lib, torch, steps, warmup, count=512, candidates=64):
+def run_batched(lib, torch, steps, warmup, count=512, candidates=64, late_at=1000):
     """The batched workload: 512 independent searches, d uniform in {3..16},
     N uniform in [d+1, d^2], 64 candidates each, one persistent launch (plus a
     finalizing launch) per step; candidate evaluations per second over all
-    instances."""
+    instances.  The cost of a step grows as the searches converge (more pairs
+    crowd within the screen's bound of each maximum and go to the FP64
+    recheck), so two figures: the first `steps` steps from the Haar starts,
+    and `steps` steps from step `late_at` on, when most instances sit at the
+    smallest radius.  The clock is warmed up on a separate batch first."""
     import inputs
     specs = [{"n": n, "d": d, "seed": 0, "stream_id": k, "max_steps": 10 ** 9}
              for k, (d, n) in enumerate(inputs.batched_instances(count, seed=0))]
+    w = lib.Batch(specs, candidates=candidates, radius0=0.1).init()
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < 0.5:
+        w.step(20)
+        torch.cuda.synchronize()
+    del w
+    flops = sum(candidates * flops_per_eval(n, d) for d, n in inputs.batched_instances(count, seed=0))
+
+    def timed(b):
+        lib.timing_reset()
+        lib.timing_enable(True)
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lib.timing_enable(False)
+        ms, cnt = lib.timing_read("batch_step")
+        avg_us = 1e3 * ms / cnt
+        return {
+            "evals_per_s": count * candidates * steps / (t1 - t0),
+            "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "kernel_avg_us": avg_us,
+            "algorithmic_tflops": flops / (avg_us * 1e-6) / 1e12,
+            # against the FP32 peak (the precision the screen stands for) and
+            # against what the split arithmetic allows (a third of the BF16 peak)
+            "frac_fp32_peak": flops / (avg_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp32"],
+            "frac_split_bf16_peak": flops / (avg_us * 1e-6) / 1e12 / (PEAK_TFLOPS["bf16"] / 3),
+        }
+
     b = lib.Batch(specs, candidates=candidates, radius0=0.1).init()
     b.step(warmup)
     torch.cuda.synchronize()
-    lib.timing_reset()
-    lib.timing_enable(True)
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lib.timing_enable(False)
-    ms, cnt = lib.timing_read("batch_step")
-    flops = sum(candidates * flops_per_eval(n, d) for d, n in inputs.batched_instances(count, seed=0))
-    avg_us = 1e3 * ms / cnt
-    return {
-        "workload": f"{count} instances, d in {{3..16}}, N in [d+1, d^2], {candidates} candidates each, "
-                    "FP32-class screen on BF16 MFMA (each FP32 value as hi + lo bfloat16 parts, three products) + "
-                    "certified FP64 pair recheck, one persistent launch and one finalizing launch per step",
-        "evals_per_s": count * candidates * steps / (t1 - t0),
-        "ms_per_step": 1e3 * (t1 - t0) / steps,
-        "kernel_avg_us": avg_us,
-        "algorithmic_tflops": flops / (avg_us * 1e-6) / 1e12,
-        # against the FP32 peak (the precision the screen stands for) and
-        # against what the split arithmetic allows (a third of the BF16 peak)
-        "frac_fp32_peak": flops / (avg_us * 1e-6) / 1e12 / PEAK_TFLOPS["fp32"],
-        "frac_split_bf16_peak": flops / (avg_us * 1e-6) / 1e12 / (PEAK_TFLOPS["bf16"] / 3),
-    }
+    out = timed(b)
+    out["steps_timed"] = f"{warmup + 1}..{warmup + steps} from the Haar starts"
+    done = warmup + steps
+    if late_at > done:
+        b.step(late_at - done)
+        torch.cuda.synchronize()
+    late = timed(b)
+    late["steps_timed"] = f"{max(late_at, done) + 1}..{max(late_at, done) + steps}"
+    late["mean_mu"] = float(b.query()[0].mean())
+    out["late"] = late
+    out["workload"] = (f"{count} instances, d in {{3..16}}, N in [d+1, d^2], {candidates} candidates each, "
+                       "FP32-class screen on BF16 MFMA (each FP32 value as hi + lo bfloat16 parts, three products) + "
+                       "certified FP64 pair recheck, one persistent launch and one finalizing launch per step")
+    return out
 
 
 def run_smooth_max(lib, torch, wl, evals, delta=1e-3):
@@ -576,7 +600,7 @@ def main():
                          "(0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=20, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--batched-steps", type=int, default=200, help="steps of the batched workload (0: skip)")
     ap.add_argument("--miso-evals", type=int, default=10,
                     help="codebook quantiser calls to time (4096 codewords, d = 64, 65536 channels; 0: skip)")
     ap.add_argument("--table2-dims", default="2,3,4,5",

@@ -70,18 +70,22 @@ __host__ __device__ constexpr int split_row_words(int d) { return split_kp(d) + 
 
 __host__ __device__ inline double eps_split(int d) {
   // |screened - exact| for unit columns, d <= 16.  Inputs: each real is
-  // rounded to FP32 (relative 2^-24) and held as hi + lo (hi = bf16 of it,
-  // lo = bf16 of the exact remainder): within delta = 2^-16 (1 + 2^-24) +
-  // 2^-24 of it, so the inner product of two unit columns moves by at most
-  // 2 delta + delta^2.  Products: the dropped lo lo' add up to at most
-  // 2^-16 (1 + u)^2 (1 + 2^-24)^2 (u = 2^-8) in each of Re and Im.
+  // rounded to FP32 (f, relative 2^-24) and held as hi + lo (hi = bf16 of
+  // f, lo = bf16 of the exact remainder r = f - hi).  With 2^e <= |f|,
+  // |r| <= 2^(e-8); at equality r is a power of two and lo = r, otherwise r
+  // lies at least nine binades below f and |lo - r| <= 2^-17 |f|.  So
+  // hi + lo is within delta = 2^-17 (1 + 2^-24) + 2^-24 of the entry and the
+  // inner product of two unit columns moves by at most 2 delta + delta^2.
+  // Products: |lo| <= (1 + u) |r| <= u (1 + u) |f| (u = 2^-8), so the dropped
+  // lo lo' add up to at most 2^-16 (1 + u)^2 (1 + 2^-24)^2 in each of Re and
+  // Im.
   // Accumulation: 96 products (32 reals, zero padded, three products each)
   // summed in FP32 with faithful additions, gamma_96 (unit 2^-23) times at
   // most (1 + u)^2 (1 + 2u) (1 + 2^-24)^2.  Re and Im together give sqrt 2;
   // the tail covers the epilogue.
   (void)d;
   const double u = 0x1p-8, v = 0x1p-24, w = 0x1p-23;
-  const double delta = 0x1p-16 * (1 + v) + v;
+  const double delta = 0x1p-17 * (1 + v) + v;
   const double unit = (1 + v) * (1 + v);
   const double dropped = 0x1p-16 * (1 + u) * (1 + u) * unit;
   const double g = 96 * w / (1.0 - 96 * w);
