@@ -214,7 +214,7 @@ def run_equal_mu(lib, torch, wl, probe_steps=300, cap_factor=4, chunk=16):
     return out, frames
 
 
-def run_batched(lib, torch, steps, warmup, count=512, candidates=64, late_at=1000):
+def run_batched(lib, torch, steps, warmup, count=512, candidates=64, late_at=1000, clock_warmup_s=0.5):
     """The batched workload: 512 independent searches, d uniform in {3..16},
     N uniform in [d+1, d^2], 64 candidates each, one persistent launch (plus a
     finalizing launch) per step; candidate evaluations per second over all
@@ -222,16 +222,18 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64, late_at=100
     crowd within the screen's bound of each maximum and go to the FP64
     recheck), so two figures: the first `steps` steps from the Haar starts,
     and `steps` steps from step `late_at` on, when most instances sit at the
-    smallest radius.  The clock is warmed up on a separate batch first."""
+    smallest radius (late_at <= 0: no second figure).  The clock is warmed
+    up on a separate batch first, for clock_warmup_s seconds."""
     import inputs
     specs = [{"n": n, "d": d, "seed": 0, "stream_id": k, "max_steps": 10 ** 9}
              for k, (d, n) in enumerate(inputs.batched_instances(count, seed=0))]
-    w = lib.Batch(specs, candidates=candidates, radius0=0.1).init()
-    t_w = time.perf_counter()
-    while time.perf_counter() - t_w < 0.5:
-        w.step(20)
-        torch.cuda.synchronize()
-    del w
+    if clock_warmup_s > 0:
+        w = lib.Batch(specs, candidates=candidates, radius0=0.1).init()
+        t_w = time.perf_counter()
+        while time.perf_counter() - t_w < clock_warmup_s:
+            w.step(20)
+            torch.cuda.synchronize()
+        del w
     flops = sum(candidates * flops_per_eval(n, d) for d, n in inputs.batched_instances(count, seed=0))
 
     def timed(b):
@@ -261,13 +263,14 @@ def run_batched(lib, torch, steps, warmup, count=512, candidates=64, late_at=100
     out = timed(b)
     out["steps_timed"] = f"{warmup + 1}..{warmup + steps} from the Haar starts"
     done = warmup + steps
-    if late_at > done:
-        b.step(late_at - done)
-        torch.cuda.synchronize()
-    late = timed(b)
-    late["steps_timed"] = f"{max(late_at, done) + 1}..{max(late_at, done) + steps}"
-    late["mean_mu"] = float(b.query()[0].mean())
-    out["late"] = late
+    if late_at > 0:
+        if late_at > done:
+            b.step(late_at - done)
+            torch.cuda.synchronize()
+        late = timed(b)
+        late["steps_timed"] = f"{max(late_at, done) + 1}..{max(late_at, done) + steps}"
+        late["mean_mu"] = float(b.query()[0].mean())
+        out["late"] = late
     out["workload"] = (f"{count} instances, d in {{3..16}}, N in [d+1, d^2], {candidates} candidates each, "
                        "FP32-class screen on BF16 MFMA (each FP32 value as hi + lo bfloat16 parts, three products) + "
                        "certified FP64 pair recheck, one persistent launch and one finalizing launch per step")
@@ -601,6 +604,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--batched-late-at", type=int, default=1000,
+                    help="also time the batched steps from this step on, when most searches have converged (0: skip)")
+    ap.add_argument("--batched-clock-warmup-s", type=float, default=0.5,
+                    help="seconds of batched steps on a separate batch before the timed ones (clock warm-up)")
     ap.add_argument("--miso-evals", type=int, default=10,
                     help="codebook quantiser calls to time (4096 codewords, d = 64, 65536 channels; 0: skip)")
     ap.add_argument("--table2-dims", default="2,3,4,5",
@@ -674,7 +681,8 @@ def main():
     smooth = run_smooth_max(lib, torch, wl, args.smooth_max_evals) if args.smooth_max_evals > 0 else None
     miso = run_miso(lib, torch, 4096, 64, 65536, args.miso_evals) if args.miso_evals > 0 else None
     table2 = run_table2(lib, [int(x) for x in args.table2_dims.split(",") if x]) if args.table2_dims else None
-    batched = run_batched(lib, torch, args.batched_steps, 2) if args.batched_steps > 0 else None
+    batched = (run_batched(lib, torch, args.batched_steps, 2, late_at=args.batched_late_at,
+                           clock_warmup_s=args.batched_clock_warmup_s) if args.batched_steps > 0 else None)
     log("batched done")
     serving = serving_in_child(args, args.serving_target_factor) if args.serving_requests > 0 else None
     serving_reachable = (serving_in_child(args, args.serving_reachable_factor)
