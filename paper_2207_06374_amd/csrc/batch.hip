@@ -351,6 +351,24 @@ __device__ __forceinline__ void group_sync(bool solo) {
   }
 }
 
+// Position of the k-th (from 0) set bit of m (k < popcount(m)).
+__device__ __forceinline__ int kth_set_bit(uint64_t m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = m & ((1ull << w) - 1);
+    const int c = __popcll(low);
+    if (k >= c) {
+      k -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
 // (bi, bj) of the pair block `step` places after (bi, bj) in row-by-row
 // upper-triangle order (row bi holds bj = bi .. nbk - 1); step <= 4 and every
 // row holds at least one block, so the loop runs at most four times.
@@ -406,12 +424,43 @@ __device__ void screen_phase(const BInst& I, const uint32_t* L, const double* c6
         frag_split(L, I.ldk, n, bj, bh, bl);
         float m[4];
         screen_split(ah, al, bh, bl, n, bi, bj, m);
+        // the block's pairs that can attain the maximum, in (v, lane) order
+        uint64_t mk[4];
+        int cnt = 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int ii = bi * 16 + 4 * (lane >> 4) + v;
           const int jj = bj * 16 + (lane & 15);
-          if (ii < jj && jj < n && !(m[v] < thr_sq)) {
-            const uint64_t pb = pair_f64_b(c64, I.d, ii, jj);
+          mk[v] = __ballot(ii < jj && jj < n && !(m[v] < thr_sq));
+          cnt += __popcll(mk[v]);
+        }
+        // four pairs per pass, 16 lanes per pair (one complex entry each,
+        // d <= 16), summed with DPP inside the lanes' row
+        for (int e0 = 0; e0 < cnt; e0 += 4) {
+          const int e = e0 + (lane >> 4);
+          const int s = lane & 15;
+          double re = 0.0, im = 0.0;
+          if (e < cnt) {
+            const int c0 = __popcll(mk[0]), c1 = __popcll(mk[1]), c2 = __popcll(mk[2]);
+            int k = e, v = 0;
+            uint64_t msk = mk[0];
+            if (k >= c0) { k -= c0; v = 1; msk = mk[1];
+              if (k >= c1) { k -= c1; v = 2; msk = mk[2];
+                if (k >= c2) { k -= c2; v = 3; msk = mk[3]; } } }
+            const int src = kth_set_bit(msk, k);  // the lane that holds the pair
+            const int ii = bi * 16 + 4 * (src >> 4) + v;
+            const int jj = bj * 16 + (src & 15);
+            if (s < I.d) {
+              const double2 x = ((const double2*)(c64 + 2 * (size_t)ii * I.d))[s];
+              const double2 y = ((const double2*)(c64 + 2 * (size_t)jj * I.d))[s];
+              re = x.x * y.x + x.y * y.y;
+              im = x.x * y.y - x.y * y.x;
+            }
+          }
+          re = group_sum<16>(re);
+          im = group_sum<16>(im);
+          if (e < cnt && s == 0) {
+            const uint64_t pb = (uint64_t)__double_as_longlong(re * re + im * im);
             best = pb > best ? pb : best;
           }
         }
