@@ -78,6 +78,16 @@ def test_batch_long_run_on_small_instances_matches_oracle():
     assert len(stopped) < len(specs)
 
 
+def test_batch_edge_sizes_match_oracle():
+    """d = 1 (every pair has |G| = 1, so every pair is rechecked) and d = 2,
+    N = d + 1, and the largest instance (d = 16, N = 256): every candidate's
+    exact mu through the split screen, its zero padding and its recheck."""
+    sizes = [(1, 2), (1, 7), (2, 3), (2, 5), (3, 4), (16, 17), (16, 256)]
+    specs = [{"n": n, "d": d, "seed": 3, "stream_id": 700 + k, "max_steps": 1000, "waves_per_item": 0}
+             for k, (d, n) in enumerate(sizes)]
+    _follow_oracle(specs, 16, 4)
+
+
 def test_batch_matches_oracle_per_instance():
     C = 16
     specs = _specs(20, seed=3, d_hi=8)
