@@ -1552,7 +1552,7 @@ trstmi_status trstmi_shutdown(void) {
   return TRSTMI_OK;
 }
 
-int32_t trstmi_abi_version(void) { return 13; }
+int32_t trstmi_abi_version(void) { return 14; }
 
 }  // extern "C"
 
