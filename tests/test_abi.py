@@ -415,3 +415,18 @@ def test_screen_bounds_equal_the_oracle(L):
         assert L.trstmi_batch_screen_bound(d) == pytest.approx(oracle.split_screen_error_bound(d), rel=1e-14, abs=0)
     assert math.isnan(L.trstmi_bf16_screen_bound(0))
     assert math.isnan(L.trstmi_batch_screen_bound(0)) and math.isnan(L.trstmi_batch_screen_bound(17))
+
+
+def test_autotuner_feasibility_matches_the_library(L):
+    """The autotuner's copy of the batched kernel's LDS rule (which
+    waves_per_item values fit an instance) agrees with the library's own
+    host check for every d <= 16 and every N the batched form takes."""
+    autotune = pytest.importorskip("paper_2207_06374_amd.autotune")
+    for d in range(1, 17):
+        for n in sorted({2, 3, d + 1, 17, 32, 33, 64, 65, 82, 83, 100, 115, 116, 128, 129, 164, 165, 192, 230, 255, 256}):
+            if n > 256:
+                continue
+            feasible = autotune.feasible(n, d)
+            for w in (1, 2, 4):
+                p, inst = _batch(L, [(n, d, w)])
+                assert (L.trstmi_batch_workspace_bytes(ctypes.byref(p), inst) > 0) == (w in feasible), (n, d, w)
